@@ -1,0 +1,232 @@
+"""CPU oracle for graph Quantum Clustering — TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The product library never does, and the oracle never
+imports the product library: the two share no code. Inputs come from the
+seeded generators in ``paper_2305_14641_amd.graphgen``, which hold none of the
+clustering arithmetic.
+
+``qc_oracle.c`` is the plain C implementation (fp64, OpenMP over sources);
+``tiny.py`` is a second, pure-Python one for graphs of a few dozen nodes.
+Each function cites the part of the paper it follows (Section 3.1, Eq. 2,
+Eq. 7, Algorithms 1-4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qc_oracle.c")
+_LIB = os.path.join(_HERE, "libqc_oracle.so")
+
+TIE_STRICT = 0
+TIE_MERGE = 1
+MAX_DIST = 126
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (fp64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        L.qco_bfs_rows.argtypes = [I, P, P, I, P, P, P]
+        L.qco_bfs_rows.restype = I
+        L.qco_hist_rows.argtypes = [I, I, P, I, P]
+        L.qco_hist_rows.restype = I
+        L.qco_hist_all.argtypes = [I, P, P, I, P, P]
+        L.qco_hist_all.restype = I
+        L.qco_potential_pairsum.argtypes = [I, I, P, D, P, P]
+        L.qco_potential_pairsum.restype = None
+        L.qco_potential_canonical.argtypes = [I, I, P, D, P, P]
+        L.qco_potential_canonical.restype = None
+        L.qco_weights.argtypes = [I, D, P, P]
+        L.qco_weights.restype = None
+        L.qco_ggd_parent.argtypes = [I, P, P, P, I, P]
+        L.qco_ggd_parent.restype = None
+        L.qco_find_centers.argtypes = [I, P, P]
+        L.qco_find_centers.restype = None
+        L.qco_potential_literal.argtypes = [I, P, P, P, D, D, P, P]
+        L.qco_potential_literal.restype = None
+        L.qco_num_threads.argtypes = []
+        L.qco_num_threads.restype = I
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(row_ptr, col):
+    return (np.ascontiguousarray(row_ptr, dtype=np.int32),
+            np.ascontiguousarray(col, dtype=np.int32))
+
+
+def num_threads() -> int:
+    return int(lib().qco_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Distances (Section 3.1 read as hop counts) and their histograms.
+
+def bfs_rows(n, row_ptr, col, sources) -> tuple:
+    """Hop-distance rows d[s, :] for the given sources (int8, -1 unreachable)."""
+    rp, c = _csr(row_ptr, col)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    out = np.empty((src.shape[0], n), dtype=np.int8)
+    dmax = np.zeros(1, dtype=np.int32)
+    st = lib().qco_bfs_rows(n, _p(rp), _p(c), src.shape[0], _p(src), _p(out), _p(dmax))
+    if st != 0:
+        raise OracleError(f"bfs status {st} (hop distance above {MAX_DIST})")
+    return out, int(dmax[0])
+
+
+def distances(n, row_ptr, col) -> tuple:
+    """Full N x N hop-distance matrix and its largest finite entry."""
+    return bfs_rows(n, row_ptr, col, np.arange(n, dtype=np.int32))
+
+
+def hist_rows(dist_rows: np.ndarray, K: int) -> np.ndarray:
+    """h[r, k] = number of entries of row r equal to k (unreachable not counted)."""
+    d = np.ascontiguousarray(dist_rows, dtype=np.int8)
+    nrows, n = d.shape
+    out = np.empty((nrows, K), dtype=np.int32)
+    st = lib().qco_hist_rows(n, nrows, _p(d), K, _p(out))
+    if st != 0:
+        raise OracleError("distance >= K in histogram")
+    return out
+
+
+def hist_all(n, row_ptr, col, K) -> tuple:
+    """Histograms of every node's distance row, without storing the matrix."""
+    rp, c = _csr(row_ptr, col)
+    out = np.empty((n, K), dtype=np.int32)
+    dmax = np.zeros(1, dtype=np.int32)
+    st = lib().qco_hist_all(n, _p(rp), _p(c), K, _p(out), _p(dmax))
+    if st != 0:
+        raise OracleError(f"hist_all status {st}")
+    return out, int(dmax[0])
+
+
+# --------------------------------------------------------------------------
+# Potential (Eq. 2, Eq. 7, Algorithm 1).
+
+def potential_pairsum(dist_rows: np.ndarray, sigma: float) -> tuple:
+    """Algorithm 1 literally, one row per node: returns (psi, V) in fp64."""
+    d = np.ascontiguousarray(dist_rows, dtype=np.int8)
+    nrows, n = d.shape
+    psi = np.empty(nrows)
+    v = np.empty(nrows)
+    lib().qco_potential_pairsum(n, nrows, _p(d), float(sigma), _p(psi), _p(v))
+    return psi, v
+
+
+def potential_canonical(hist: np.ndarray, sigma: float) -> tuple:
+    """Canonical fp64 (psi, V) from distance histograms (the GGD reference)."""
+    h = np.ascontiguousarray(hist, dtype=np.int32)
+    nrows, K = h.shape
+    psi = np.empty(nrows)
+    v = np.empty(nrows)
+    lib().qco_potential_canonical(nrows, K, _p(h), float(sigma), _p(psi), _p(v))
+    return psi, v
+
+
+def weights(K: int, sigma: float) -> tuple:
+    w = np.empty(K)
+    a = np.zeros(1)
+    lib().qco_weights(K, float(sigma), _p(w), _p(a))
+    return w, float(a[0])
+
+
+def potential_literal(n, row_ptr, col, sigma, weight=None, cap=2.0) -> tuple:
+    """Algorithm 1 on the dense distance of Section 3.1 read literally:
+    edge weight for an edge, ``cap`` for a missing edge, 0 on the diagonal."""
+    rp, c = _csr(row_ptr, col)
+    psi = np.empty(n)
+    v = np.empty(n)
+    if weight is None:
+        wp = None
+    else:
+        w = np.ascontiguousarray(weight, dtype=np.float64)
+        wp = _p(w)
+    lib().qco_potential_literal(n, _p(rp), _p(c), wp, float(cap), float(sigma), _p(psi), _p(v))
+    return psi, v
+
+
+# --------------------------------------------------------------------------
+# Graph Gradient Descent (Algorithms 2 and 3).
+
+def ggd_parent(n, row_ptr, col, v, tie_mode=TIE_STRICT) -> np.ndarray:
+    rp, c = _csr(row_ptr, col)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty(n, dtype=np.int32)
+    lib().qco_ggd_parent(n, _p(rp), _p(c), _p(vv), int(tie_mode), _p(out))
+    return out
+
+
+def find_centers(parent: np.ndarray) -> np.ndarray:
+    p = np.ascontiguousarray(parent, dtype=np.int32)
+    out = np.empty_like(p)
+    lib().qco_find_centers(p.shape[0], _p(p), _p(out))
+    if (out < 0).any():
+        raise OracleError("parent pointers contain a cycle")
+    return out
+
+
+def cluster(n, row_ptr, col, sigmas, tie_mode=TIE_STRICT, with_dist=True) -> dict:
+    """Algorithm 4 end to end for a list of sigmas.
+
+    Returns distances (if with_dist), histograms, canonical and pair-sum
+    (psi, V) per sigma, parents and labels per sigma.
+    """
+    out = {}
+    if with_dist:
+        dist, dmax = distances(n, row_ptr, col)
+        out["dist"] = dist
+        K = dmax + 1
+        hist = hist_rows(dist, K)
+    else:
+        hist, dmax = hist_all(n, row_ptr, col, MAX_DIST + 1)
+        K = dmax + 1
+        hist = np.ascontiguousarray(hist[:, :K])
+    out["dmax"] = dmax
+    out["hist"] = hist
+    res = []
+    for s in sigmas:
+        psi_c, v_c = potential_canonical(hist, s)
+        r = {"sigma": float(s), "psi": psi_c, "v": v_c}
+        if with_dist:
+            psi_p, v_p = potential_pairsum(out["dist"], s)
+            r["psi_pairsum"], r["v_pairsum"] = psi_p, v_p
+        par = ggd_parent(n, row_ptr, col, v_c, tie_mode)
+        r["parent"] = par
+        r["labels"] = find_centers(par)
+        res.append(r)
+    out["per_sigma"] = res
+    return out
