@@ -1,0 +1,179 @@
+/*
+ * qc.h — C ABI of the MI355X (gfx950) graph Quantum Clustering library.
+ *
+ * The library computes, for an undirected graph, the quantities of Section 3.1
+ * of Wang, He & Liu, "Graph Analysis Using a GPU-based Parallel Algorithm:
+ * Quantum Clustering" (arXiv 2305.14641):
+ *   - node-to-node distances (hop counts of shortest paths),
+ *   - the wave function psi (Eq. 2) and the potential V (Eq. 7, approximate
+ *     form, as computed by Algorithm 1) of every node for a list of widths
+ *     sigma,
+ *   - Graph Gradient Descent labels (Algorithms 2-4): each node descends to
+ *     its lowest neighbour while that neighbour is strictly lower; the label
+ *     is the id of the local minimum where the descent ends.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a qc_status; nothing throws or aborts across the ABI.
+ *   - Arguments are validated on the host before any device work; on an error
+ *     status nothing has been written to any output.
+ *   - Pointers documented as "device" are HIP device pointers (e.g. a torch
+ *     tensor's data_ptr()); the caller owns them and keeps them alive until
+ *     the stream has passed the call. Pointers documented as "host" are read
+ *     (or written) before the call returns.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream. Device work is ordered on that stream; device outputs are valid
+ *     once the stream has reached the call (e.g. after qc_graph_sync).
+ *   - Node ids are 0-based. Distances are int8: 0..126 for reachable pairs,
+ *     -1 for unreachable pairs; a finite distance above 126 is an error
+ *     (QC_E_OVERFLOW), never truncated.
+ *   - One handle is used by one host thread at a time; distinct handles are
+ *     independent.
+ */
+#ifndef QC_H_
+#define QC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qc_status;
+
+enum {
+    QC_OK = 0,
+    QC_E_INVAL = 1,         /* NULL pointer, size out of range, sigma <= 0 or not finite */
+    QC_E_NOT_SYMMETRIC = 2, /* CSR not symmetric, unsorted, duplicated, or with self-loops */
+    QC_E_OOM = 3,           /* device or pinned-host allocation failed */
+    QC_E_DEVICE = 4,        /* no gfx950 device visible, or a HIP call failed */
+    QC_E_OVERFLOW = 5,      /* a finite hop distance above 126 */
+    QC_E_STATE = 6,         /* call order violated (e.g. labels before potential) */
+    QC_E_BUSY = 7           /* serving: request does not fit the memory budget now */
+};
+
+/* Tie rules of the descent (Algorithm 2 and the prose after Algorithm 4).
+ * STRICT: a node moves to the lowest neighbour (equal neighbours -> smallest
+ *         id) only if that neighbour's V is strictly lower than its own.
+ * MERGE:  a node moves to the (V, id)-lexicographic minimum over itself and
+ *         its neighbours, so equal-V neighbours join the smallest id. */
+enum { QC_TIE_STRICT = 0, QC_TIE_MERGE = 1 };
+
+/* Arithmetic of qc_potential (psi and V are always returned as FP32).
+ * FP64ACC: histogram x weight products accumulated in FP64 (default).
+ * FP32C:   FP32 with compensated (error-free transformation) sums.
+ * BF16:    histograms and weights rounded to BF16, FP32 accumulation on the
+ *          matrix cores; approximate (about 1e-3 relative) — qc_ggd_labels
+ *          refuses potentials computed this way (QC_E_STATE). */
+enum { QC_PREC_FP64ACC = 0, QC_PREC_FP32C = 1, QC_PREC_BF16 = 2 };
+
+/* qc_graph_create flags. */
+enum {
+    QC_GRAPH_CANONICALIZE = 1u /* symmetrise, sort, drop duplicates and self-loops first */
+};
+
+typedef struct qc_graph_s *qc_graph;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *qc_status_str(qc_status s);
+
+/* Number of visible gfx950 devices (0 when none); does not touch any handle. */
+qc_status qc_device_count(int32_t *count_out);
+
+/*
+ * Create a graph handle from a CSR adjacency (the adjacency matrix of
+ * Algorithm 1's input, stored sparsely).
+ *   n        number of nodes, 1 <= n <= 65536
+ *   nnz      number of stored entries (2 x undirected edges), 0 <= nnz < 2^31
+ *   row_ptr  host, int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_idx  host, int32[nnz], neighbours of node i in row_ptr[i]..row_ptr[i+1]-1
+ *   flags    0: the CSR must already be canonical (each row strictly
+ *            increasing, no self-loop, (i,j) present iff (j,i) present),
+ *            else QC_E_NOT_SYMMETRIC; QC_GRAPH_CANONICALIZE: the library
+ *            canonicalises a copy first (the input is left unchanged).
+ *   stream   stream for the upload
+ *   out      host, receives the handle (unchanged on error)
+ * The library copies the CSR; the caller keeps ownership of its arrays.
+ */
+qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, uint32_t flags, void *stream,
+                          qc_graph *out);
+
+/* Release a handle and all device memory it owns (waits for its work). */
+qc_status qc_graph_destroy(qc_graph g);
+
+/* Sizes of a handle: any output pointer may be NULL. dmax is -1 until the
+ * first qc_distances / qc_potential has run. */
+qc_status qc_graph_info(qc_graph g, int32_t *n, int64_t *nnz, int32_t *dmax,
+                        int32_t *n_components);
+
+/*
+ * Hop distances between all pairs of nodes (Section 3.1: the distance the
+ * potential is built from, read as the length of a shortest path) and the
+ * per-node distance histograms h[i][k] = #{j : d(i,j) = k} that Algorithm 1's
+ * sums regroup into.
+ *   dist_out  device, int8[n*n] row-major (dist_out[i*n + j] = d(i,j)), 16-byte
+ *             aligned (else QC_E_INVAL), or
+ *             NULL to keep the matrix in a library-owned device buffer.
+ *             A non-NULL buffer is also remembered as the resident matrix
+ *             and must stay alive while the handle may read it (until the
+ *             next qc_distances call or qc_graph_destroy).
+ *   dmax_out  host, may be NULL: largest finite distance. The first call on a
+ *             handle always waits for the stream (it needs dmax to size the
+ *             histograms); later calls return the cached value.
+ * Errors: QC_E_OVERFLOW if some finite distance exceeds 126.
+ */
+qc_status qc_distances(qc_graph g, int8_t *dist_out, int32_t *dmax_out, void *stream);
+
+/*
+ * Copy the resident histograms to the caller.
+ *   hist_out  device, int32[n * K] row-major, or NULL (then only k_out is set)
+ *   k_out     host, receives K (the row length, >= dmax + 1, a multiple of 32)
+ * Errors: QC_E_STATE before qc_distances / qc_potential.
+ */
+qc_status qc_get_histograms(qc_graph g, int32_t *hist_out, int32_t *k_out, void *stream);
+
+/*
+ * psi (Eq. 2) and V (Algorithm 1: (1/(2 sigma^2)) sum_j d^2 e^{-d^2/2sigma^2}
+ * / sum_j e^{-d^2/2sigma^2}, self term included, unreachable j skipped) of
+ * every node for each width in `sigmas`.
+ *   sigmas     host, double[n_sigmas], each finite and > 0
+ *   n_sigmas   1 <= n_sigmas <= 1024
+ *   psi_out    device, float[n_sigmas][n], or NULL
+ *   v_out      device, float[n_sigmas][n], or NULL
+ *   precision  QC_PREC_* (see above)
+ * Runs qc_distances first (with a library-owned matrix) if it has not run.
+ * The values are kept resident for qc_ggd_labels; `sigma_index` there indexes
+ * this list. Relative error of psi and V vs an FP64 evaluation: <= 1e-6 for
+ * FP64ACC and FP32C.
+ */
+qc_status qc_potential(qc_graph g, const double *sigmas, int32_t n_sigmas,
+                       float *psi_out, float *v_out, uint32_t precision, void *stream);
+
+/*
+ * Graph Gradient Descent labels for one width of the last qc_potential call
+ * (Algorithms 2 and 3): labels_out[i] = id of the local minimum node i's
+ * descent ends at. Comparisons whose FP32 gap is within the FP32 error bound
+ * are re-decided with the canonical FP64 potential (h_k times exp weights
+ * summed in ascending k, no fused multiply-add), so labels do not depend on
+ * FP32 rounding.
+ *   sigma_index  0 <= sigma_index < n_sigmas of the last qc_potential
+ *   tie_mode     QC_TIE_STRICT or QC_TIE_MERGE
+ *   labels_out   device, int32[n]
+ * Errors: QC_E_STATE before qc_potential, or after a QC_PREC_BF16 potential.
+ */
+qc_status qc_ggd_labels(qc_graph g, int32_t sigma_index, uint32_t tie_mode,
+                        int32_t *labels_out, void *stream);
+
+/* Number of node decisions the last qc_ggd_labels call (or batch run)
+ * re-decided in FP64 (waits for the stream). */
+qc_status qc_last_recheck_count(qc_graph g, int64_t *count_out);
+
+/* Wait for all work issued on `stream` and return any error the device
+ * latched (QC_E_OVERFLOW) since the last check. */
+qc_status qc_graph_sync(qc_graph g, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QC_H_ */

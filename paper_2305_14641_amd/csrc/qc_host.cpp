@@ -1,0 +1,149 @@
+// Host-side helpers that need no GPU (see qc_host.h).
+#include "qc_host.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "qc_internal.h"
+
+namespace qc {
+
+qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                       bool canonicalize, std::vector<int32_t> &rp_out,
+                       std::vector<int32_t> &col_out)
+{
+    if (n < 1 || n > kMaxNodes) return QC_E_INVAL;
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return QC_E_INVAL;
+    if (!row_ptr) return QC_E_INVAL;
+    if (nnz > 0 && !col) return QC_E_INVAL;
+    if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz) return QC_E_INVAL;
+    for (int32_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return QC_E_INVAL;
+    for (int64_t e = 0; e < nnz; ++e)
+        if (col[e] < 0 || col[e] >= n) return QC_E_INVAL;
+
+    if (canonicalize) {
+        std::vector<std::vector<int32_t>> adj(n);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const int32_t j = col[e];
+                if (j == i) continue;
+                adj[i].push_back(j);
+                adj[j].push_back(i);
+            }
+        rp_out.assign(n + 1, 0);
+        col_out.clear();
+        for (int32_t i = 0; i < n; ++i) {
+            auto &a = adj[i];
+            std::sort(a.begin(), a.end());
+            a.erase(std::unique(a.begin(), a.end()), a.end());
+            col_out.insert(col_out.end(), a.begin(), a.end());
+            rp_out[i + 1] = (int32_t)col_out.size();
+        }
+        if ((int64_t)col_out.size() >= ((int64_t)1 << 31)) return QC_E_INVAL;
+        return QC_OK;
+    }
+
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            if (col[e] == i) return QC_E_NOT_SYMMETRIC;
+            if (e > row_ptr[i] && col[e] <= col[e - 1]) return QC_E_NOT_SYMMETRIC;
+        }
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (!std::binary_search(col + row_ptr[j], col + row_ptr[j + 1], i))
+                return QC_E_NOT_SYMMETRIC;
+        }
+    }
+    rp_out.assign(row_ptr, row_ptr + n + 1);
+    col_out.assign(col, col + nnz);
+    return QC_OK;
+}
+
+static int32_t uf_find(std::vector<int32_t> &p, int32_t x)
+{
+    while (p[x] != x) {
+        p[x] = p[p[x]];
+        x = p[x];
+    }
+    return x;
+}
+
+int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col)
+{
+    std::vector<int32_t> p(n);
+    std::iota(p.begin(), p.end(), 0);
+    int32_t comps = n;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            int32_t a = uf_find(p, i), b = uf_find(p, col[e]);
+            if (a != b) {
+                p[std::max(a, b)] = std::min(a, b);
+                --comps;
+            }
+        }
+    return comps;
+}
+
+BfsPlan plan_bfs(int32_t n)
+{
+    static const int kAllowed[] = {1, 2, 4, 6, 8, 10, 12};
+    for (int bw : {64, 32, 16, 8, 4}) {
+        const int64_t words = ((int64_t)n * bw + 31) / 32;  // 32-bit words of one bit field
+        const int64_t need = (words + kBfsThreads - 1) / kBfsThreads;
+        for (int nw : kAllowed) {
+            if (bw == 64 && (nw % 2)) continue;
+            if (nw >= need) {
+                BfsPlan p;
+                p.bw = bw;
+                p.nw = nw;
+                p.n_batches = (int)((n + bw - 1) / bw);
+                return p;
+            }
+        }
+    }
+    BfsPlan none = {0, 0, 0};
+    return none;
+}
+
+static void split_f32(double x, float &hi, float &lo)
+{
+    hi = (float)x;
+    lo = (float)(x - (double)hi);
+}
+
+void weight_tables(const double *sigmas, int n_sigmas, int K, std::vector<double> &w64,
+                   std::vector<double> &u64, std::vector<double> &inv_a, std::vector<float> &w32c)
+{
+    w64.assign((size_t)n_sigmas * K, 0.0);
+    u64.assign((size_t)n_sigmas * K, 0.0);
+    inv_a.assign(n_sigmas, 0.0);
+    w32c.assign((size_t)n_sigmas * K * 4, 0.0f);
+    for (int s = 0; s < n_sigmas; ++s) {
+        const double a = (2.0 * sigmas[s]) * sigmas[s];
+        inv_a[s] = 1.0 / a;
+        for (int k = 0; k < K; ++k) {
+            const double w = exp(-(double)(k * k) / a);
+            const double u = ((double)(k * k) * w) / a;
+            w64[(size_t)s * K + k] = w;
+            u64[(size_t)s * K + k] = u;
+            float *c = &w32c[((size_t)s * K + k) * 4];
+            split_f32(w, c[0], c[1]);
+            split_f32(u, c[2], c[3]);
+        }
+    }
+}
+
+qc_status validate_sigmas(const double *sigmas, int32_t n_sigmas)
+{
+    if (!sigmas || n_sigmas < 1 || n_sigmas > 1024) return QC_E_INVAL;
+    for (int32_t s = 0; s < n_sigmas; ++s)
+        if (!(sigmas[s] > 0.0) || !isfinite(sigmas[s])) return QC_E_INVAL;
+    return QC_OK;
+}
+
+}  // namespace qc

@@ -1,0 +1,45 @@
+// Host-side helpers of the library that need no GPU: CSR validation and
+// canonicalisation, connected components, BFS launch planning, weight tables.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "qc.h"
+
+namespace qc {
+
+// Validate a CSR for qc_graph_create. Returns QC_OK, QC_E_INVAL (pointers,
+// sizes, ranges) or QC_E_NOT_SYMMETRIC (ordering, duplicates, self-loops,
+// asymmetry). With `canonicalize`, only the range checks apply and the
+// canonical form is written to rp_out / col_out.
+qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                       bool canonicalize, std::vector<int32_t> &rp_out,
+                       std::vector<int32_t> &col_out);
+
+// Number of connected components (union-find over the canonical CSR).
+int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col);
+
+// BFS batch width (sources per workgroup) and 32-bit words per thread for a
+// graph of n nodes: the widest batch whose distance bytes fit the register
+// budget of one 1024-thread workgroup.
+struct BfsPlan { int bw; int nw; int n_batches; };
+BfsPlan plan_bfs(int32_t n);
+
+// Histogram row length for a largest finite distance dmax.
+inline int bins_for(int dmax) { return dmax < 32 ? 32 : (dmax < 64 ? 64 : 128); }
+
+// Weight tables of one sigma list (host C library exp, FP64):
+//   w64[s*K + k] = exp(-(k*k) / a_s),  a_s = (2 sigma_s) sigma_s
+//   u64[s*K + k] = (k*k) * w64 / a_s
+//   inv_a[s]     = 1 / a_s
+//   w32c[(s*K + k)*4 + {0,1,2,3}] = FP32 hi/lo splits of w64 and u64
+void weight_tables(const double *sigmas, int n_sigmas, int K, std::vector<double> &w64,
+                   std::vector<double> &u64, std::vector<double> &inv_a,
+                   std::vector<float> &w32c);
+
+// Check a sigma list (count 1..1024, every value finite and > 0).
+qc_status validate_sigmas(const double *sigmas, int32_t n_sigmas);
+
+}  // namespace qc

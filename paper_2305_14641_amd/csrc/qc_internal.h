@@ -1,0 +1,93 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+// Not part of the public ABI (include/qc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qc {
+
+// Largest finite hop distance an int8 distance can hold; reaching level 127
+// in a breadth-first search is reported as an overflow.
+constexpr int kMaxDist = 126;
+// Largest supported node count: edges are packed as (row << 16 | col).
+constexpr int kMaxNodes = 65536;
+// Threads per workgroup of the multi-source BFS.
+constexpr int kBfsThreads = 1024;
+// 32-bit words of `seen` bits one BFS thread owns at most (see bfs_plan).
+constexpr int kBfsMaxWordsPerThread = 12;
+
+// Device-visible description of one graph and its resident buffers.
+// Kernels receive an array of these plus a job table, so one launch can
+// serve one graph or many.
+struct GraphDev {
+    int32_t n;
+    int32_t K;            // histogram row length (multiple of 32)
+    int32_t dmax;         // largest finite distance (valid after the BFS)
+    int32_t n_sigmas;
+    int64_t nnz;
+    const int32_t *row_ptr;   // [n+1]
+    const int32_t *col;       // [nnz]
+    const uint32_t *edges;    // [nnz] packed (row << 16) | col, rows ascending
+    int8_t *dist;             // [n*n] row-major
+    int32_t *hist;            // [n*K]
+    float *psi;               // [n_sigmas*n] resident
+    float *v;                 // [n_sigmas*n] resident
+    const double *w64;        // [n_sigmas*K] exp(-k^2/a), host C library exp
+    const double *u64;        // [n_sigmas*K] k^2 * w / a
+    const double *inv_a;      // [n_sigmas] 1/a, a = (2 sigma) sigma
+    const float *w32c;        // [n_sigmas*K*4] FP32 (w_hi, w_lo, u_hi, u_lo)
+    int32_t *parent;          // [n_sigmas*n] descent parents
+    int32_t *status;          // [2]: 0 largest finite distance, 1 overflow flag
+    unsigned long long *recheck;  // count of FP64 re-decided nodes
+};
+
+struct BfsJob { int32_t g; int32_t s0; };                  // graph index, first source
+struct NodeJob { int32_t g; int32_t i0; int64_t out_off; };  // graph, first node, output offset
+
+// Rows of the distance matrix one histogram job covers, by bin count.
+inline int hist_rows_per_job(int K) { return K >= 128 ? 4 : 8; }
+// Nodes per job of the potential and descent kernels.
+constexpr int kNodesPerJob = 256;
+
+// Relative FP32 gap under which a descent comparison is re-decided in FP64.
+// It exceeds twice the worst FP32 error of V for both FP64ACC (about 2^-24)
+// and FP32C (about 7 * 2^-24) potentials.
+constexpr float kTieTau = 1.9073486328125e-06f;  // 2^-19
+
+// ---- launchers (qc_kernels.hip); each returns hipSuccess or the launch error.
+
+// Write one descriptor into device memory in stream order.
+hipError_t launch_set_desc(GraphDev *dst, const GraphDev &src, hipStream_t stream);
+
+// Multi-source BFS over `n_jobs` (graph, source-batch) jobs; every graph of the
+// launch must share the batch width `bw` and words-per-thread `nw`.
+hipError_t launch_bfs(int bw, int nw, const GraphDev *graphs, const BfsJob *jobs,
+                      int n_jobs, hipStream_t stream);
+
+// Histograms of the resident distance rows (one job = hist_rows_per_job(K)
+// rows of one graph). `K` is the shared bin count (32, 64 or 128).
+hipError_t launch_hist(int K, const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
+                       hipStream_t stream);
+
+// psi/V of every (node, sigma); one job = kNodesPerJob nodes of one graph.
+// Optional caller outputs: out[out_off + s*out_ld + (i - i0_of_graph)].
+hipError_t launch_potential(int precision, int K, const GraphDev *graphs, const NodeJob *jobs,
+                            int n_jobs, float *psi_out, float *v_out, int64_t out_ld,
+                            hipStream_t stream);
+
+// Descent parents for sigmas sigma_base .. sigma_base+n_sig-1 of every job.
+hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob *jobs,
+                             int n_jobs, int sigma_base, int n_sig, hipStream_t stream);
+
+// Pointer jumping, one workgroup per (graph job, sigma); labels of sigma
+// sigma_base + y go to labels_base + y*labels_ld + job.out_off.
+hipError_t launch_pointer_jump(const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
+                               int sigma_base, int n_sig, int32_t *labels_base,
+                               int64_t labels_ld, hipStream_t stream);
+
+// Fill kernel (used instead of hipMemsetAsync so work can be graph-captured).
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t stream);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t count, hipStream_t stream);
+
+}  // namespace qc

@@ -1,0 +1,600 @@
+// HIP kernels (gfx950) of the graph Quantum Clustering hot path:
+//   k_bfs        all-pairs hop distances by bit-parallel multi-source BFS
+//   k_hist       per-node distance histograms from the int8 distance rows
+//   k_potential  psi (Eq. 2) and V (Algorithm 1) from histogram x exp weights
+//   k_ggd_parent Graph Gradient Descent step (Algorithm 2) with FP64 re-check
+//   k_jump       find the centre of every node (Algorithm 3) by pointer jumping
+#include "qc_internal.h"
+
+#include <float.h>
+
+namespace qc {
+
+// ===========================================================================
+// Multi-source BFS.
+//
+// One workgroup owns a batch of BW consecutive sources s0..s0+BW-1 and runs
+// the level-synchronous search of all of them at once. LDS holds two bit
+// fields per node: `seen` (which sources have reached the node) and `nxt`
+// (which reach it at the current level). A level is:
+//   A. edge-parallel pull: for every edge (r, c), the sources that have seen c
+//      but not r reach r now:  nxt[r] |= seen[c] & ~seen[r]   (LDS atomic OR)
+//   B. word-owner update: every thread owns whole 32-bit words of the fields;
+//      it folds nxt into seen and records the level as the distance byte of
+//      each newly reached (node, source) pair.
+// Using `seen` rather than the previous frontier in A is exact: a source that
+// reached c at an earlier level would already have reached r.
+//
+// The distance bytes of every (owned node, batch source) pair live in
+// registers for the whole search (8 VGPRs per owned 32-bit word), so each
+// batch writes its BW output rows exactly once, when it is done. The graph is
+// undirected, so node v's distances to the batch sources are the entries
+// (s0+b, v) of the row-major matrix: rows s0..s0+BW-1 are this workgroup's.
+// ===========================================================================
+
+template <int BW> struct BfsWord {
+    using T = uint32_t;
+    static constexpr int kBits = 32;
+    static constexpr int kPer = 32 / BW;  // nodes per word
+};
+template <> struct BfsWord<64> {
+    using T = unsigned long long;
+    static constexpr int kBits = 64;
+    static constexpr int kPer = 1;
+};
+
+// 4-bit mask -> 4 bytes of 0xFF / 0x00 (bit i selects byte i).
+__device__ __forceinline__ uint32_t expand4(uint32_t m4)
+{
+    return ((m4 * 0x00204081u) & 0x01010101u) * 0xFFu;
+}
+
+template <int BW>
+__device__ __forceinline__ typename BfsWord<BW>::T field_of(const typename BfsWord<BW>::T *a, int v)
+{
+    using W = BfsWord<BW>;
+    if constexpr (BW >= 32) {
+        return a[v];
+    } else {
+        const uint32_t w = a[v / W::kPer];
+        return (w >> ((v % W::kPer) * BW)) & ((1u << BW) - 1u);
+    }
+}
+
+// Apply newly reached bits `y` of word j at `level`: each byte starts as 0xFF
+// (unreached) and is set exactly once, so XOR with (0xFF ^ level) writes level.
+template <int NREG>
+__device__ __forceinline__ void record_level(uint32_t (&d)[NREG], unsigned long long y, uint32_t kx)
+{
+#pragma unroll
+    for (int t = 0; t < NREG; ++t) {
+        const uint32_t m4 = (uint32_t)(y >> (4 * t)) & 0xFu;
+        if (m4) d[t] ^= expand4(m4) & kx;
+    }
+}
+
+template <int BW, int NW>
+__global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict__ graphs,
+                                                     const BfsJob *__restrict__ jobs)
+{
+    using W = BfsWord<BW>;
+    using T = typename W::T;
+    constexpr int NWW = (BW == 64) ? NW / 2 : NW;   // words of type T per thread
+    constexpr int NREG = W::kBits / 4;              // distance VGPRs per word
+    constexpr int kLdsWords = NWW * kBfsThreads;
+
+    __shared__ T seen[kLdsWords];
+    __shared__ T nxt[kLdsWords];
+
+    const BfsJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int s0 = job.s0;
+    const int nb = min(BW, n - s0);
+    const int nwords = (n + W::kPer - 1) / W::kPer;
+    const int tid = threadIdx.x;
+    const int64_t nnz = G.nnz;
+    const uint32_t *__restrict__ edges = G.edges;
+
+    uint32_t dist[NWW][NREG];
+#pragma unroll
+    for (int j = 0; j < NWW; ++j)
+#pragma unroll
+        for (int t = 0; t < NREG; ++t) dist[j][t] = 0xFFFFFFFFu;
+
+    // Level 0: each source has reached itself.
+#pragma unroll
+    for (int j = 0; j < NWW; ++j) {
+        const int w = j * kBfsThreads + tid;
+        T bits = 0;
+        if (w < nwords) {
+#pragma unroll
+            for (int q = 0; q < W::kPer; ++q) {
+                const int b = w * W::kPer + q - s0;
+                if (b >= 0 && b < nb) bits |= (T)1 << (q * BW + b);
+            }
+        }
+        seen[w] = bits;
+        nxt[w] = 0;
+        record_level<NREG>(dist[j], (unsigned long long)bits, 0xFFFFFFFFu);
+    }
+    __syncthreads();
+
+    int last = 0;
+    bool overflow = false;
+    for (int level = 1;; ++level) {
+        // A. pull over every edge.
+        for (int64_t e = tid; e < nnz; e += kBfsThreads) {
+            const uint32_t rc = edges[e];
+            const int r = (int)(rc >> 16);
+            const int c = (int)(rc & 0xFFFFu);
+            const T x = field_of<BW>(seen, c);
+            if (x) {
+                const T y = x & ~field_of<BW>(seen, r);
+                if (y) atomicOr(&nxt[r / W::kPer], (T)(y << ((r % W::kPer) * BW)));
+            }
+        }
+        __syncthreads();
+        // B. fold the new bits of owned words into seen and the distance bytes.
+        int any = 0;
+        const uint32_t kx = (0xFFu ^ (uint32_t)level) * 0x01010101u;
+#pragma unroll
+        for (int j = 0; j < NWW; ++j) {
+            const int w = j * kBfsThreads + tid;
+            if (w < nwords) {
+                const T y = nxt[w];
+                if (y) {
+                    nxt[w] = 0;
+                    seen[w] |= y;
+                    any = 1;
+                    record_level<NREG>(dist[j], (unsigned long long)y, kx);
+                }
+            }
+        }
+        if (!__syncthreads_or(any)) break;
+        last = level;
+        if (level > kMaxDist) { overflow = true; break; }
+    }
+
+    // Rows s0..s0+nb-1, columns = owned nodes.
+    int8_t *__restrict__ out = G.dist;
+#pragma unroll
+    for (int j = 0; j < NWW; ++j) {
+        const int w = j * kBfsThreads + tid;
+        if (w < nwords) {
+#pragma unroll
+            for (int q = 0; q < W::kPer; ++q) {
+                const int v = w * W::kPer + q;
+                if (v < n) {
+#pragma unroll
+                    for (int b = 0; b < BW; ++b) {
+                        if (b < nb) {
+                            const int i = q * BW + b;
+                            const uint32_t byte = (dist[j][i / 4] >> (8 * (i % 4))) & 0xFFu;
+                            out[(int64_t)(s0 + b) * n + v] = (int8_t)byte;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (tid == 0) {
+        atomicMax(&G.status[0], last);
+        if (overflow) atomicOr(&G.status[1], 1);
+    }
+}
+
+template <int BW, int NW>
+static hipError_t launch_bfs_t(const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                               hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_bfs<BW, NW>), dim3(n_jobs), dim3(kBfsThreads), 0, stream, graphs, jobs);
+    return hipGetLastError();
+}
+
+template <int BW>
+static hipError_t launch_bfs_bw(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                                hipStream_t stream)
+{
+    switch (nw) {
+    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1>(graphs, jobs, n_jobs, stream);
+            return hipErrorInvalidValue;
+    case 2: return launch_bfs_t<BW, 2>(graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_t<BW, 4>(graphs, jobs, n_jobs, stream);
+    case 6: return launch_bfs_t<BW, 6>(graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_t<BW, 8>(graphs, jobs, n_jobs, stream);
+    case 10: return launch_bfs_t<BW, 10>(graphs, jobs, n_jobs, stream);
+    case 12: return launch_bfs_t<BW, 12>(graphs, jobs, n_jobs, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bfs(int bw, int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                      hipStream_t stream)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    switch (bw) {
+    case 4: return launch_bfs_bw<4>(nw, graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_bw<8>(nw, graphs, jobs, n_jobs, stream);
+    case 16: return launch_bfs_bw<16>(nw, graphs, jobs, n_jobs, stream);
+    case 32: return launch_bfs_bw<32>(nw, graphs, jobs, n_jobs, stream);
+    case 64: return launch_bfs_bw<64>(nw, graphs, jobs, n_jobs, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ===========================================================================
+// Distance histograms h[i][k] = #{j : d(i,j) = k} from resident int8 rows.
+// One wavefront per row; every lane counts into its own LDS column
+// (bins[k][lane]) so increments never collide, then lane k sums bin k over
+// the 64 columns with a rotated start to stay free of bank conflicts.
+// Loads are aligned 16-byte chunks; bytes outside the row are masked.
+// ===========================================================================
+
+template <int K, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict__ graphs,
+                                                     const NodeJob *__restrict__ jobs)
+{
+    __shared__ uint32_t bins[WAVES][K][64];
+    const NodeJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int wave = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int row = job.i0 + wave;
+    const bool active = row < n;
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) bins[wave][k][lane] = 0;
+
+    if (active) {
+        const int8_t *__restrict__ base = G.dist;
+        const int64_t total = (int64_t)n * n;
+        const int64_t r0 = (int64_t)row * n;
+        const int64_t r1 = r0 + n;
+        for (int64_t c = (r0 & ~(int64_t)15) + lane * 16; c < r1; c += 64 * 16) {
+            if (c + 16 <= total) {
+                const uint4 x = *reinterpret_cast<const uint4 *>(base + c);
+                const uint32_t wv[4] = {x.x, x.y, x.z, x.w};
+                const bool inside = (c >= r0) && (c + 16 <= r1);
+#pragma unroll
+                for (int p = 0; p < 16; ++p) {
+                    const int d = (int)(int8_t)((wv[p / 4] >> (8 * (p % 4))) & 0xFFu);
+                    const int64_t f = c + p;
+                    if ((inside || (f >= r0 && f < r1)) && d >= 0 && d < K)
+                        __hip_atomic_fetch_add(&bins[wave][d][lane], 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            } else {
+                for (int64_t f = c; f < c + 16 && f < total; ++f) {
+                    const int d = (int)base[f];
+                    if (f >= r0 && f < r1 && d >= 0 && d < K)
+                        __hip_atomic_fetch_add(&bins[wave][d][lane], 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        int32_t *__restrict__ h = G.hist + (int64_t)row * G.K;
+        for (int k = lane; k < K; k += 64) {
+            uint32_t s = 0;
+            for (int l = 0; l < 64; ++l) s += bins[wave][k][(l + k) & 63];
+            h[k] = (int32_t)s;
+        }
+        for (int k = K + lane; k < G.K; k += 64) h[k] = 0;
+    }
+}
+
+hipError_t launch_hist(int K, const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
+                       hipStream_t stream)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    switch (K) {
+    case 32: hipLaunchKernelGGL((k_hist<32, 8>), dim3(n_jobs), dim3(512), 0, stream, graphs, jobs); break;
+    case 64: hipLaunchKernelGGL((k_hist<64, 8>), dim3(n_jobs), dim3(512), 0, stream, graphs, jobs); break;
+    case 128: hipLaunchKernelGGL((k_hist<128, 4>), dim3(n_jobs), dim3(256), 0, stream, graphs, jobs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// psi and V (Eq. 2; Algorithm 1 regrouped by distance value):
+//   psi_i = sum_k h[i][k] w_k,  V_i = sum_k h[i][k] u_k / psi_i,
+//   w_k = exp(-k^2 / (2 sigma^2)),  u_k = k^2 w_k / (2 sigma^2).
+// One thread per node, all sigmas of the graph; the histogram row stays in
+// registers. FP64ACC: FP64 fused multiply-adds (the FP64 vector rate is half
+// the FP32 rate, and one FMA64 per term is far cheaper than a compensated
+// FP32 sum). FP32C: FP32 with error-free products (FMA) and TwoSum, weights
+// split as hi + lo FP32 pairs.
+// ===========================================================================
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+
+template <int K, int PREC>
+__global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ graphs,
+                                                   const NodeJob *__restrict__ jobs,
+                                                   float *__restrict__ psi_out,
+                                                   float *__restrict__ v_out, int64_t out_ld)
+{
+    const NodeJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int i = job.i0 + (int)threadIdx.x;
+    if (i >= n) return;
+    const int kmax = min(G.dmax + 1, K);
+    const int32_t *__restrict__ hrow = G.hist + (int64_t)i * G.K;
+    int32_t h[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) h[k] = (k < kmax) ? hrow[k] : 0;
+
+    for (int s = 0; s < G.n_sigmas; ++s) {
+        float psi32, v32;
+        if constexpr (PREC == 0) {
+            const double *__restrict__ w = G.w64 + (int64_t)s * G.K;
+            const double *__restrict__ u = G.u64 + (int64_t)s * G.K;
+            double p = 0.0, q = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (k < kmax) {
+                    const double hk = (double)h[k];
+                    p = __fma_rn(hk, w[k], p);
+                    q = __fma_rn(hk, u[k], q);
+                }
+            }
+            psi32 = (float)p;
+            v32 = (float)(q / p);
+        } else {
+            const float *__restrict__ wt = G.w32c + (int64_t)s * G.K * 4;
+            float ps = 0.f, pe = 0.f, qs = 0.f, qe = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (k < kmax) {
+                    const float hk = (float)h[k];   // exact: counts < 2^24
+                    const float whi = wt[4 * k + 0], wlo = wt[4 * k + 1];
+                    const float uhi = wt[4 * k + 2], ulo = wt[4 * k + 3];
+                    // psi: TwoProduct(hk, whi) + hk*wlo, then TwoSum into (ps, pe)
+                    float t = hk * whi;
+                    float te = __fmaf_rn(hk, whi, -t) + hk * wlo;
+                    float s1, e1;
+                    two_sum(ps, t, s1, e1);
+                    ps = s1;
+                    pe += e1 + te;
+                    t = hk * uhi;
+                    te = __fmaf_rn(hk, uhi, -t) + hk * ulo;
+                    two_sum(qs, t, s1, e1);
+                    qs = s1;
+                    qe += e1 + te;
+                }
+            }
+            const float p = ps + pe;
+            const float q = qs + qe;
+            psi32 = p;
+            v32 = __fdiv_rn(q, p);
+        }
+        const int64_t o = (int64_t)s * n + i;
+        G.psi[o] = psi32;
+        G.v[o] = v32;
+        const int64_t ou = job.out_off + (int64_t)s * out_ld + i;
+        if (psi_out) psi_out[ou] = psi32;
+        if (v_out) v_out[ou] = v32;
+    }
+}
+
+hipError_t launch_potential(int precision, int K, const GraphDev *graphs, const NodeJob *jobs,
+                            int n_jobs, float *psi_out, float *v_out, int64_t out_ld,
+                            hipStream_t stream)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    const dim3 grid(n_jobs), block(256);
+#define QC_POT_ARGS grid, block, 0, stream, graphs, jobs, psi_out, v_out, out_ld
+    if (precision == 0) {
+        switch (K) {
+        case 32: hipLaunchKernelGGL((k_potential<32, 0>), QC_POT_ARGS); break;
+        case 64: hipLaunchKernelGGL((k_potential<64, 0>), QC_POT_ARGS); break;
+        case 128: hipLaunchKernelGGL((k_potential<128, 0>), QC_POT_ARGS); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else if (precision == 1) {
+        switch (K) {
+        case 32: hipLaunchKernelGGL((k_potential<32, 1>), QC_POT_ARGS); break;
+        case 64: hipLaunchKernelGGL((k_potential<64, 1>), QC_POT_ARGS); break;
+        case 128: hipLaunchKernelGGL((k_potential<128, 1>), QC_POT_ARGS); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef QC_POT_ARGS
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Graph Gradient Descent, first half of Algorithm 2: every node picks the
+// neighbour it descends to.
+//
+// FP32 pass: lowest and second-lowest neighbour V (the lowest keeps the
+// smallest id, since neighbours are sorted). If both the argmin and the
+// comparison with the node's own V are clear by more than the FP32 error
+// bound, the FP32 order is the FP64 order and the decision is final.
+// Otherwise the node is re-decided with the canonical FP64 potential of
+// itself and of every neighbour within the bound of the lowest one. The
+// canonical FP64 value sums h_k * w_k and (k^2 h_k) * w_k in ascending k from
+// +0.0 with separate roundings (no contraction), then (1/a) * (S1/S2): the
+// same IEEE operations in the same order as the CPU oracle, so both sides
+// take identical decisions, exact ties included.
+// ===========================================================================
+
+__device__ __noinline__ double canonical_v(const int32_t *__restrict__ h, int kmax,
+                                           const double *__restrict__ w, double inv_a)
+{
+#pragma clang fp contract(off)
+    double s2 = 0.0, s1 = 0.0;
+    for (int k = 0; k < kmax; ++k) {
+        const double hk = (double)h[k];
+        s2 = s2 + hk * w[k];
+        s1 = s1 + ((double)(k * k) * hk) * w[k];
+    }
+    return inv_a * (s1 / s2);
+}
+
+__global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev *__restrict__ graphs,
+                                                    const NodeJob *__restrict__ jobs, int sigma_base)
+{
+    const NodeJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int s = sigma_base + (int)blockIdx.y;
+    const int i = job.i0 + (int)threadIdx.x;
+    if (i >= n || s >= G.n_sigmas) return;
+    const float *__restrict__ V = G.v + (int64_t)s * n;
+    const int32_t *__restrict__ col = G.col;
+    const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
+    const float vi = V[i];
+
+    float m1 = FLT_MAX, m2 = FLT_MAX;
+    int j1 = -1;
+    for (int e = e0; e < e1; ++e) {
+        const int j = col[e];
+        const float vj = V[j];
+        if (vj < m1) { m2 = m1; m1 = vj; j1 = j; }
+        else if (vj < m2) m2 = vj;
+    }
+    int parent = i;
+    if (j1 >= 0) {
+        const float tau = kTieTau;
+        bool ambiguous = (m2 - m1 <= tau * m2);
+        const float hi = fmaxf(m1, vi), lo = fminf(m1, vi);
+        if (hi - lo <= tau * hi) ambiguous = true;
+        if (!ambiguous) {
+            parent = (m1 < vi) ? j1 : i;
+        } else {
+            const int K = G.K;
+            const int kmax = G.dmax + 1;
+            const double *__restrict__ w = G.w64 + (int64_t)s * K;
+            const double inv_a = G.inv_a[s];
+            const double vi64 = canonical_v(G.hist + (int64_t)i * K, kmax, w, inv_a);
+            double bv = DBL_MAX;
+            int best = -1;
+            for (int e = e0; e < e1; ++e) {
+                const int j = col[e];
+                const float vj = V[j];
+                if (vj - m1 <= tau * vj) {
+                    const double d = canonical_v(G.hist + (int64_t)j * K, kmax, w, inv_a);
+                    if (d < bv) { bv = d; best = j; }
+                }
+            }
+            if (tie_mode == 0) parent = (bv < vi64) ? best : i;
+            else parent = (bv < vi64 || (bv == vi64 && best < i)) ? best : i;
+            atomicAdd(G.recheck, 1ull);
+        }
+    }
+    G.parent[(int64_t)s * n + i] = parent;
+}
+
+hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob *jobs,
+                             int n_jobs, int sigma_base, int n_sig, hipStream_t stream)
+{
+    if (n_jobs <= 0 || n_sig <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ggd_parent, dim3(n_jobs, n_sig), dim3(256), 0, stream, tie_mode, graphs,
+                       jobs, sigma_base);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Algorithm 3 for every node: pointer jumping lab[i] <- lab[lab[i]] until
+// every node points at a root (a node that is its own parent). Parents only
+// ever point to strictly lower (V, id) nodes, so the forest has no cycles and
+// the loop ends after about log2(height) rounds. One workgroup per (graph,
+// sigma); updates in place are safe because every value written is an
+// ancestor on the same path.
+// ===========================================================================
+
+__global__ __launch_bounds__(1024) void k_jump(const GraphDev *__restrict__ graphs,
+                                               const NodeJob *__restrict__ jobs, int sigma_base,
+                                               int32_t *labels_base, int64_t labels_ld)
+{
+    const NodeJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int s = sigma_base + (int)blockIdx.y;
+    if (s >= G.n_sigmas) return;
+    const int32_t *__restrict__ par = G.parent + (int64_t)s * n;
+    int32_t *lab = labels_base + (int64_t)blockIdx.y * labels_ld + job.out_off;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = par[i];
+    __syncthreads();
+    for (int round = 0; round < 64; ++round) {
+        int changed = 0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int p = __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int q = __hip_atomic_load(&lab[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (q != p) {
+                __hip_atomic_store(&lab[i], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+}
+
+hipError_t launch_pointer_jump(const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
+                               int sigma_base, int n_sig, int32_t *labels_base,
+                               int64_t labels_ld, hipStream_t stream)
+{
+    if (n_jobs <= 0 || n_sig <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jump, dim3(n_jobs, n_sig), dim3(1024), 0, stream, graphs, jobs,
+                       sigma_base, labels_base, labels_ld);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+
+__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    int blocks = (int)((count + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, stream, p, count, value);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t count, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, stream, p, count);
+    return hipGetLastError();
+}
+
+__global__ void k_set_desc(GraphDev *dst, GraphDev src)
+{
+    if (threadIdx.x == 0) *dst = src;
+}
+
+hipError_t launch_set_desc(GraphDev *dst, const GraphDev &src, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, stream, dst, src);
+    return hipGetLastError();
+}
+
+}  // namespace qc

@@ -1,0 +1,226 @@
+"""Python binding of the C ABI in include/qc.h (ctypes).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libqc_hip.so``. PyTorch supplies device memory (tensors) and the
+stream (``torch.cuda.current_stream()``). The binding refuses to run when the
+library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqc_hip.so")
+
+QC_OK = 0
+QC_E_INVAL = 1
+QC_E_NOT_SYMMETRIC = 2
+QC_E_OOM = 3
+QC_E_DEVICE = 4
+QC_E_OVERFLOW = 5
+QC_E_STATE = 6
+QC_E_BUSY = 7
+
+TIE_STRICT = 0
+TIE_MERGE = 1
+
+PREC_FP64ACC = 0
+PREC_FP32C = 1
+PREC_BF16 = 2
+
+GRAPH_CANONICALIZE = 1
+
+# Every symbol include/qc.h declares (checked by the tests).
+EXPORTED = [
+    "qc_status_str", "qc_device_count", "qc_graph_create", "qc_graph_destroy",
+    "qc_graph_info", "qc_distances", "qc_get_histograms", "qc_potential",
+    "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync",
+]
+
+
+class QCError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)}")
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2305_14641_amd.build` "
+                "(or __graft_entry__.build()); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I32 = ctypes.c_int32
+        I64 = ctypes.c_int64
+        U32 = ctypes.c_uint32
+        L.qc_status_str.argtypes = [I32]
+        L.qc_status_str.restype = ctypes.c_char_p
+        L.qc_device_count.argtypes = [P]
+        L.qc_graph_create.argtypes = [I32, I64, P, P, U32, P, P]
+        L.qc_graph_destroy.argtypes = [P]
+        L.qc_graph_info.argtypes = [P, P, P, P, P]
+        L.qc_distances.argtypes = [P, P, P, P]
+        L.qc_get_histograms.argtypes = [P, P, P, P]
+        L.qc_potential.argtypes = [P, P, I32, P, P, U32, P]
+        L.qc_ggd_labels.argtypes = [P, I32, U32, P, P]
+        L.qc_last_recheck_count.argtypes = [P, P]
+        L.qc_graph_sync.argtypes = [P, P]
+        for name in EXPORTED[1:]:
+            getattr(L, name).restype = I32
+        _lib = L
+    return _lib
+
+
+def status_str(status: int) -> str:
+    return lib().qc_status_str(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != QC_OK:
+        raise QCError(status, what)
+
+
+def device_count() -> int:
+    c = ctypes.c_int32(0)
+    _check(lib().qc_device_count(ctypes.byref(c)), "qc_device_count")
+    return int(c.value)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    if stream is None:
+        if not torch.cuda.is_available():
+            return None  # default stream; the library reports QC_E_DEVICE itself
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Graph:
+    """A graph handle: CSR uploaded once, distances/potentials resident."""
+
+    def __init__(self, n: int, row_ptr, col, canonicalize: bool = False, stream=None):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        self._rp, self._col = rp, c
+        h = ctypes.c_void_p()
+        st = lib().qc_graph_create(
+            int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+            c.ctypes.data_as(ctypes.c_void_p), GRAPH_CANONICALIZE if canonicalize else 0,
+            _stream_ptr(stream), ctypes.byref(h))
+        _check(st, "qc_graph_create")
+        self._h = h
+        self.n = int(n)
+        self.sigmas = None
+
+    @classmethod
+    def from_graph(cls, g, **kw):
+        return cls(g.n, g.row_ptr, g.col, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().qc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n = ctypes.c_int32()
+        nnz = ctypes.c_int64()
+        dmax = ctypes.c_int32()
+        comps = ctypes.c_int32()
+        _check(lib().qc_graph_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
+                                   ctypes.byref(dmax), ctypes.byref(comps)), "qc_graph_info")
+        return dict(n=n.value, nnz=nnz.value, dmax=dmax.value, n_components=comps.value)
+
+    def distances(self, out=None, stream=None):
+        """Hop-distance matrix (int8 [n, n], -1 = unreachable) into `out`
+        (a CUDA int8 tensor) or kept resident when out is None. Returns dmax."""
+        if out is not None:
+            self._check_tensor(out, (self.n, self.n), "int8")
+        dmax = ctypes.c_int32(-1)
+        _check(lib().qc_distances(self._h, _dptr(out), ctypes.byref(dmax), _stream_ptr(stream)),
+               "qc_distances")
+        return int(dmax.value)
+
+    def histograms(self, stream=None):
+        import torch
+        k = ctypes.c_int32(0)
+        _check(lib().qc_get_histograms(self._h, None, ctypes.byref(k), _stream_ptr(stream)),
+               "qc_get_histograms")
+        out = torch.empty((self.n, k.value), dtype=torch.int32, device="cuda")
+        _check(lib().qc_get_histograms(self._h, _dptr(out), ctypes.byref(k), _stream_ptr(stream)),
+               "qc_get_histograms")
+        return out
+
+    def potential(self, sigmas, psi=None, v=None, precision=PREC_FP64ACC, stream=None):
+        """psi and V [len(sigmas), n] (float32) for each sigma."""
+        import torch
+        sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).reshape(-1))
+        S = sig.shape[0]
+        if psi is None:
+            psi = torch.empty((S, self.n), dtype=torch.float32, device="cuda")
+        if v is None:
+            v = torch.empty((S, self.n), dtype=torch.float32, device="cuda")
+        self._check_tensor(psi, (S, self.n), "float32")
+        self._check_tensor(v, (S, self.n), "float32")
+        _check(lib().qc_potential(self._h, sig.ctypes.data_as(ctypes.c_void_p), S, _dptr(psi),
+                                  _dptr(v), int(precision), _stream_ptr(stream)), "qc_potential")
+        self.sigmas = sig
+        return psi, v
+
+    def labels(self, sigma_index=0, tie_mode=TIE_STRICT, out=None, stream=None):
+        """Graph Gradient Descent labels (int32 [n]) for one sigma."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n,), dtype=torch.int32, device="cuda")
+        self._check_tensor(out, (self.n,), "int32")
+        _check(lib().qc_ggd_labels(self._h, int(sigma_index), int(tie_mode), _dptr(out),
+                                   _stream_ptr(stream)), "qc_ggd_labels")
+        return out
+
+    def recheck_count(self) -> int:
+        c = ctypes.c_int64(0)
+        _check(lib().qc_last_recheck_count(self._h, ctypes.byref(c)), "qc_last_recheck_count")
+        return int(c.value)
+
+    def sync(self, stream=None):
+        _check(lib().qc_graph_sync(self._h, _stream_ptr(stream)), "qc_graph_sync")
+
+    @staticmethod
+    def _check_tensor(t, shape, dtype):
+        import torch
+        want = getattr(torch, dtype)
+        if not t.is_cuda or t.dtype != want or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous CUDA {dtype} tensor of shape {shape}")
+
+
+def cluster(g, sigmas, tie_mode=TIE_STRICT, precision=PREC_FP64ACC, dist_out=None):
+    """Algorithm 4 for a list of sigmas on the GPU: returns (dmax, psi, V, labels)."""
+    import torch
+    G = Graph.from_graph(g)
+    dmax = G.distances(dist_out)
+    psi, v = G.potential(sigmas, precision=precision)
+    labels = torch.stack([G.labels(s, tie_mode) for s in range(len(sigmas))])
+    return G, dmax, psi, v, labels

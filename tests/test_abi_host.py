@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+headers declare, and rejects invalid input on the host before any device work
+(qc_graph_create validates first; on a machine without a gfx950 device a
+valid graph is refused with QC_E_DEVICE)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2305_14641_amd import qc
+from paper_2305_14641_amd import graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(qc_\w+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = qc.lib()
+    names = declared_symbols()
+    assert "qc_graph_create" in names and "qc_potential" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(qc.EXPORTED) <= set(names)
+
+
+def test_status_strings():
+    for s in range(8):
+        assert qc.status_str(s).startswith("QC_")
+    assert "unknown" in qc.status_str(99)
+
+
+def create(n, rp, col, flags=0):
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    st = qc.lib().qc_graph_create(n, col.shape[0], rp.ctypes.data_as(ctypes.c_void_p),
+                                  col.ctypes.data_as(ctypes.c_void_p) if col.size else None,
+                                  flags, None, ctypes.byref(h))
+    if st == qc.QC_OK:
+        qc.lib().qc_graph_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("case,want", [
+    ((0, [0], []), qc.QC_E_INVAL),                          # n = 0
+    ((70000, [0] * 70001, []), qc.QC_E_INVAL),              # n above 65536
+    ((3, [0, 1, 2, 2], [1, 0, 0]), qc.QC_E_INVAL),          # row_ptr[n] != nnz... (3 entries, rp[3]=2)
+    ((2, [0, 2, 1], [1, 0]), qc.QC_E_INVAL),                # decreasing row_ptr
+    ((2, [0, 1, 2], [1, 5]), qc.QC_E_INVAL),                # column out of range
+    ((2, [0, 1, 2], [1, 1]), qc.QC_E_NOT_SYMMETRIC),        # self-loop
+    ((3, [0, 1, 1, 1], [1]), qc.QC_E_NOT_SYMMETRIC),        # (0,1) without (1,0)
+    ((3, [0, 2, 3, 4], [2, 1, 0, 0]), qc.QC_E_NOT_SYMMETRIC),  # unsorted row
+    ((3, [0, 2, 3, 4], [1, 1, 0, 0]), qc.QC_E_NOT_SYMMETRIC),  # duplicate entry
+])
+def test_invalid_csr_rejected_on_host(case, want):
+    n, rp, col = case
+    assert create(n, rp, col) == want
+
+
+def test_null_pointers_rejected():
+    L = qc.lib()
+    h = ctypes.c_void_p()
+    assert L.qc_graph_create(2, 2, None, None, 0, None, ctypes.byref(h)) == qc.QC_E_INVAL
+    rp = np.array([0, 1, 2], np.int32)
+    col = np.array([1, 0], np.int32)
+    assert L.qc_graph_create(2, 2, rp.ctypes.data_as(ctypes.c_void_p),
+                             col.ctypes.data_as(ctypes.c_void_p), 0, None, None) == qc.QC_E_INVAL
+    assert L.qc_graph_create(2, 2, rp.ctypes.data_as(ctypes.c_void_p),
+                             col.ctypes.data_as(ctypes.c_void_p), 8, None,
+                             ctypes.byref(h)) == qc.QC_E_INVAL  # unknown flag
+    for fn, args in [("qc_graph_destroy", [None]), ("qc_distances", [None, None, None, None]),
+                     ("qc_potential", [None, None, 1, None, None, 0, None]),
+                     ("qc_ggd_labels", [None, 0, 0, None, None]),
+                     ("qc_graph_info", [None, None, None, None, None]),
+                     ("qc_graph_sync", [None, None]),
+                     ("qc_last_recheck_count", [None, None]),
+                     ("qc_get_histograms", [None, None, None, None])]:
+        assert getattr(L, fn)(*args) == qc.QC_E_INVAL, fn
+
+
+def test_valid_graph_without_gpu_reports_device():
+    if qc.device_count() > 0:
+        pytest.skip("a gfx950 device is visible")
+    g = gg.config1()
+    assert create(g.n, g.row_ptr, g.col) == qc.QC_E_DEVICE
+    # a non-canonical graph that canonicalises is also valid input
+    assert create(3, [0, 2, 3, 4], [2, 1, 0, 0], flags=qc.GRAPH_CANONICALIZE) == qc.QC_E_DEVICE
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(qc, "_lib", None)
+    monkeypatch.setattr(qc, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        qc.lib()
