@@ -172,6 +172,25 @@ qc_status qc_last_recheck_count(qc_graph g, int64_t *count_out);
  * latched (QC_E_OVERFLOW) since the last check. */
 qc_status qc_graph_sync(qc_graph g, void *stream);
 
+/*
+ * Kernel timing, for benchmarks (process-wide). While enabled, the library
+ * brackets every kernel launch of each stage with a pair of HIP events
+ * recorded on the launch stream (never while that stream is being captured
+ * into a HIP graph). qc_timing_read waits for the recorded events and returns
+ * the summed device time and the number of launches of one stage.
+ *   stage  QC_STAGE_*;  total_ms, launches: host, may be NULL
+ */
+enum {
+    QC_STAGE_BFS = 0,        /* multi-source BFS (distances) */
+    QC_STAGE_HIST = 1,       /* distance histograms */
+    QC_STAGE_POTENTIAL = 2,  /* psi / V */
+    QC_STAGE_GGD = 3,        /* descent parents (with FP64 re-check) */
+    QC_STAGE_JUMP = 4,       /* pointer jumping to labels */
+    QC_N_STAGES = 5
+};
+qc_status qc_timing_enable(int32_t on);  /* on = 1 also clears earlier records */
+qc_status qc_timing_read(int32_t stage, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

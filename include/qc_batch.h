@@ -1,0 +1,73 @@
+/*
+ * qc_batch.h — batched form: many graphs of uneven size and many widths
+ * sigma in a handful of grouped launches, optionally replayed as one HIP graph.
+ *
+ * A batch runs Algorithm 4 of Wang, He & Liu (arXiv 2305.14641) — distances,
+ * potentials (Eq. 2, Eq. 7 / Algorithm 1), Graph Gradient Descent labels
+ * (Algorithms 2-3) — for every (graph, sigma) pair of the batch. Every result
+ * is bitwise identical to what the plain per-graph calls of qc.h return.
+ */
+#ifndef QC_BATCH_H_
+#define QC_BATCH_H_
+
+#include "qc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qc_batch_s *qc_batch;
+
+enum {
+    QC_BATCH_HIPGRAPH = 1u, /* capture the launch sequence once, replay it afterwards */
+    QC_BATCH_FP32C = 2u     /* potentials in compensated FP32 instead of FP64 accumulation */
+};
+
+/*
+ * Plan a batch.
+ *   graphs     host, qc_graph[n_graphs] created with qc_graph_create; the batch
+ *              uses their resident buffers (distance matrix, histograms,
+ *              potentials, weights), so a graph must not be used elsewhere
+ *              while a batch run is in flight, and must outlive the batch.
+ *              A graph appears at most once. The batch keeps the resident
+ *              distance matrix each graph has when the batch is created.
+ *   n_graphs   1 <= n_graphs <= 65536
+ *   sigmas     host, double[n_sigmas], each finite and > 0 (1..1024 values),
+ *              shared by every graph
+ *   tie_mode   QC_TIE_STRICT or QC_TIE_MERGE
+ *   flags      any of QC_BATCH_HIPGRAPH, QC_BATCH_FP32C
+ *   stream     stream for any set-up work (graphs whose largest distance is
+ *              not yet known run their distances once here, synchronously)
+ *   out        host, receives the batch handle
+ * Errors: QC_E_INVAL, QC_E_OVERFLOW (from a set-up distance pass), QC_E_OOM.
+ */
+qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double *sigmas,
+                          int32_t n_sigmas, uint32_t tie_mode, uint32_t flags, void *stream,
+                          qc_batch *out);
+
+/* Node offsets of each graph in the concatenated output layout:
+ * offsets host int64[n_graphs + 1]; offsets[n_graphs] = total nodes. */
+qc_status qc_batch_node_offsets(qc_batch b, int64_t *offsets);
+
+/*
+ * Run the whole path for every (graph, sigma).
+ *   psi_out, v_out  device, float[n_sigmas][total_nodes] (graph g's node i of
+ *                   sigma s at [s*total + offsets[g] + i]), or NULL
+ *   labels_out      device, int32[n_sigmas][total_nodes], same layout, required
+ * With QC_BATCH_HIPGRAPH the first run captures the launches on `stream`
+ * and every later run with the same output pointers replays that graph.
+ */
+qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
+                       void *stream);
+
+/* Number of node decisions re-decided in FP64 by the last run (waits). */
+qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out);
+
+/* Release the batch (the graphs stay valid). */
+qc_status qc_batch_destroy(qc_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QC_BATCH_H_ */

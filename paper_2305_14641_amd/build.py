@@ -20,7 +20,9 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqc_hip.so")
 
-SOURCES = ["qc_kernels.hip", "qc_api.cpp", "qc_host.cpp", "qc_batch.cpp", "qc_server.cpp"]
+SOURCES = ["qc_kernels.hip", "qc_bfs_4.hip", "qc_bfs_8.hip", "qc_bfs_16.hip", "qc_bfs_32.hip",
+           "qc_bfs_64.hip", "qc_api.cpp", "qc_host.cpp", "qc_timing.cpp", "qc_batch.cpp",
+           "qc_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -41,7 +43,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(12, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]

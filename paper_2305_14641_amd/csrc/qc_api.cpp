@@ -10,113 +10,17 @@
 #include "qc.h"
 #include "qc_host.h"
 #include "qc_internal.h"
+#include "qc_handle.h"
 
 using namespace qc;
 
-struct qc_graph_s {
-    int device = 0;
-    int32_t n = 0;
-    int64_t nnz = 0;
-    int32_t n_components = 0;
-    BfsPlan plan{};
-
-    // device CSR
-    int32_t *d_row_ptr = nullptr;
-    int32_t *d_col = nullptr;
-    uint32_t *d_edges = nullptr;
-
-    // distances and histograms
-    int8_t *d_dist_owned = nullptr;   // library-owned matrix (n*n, 16-byte padded)
-    int8_t *d_dist = nullptr;         // current resident matrix (owned or caller's)
-    int32_t *d_hist = nullptr;
-    int K = 0;
-    int32_t dmax = -1;
-    bool have_dist = false;
-
-    // potentials
-    int n_sigmas = 0;
-    int pot_cap = 0;                  // sigmas the buffers below hold
-    float *d_psi = nullptr, *d_v = nullptr;
-    int32_t *d_parent = nullptr;
-    double *d_w64 = nullptr, *d_u64 = nullptr, *d_inv_a = nullptr;
-    float *d_w32c = nullptr;
-    int w_cap = 0;                    // sigma*K entries the weight buffers hold
-    bool have_pot = false;
-    uint32_t pot_precision = 0;
-
-    // status words, descriptor, job tables
-    int32_t *d_status = nullptr;              // [2]
-    unsigned long long *d_recheck = nullptr;  // [1]
-    GraphDev *d_desc = nullptr;
-    BfsJob *d_bfs_jobs = nullptr;
-    NodeJob *d_node_jobs = nullptr;           // kNodesPerJob nodes each
-    int n_node_jobs = 0;
-    NodeJob *d_hist_jobs = nullptr;           // hist_rows_per_job(K) rows each
-    int n_hist_jobs = 0;
-    int hist_jobs_k = 0;
-
-    GraphDev desc() const
-    {
-        GraphDev d;
-        memset(&d, 0, sizeof d);
-        d.n = n;
-        d.K = K;
-        d.dmax = dmax;
-        d.n_sigmas = n_sigmas;
-        d.nnz = nnz;
-        d.row_ptr = d_row_ptr;
-        d.col = d_col;
-        d.edges = d_edges;
-        d.dist = d_dist;
-        d.hist = d_hist;
-        d.psi = d_psi;
-        d.v = d_v;
-        d.w64 = d_w64;
-        d.u64 = d_u64;
-        d.inv_a = d_inv_a;
-        d.w32c = d_w32c;
-        d.parent = d_parent;
-        d.status = d_status;
-        d.recheck = d_recheck;
-        return d;
-    }
-};
-
-namespace {
+namespace qc {
 
 qc_status from_hip(hipError_t e)
 {
     if (e == hipSuccess) return QC_OK;
     if (e == hipErrorOutOfMemory) return QC_E_OOM;
     return QC_E_DEVICE;
-}
-
-#define QC_TRY(expr)                                  \
-    do {                                              \
-        qc_status _st = (expr);                       \
-        if (_st != QC_OK) return _st;                 \
-    } while (0)
-#define QC_HIP(expr) QC_TRY(from_hip(expr))
-
-template <class T>
-qc_status dalloc(T **p, size_t count)
-{
-    *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return e == hipErrorOutOfMemory ? QC_E_OOM : QC_E_DEVICE;
-    }
-    return QC_OK;
-}
-
-template <class T>
-void dfree(T *&p)
-{
-    if (p) (void)hipFree((void *)p);
-    p = nullptr;
 }
 
 qc_status check_device(int *dev_out)
@@ -135,19 +39,25 @@ qc_status check_device(int *dev_out)
     return QC_OK;
 }
 
-hipStream_t as_stream(void *s) { return (hipStream_t)s; }
-
 qc_status push_desc(qc_graph g, hipStream_t st)
 {
     return from_hip(launch_set_desc(g->d_desc, g->desc(), st));
 }
 
-// Upload a small host array synchronously (set-up only, never in a timed path).
-template <class T>
-qc_status upload(T *dst, const std::vector<T> &src)
+qc_status set_plan(qc_graph g, const BfsPlan &p)
 {
-    if (src.empty()) return QC_OK;
-    return from_hip(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (p.bw <= 0) return QC_E_INVAL;
+    if (g->d_bfs_jobs && p.bw == g->plan.bw) {
+        g->plan = p;
+        return QC_OK;
+    }
+    std::vector<BfsJob> jobs(p.n_batches);
+    for (int b = 0; b < p.n_batches; ++b) jobs[b] = BfsJob{0, b * p.bw};
+    dfree(g->d_bfs_jobs);
+    QC_TRY(dalloc(&g->d_bfs_jobs, jobs.size()));
+    QC_TRY(upload(g->d_bfs_jobs, jobs));
+    g->plan = p;
+    return QC_OK;
 }
 
 qc_status ensure_hist_jobs(qc_graph g)
@@ -169,20 +79,30 @@ qc_status run_distances(qc_graph g, hipStream_t st)
 {
     QC_HIP(launch_fill_i32(g->d_status, 2, 0, st));
     QC_TRY(push_desc(g, st));
-    QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->d_desc, g->d_bfs_jobs, g->plan.n_batches, st));
+    {
+        StageTimer t(QC_STAGE_BFS, st);
+        QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->plan.planes, g->d_desc, g->d_bfs_jobs,
+                          g->plan.n_batches, st));
+    }
     if (g->dmax < 0) {
         int32_t status[2];
         QC_HIP(hipMemcpyAsync(status, g->d_status, sizeof status, hipMemcpyDeviceToHost, st));
         QC_HIP(hipStreamSynchronize(st));
         if (status[1]) return QC_E_OVERFLOW;
+        if (status[1] & 2) return QC_E_DEVICE;  // cannot happen with 7 planes
         g->dmax = status[0];
         g->K = bins_for(g->dmax);
+        // later runs need only enough planes for dmax: maybe a wider batch
+        QC_TRY(set_plan(g, plan_bfs(g->n, g->dmax)));
         dfree(g->d_hist);
         QC_TRY(dalloc(&g->d_hist, (size_t)g->n * g->K));
         QC_TRY(ensure_hist_jobs(g));
         QC_TRY(push_desc(g, st));
     }
-    QC_HIP(launch_hist(g->K, g->d_desc, g->d_hist_jobs, g->n_hist_jobs, st));
+    {
+        StageTimer t(QC_STAGE_HIST, st);
+        QC_HIP(launch_hist(g->K, g->d_desc, g->d_hist_jobs, g->n_hist_jobs, st));
+    }
     g->have_dist = true;
     return QC_OK;
 }
@@ -192,9 +112,11 @@ qc_status ensure_sigma_buffers(qc_graph g, int S)
     if (S > g->pot_cap) {
         dfree(g->d_psi);
         dfree(g->d_v);
+        dfree(g->d_v64);
         dfree(g->d_parent);
         QC_TRY(dalloc(&g->d_psi, (size_t)S * g->n));
         QC_TRY(dalloc(&g->d_v, (size_t)S * g->n));
+        QC_TRY(dalloc(&g->d_v64, (size_t)S * g->n));
         QC_TRY(dalloc(&g->d_parent, (size_t)S * g->n));
         g->pot_cap = S;
     }
@@ -212,6 +134,28 @@ qc_status ensure_sigma_buffers(qc_graph g, int S)
     return QC_OK;
 }
 
+qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStream_t st)
+{
+    std::vector<double> sig(sigmas, sigmas + n_sigmas);
+    if (sig != g->sigmas_loaded) {
+        std::vector<double> w64, u64, inv_a;
+        std::vector<float> w32c;
+        weight_tables(sigmas, n_sigmas, g->K, w64, u64, inv_a, w32c);
+        QC_TRY(ensure_sigma_buffers(g, n_sigmas));
+        // The weight tables are tiny; a synchronous upload keeps host buffers
+        // safe. A repeated sigma list reuses the tables already on the device.
+        QC_HIP(hipStreamSynchronize(st));
+        QC_TRY(upload(g->d_w64, w64));
+        QC_TRY(upload(g->d_u64, u64));
+        QC_TRY(upload(g->d_inv_a, inv_a));
+        QC_TRY(upload(g->d_w32c, w32c));
+        g->sigmas_loaded = sig;
+        g->n_sigmas = n_sigmas;
+        QC_TRY(push_desc(g, st));
+    }
+    return QC_OK;
+}
+
 void destroy(qc_graph g)
 {
     if (!g) return;
@@ -223,6 +167,7 @@ void destroy(qc_graph g)
     dfree(g->d_hist);
     dfree(g->d_psi);
     dfree(g->d_v);
+    dfree(g->d_v64);
     dfree(g->d_parent);
     dfree(g->d_w64);
     dfree(g->d_u64);
@@ -237,7 +182,7 @@ void destroy(qc_graph g)
     delete g;
 }
 
-}  // namespace
+}  // namespace qc
 
 extern "C" {
 
@@ -291,15 +236,13 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
     g->n = n;
     g->nnz = (int64_t)col.size();
     g->n_components = count_components(n, rp, col);
-    g->plan = plan_bfs(n);
     hipStream_t st = as_stream(stream);
 
-    std::vector<uint32_t> edges(g->nnz);
+    // packed edges, padded with no-op (0, 0) entries to a multiple of 4
+    std::vector<uint32_t> edges(((g->nnz + 3) / 4) * 4 + 4, 0u);
     for (int32_t i = 0; i < n; ++i)
         for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
             edges[e] = ((uint32_t)i << 16) | (uint32_t)col[e];
-    std::vector<BfsJob> bjobs(g->plan.n_batches);
-    for (int b = 0; b < g->plan.n_batches; ++b) bjobs[b] = BfsJob{0, b * g->plan.bw};
     std::vector<NodeJob> njobs;
     for (int i = 0; i < n; i += kNodesPerJob) njobs.push_back(NodeJob{0, i, 0});
     g->n_node_jobs = (int)njobs.size();
@@ -309,11 +252,11 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
     if ((st_ = dalloc(&g->d_row_ptr, rp.size())) || (st_ = dalloc(&g->d_col, col.size())) ||
         (st_ = dalloc(&g->d_edges, edges.size())) || (st_ = dalloc(&g->d_status, 2)) ||
         (st_ = dalloc(&g->d_recheck, 1)) || (st_ = dalloc(&g->d_desc, 1)) ||
-        (st_ = dalloc(&g->d_bfs_jobs, bjobs.size())) || (st_ = dalloc(&g->d_node_jobs, njobs.size())))
+        (st_ = dalloc(&g->d_node_jobs, njobs.size())))
         return fail(st_);
     if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
-        (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_bfs_jobs, bjobs)) ||
-        (st_ = upload(g->d_node_jobs, njobs)))
+        (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
+        (st_ = set_plan(g, plan_bfs(n, -1))))
         return fail(st_);
     if ((st_ = from_hip(launch_fill_u64(g->d_recheck, 1, st))) || (st_ = push_desc(g, st)))
         return fail(st_);
@@ -374,22 +317,18 @@ qc_status qc_potential(qc_graph g, const double *sigmas, int32_t n_sigmas, float
     hipStream_t st = as_stream(stream);
     if (!g->have_dist) QC_TRY(qc_distances(g, nullptr, nullptr, stream));
 
-    std::vector<double> w64, u64, inv_a;
-    std::vector<float> w32c;
-    weight_tables(sigmas, n_sigmas, g->K, w64, u64, inv_a, w32c);
-    QC_TRY(ensure_sigma_buffers(g, n_sigmas));
-    // The weight tables are tiny; a synchronous upload keeps host buffers safe.
-    QC_HIP(hipStreamSynchronize(st));
-    QC_TRY(upload(g->d_w64, w64));
-    QC_TRY(upload(g->d_u64, u64));
-    QC_TRY(upload(g->d_inv_a, inv_a));
-    QC_TRY(upload(g->d_w32c, w32c));
-    g->n_sigmas = n_sigmas;
-    QC_TRY(push_desc(g, st));
-    QC_HIP(launch_potential((int)precision, g->K, g->d_desc, g->d_node_jobs, g->n_node_jobs,
-                            psi_out, v_out, g->n, st));
+    QC_TRY(load_sigmas(g, sigmas, n_sigmas, st));
+    if (precision != g->pot_precision) {
+        // the descriptor's FP64 table pointer depends on the precision
+        g->pot_precision = precision;
+        QC_TRY(push_desc(g, st));
+    }
+    {
+        StageTimer t(QC_STAGE_POTENTIAL, st);
+        QC_HIP(launch_potential((int)precision, g->K, g->d_desc, g->d_node_jobs, g->n_node_jobs,
+                                psi_out, v_out, g->n, st));
+    }
     g->have_pot = true;
-    g->pot_precision = precision;
     return QC_OK;
 }
 
@@ -402,9 +341,15 @@ qc_status qc_ggd_labels(qc_graph g, int32_t sigma_index, uint32_t tie_mode, int3
     if (sigma_index < 0 || sigma_index >= g->n_sigmas) return QC_E_INVAL;
     hipStream_t st = as_stream(stream);
     QC_HIP(launch_fill_u64(g->d_recheck, 1, st));
-    QC_HIP(launch_ggd_parent((int)tie_mode, g->d_desc, g->d_node_jobs, g->n_node_jobs, sigma_index,
-                             1, st));
-    QC_HIP(launch_pointer_jump(g->d_desc, g->d_node_jobs, 1, sigma_index, 1, labels_out, 0, st));
+    {
+        StageTimer t(QC_STAGE_GGD, st);
+        QC_HIP(launch_ggd_parent((int)tie_mode, g->d_desc, g->d_node_jobs, g->n_node_jobs,
+                                 sigma_index, 1, st));
+    }
+    {
+        StageTimer t(QC_STAGE_JUMP, st);
+        QC_HIP(launch_pointer_jump(g->d_desc, g->d_node_jobs, 1, sigma_index, 1, labels_out, 0, st));
+    }
     return QC_OK;
 }
 

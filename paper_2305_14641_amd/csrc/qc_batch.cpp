@@ -1,0 +1,316 @@
+// Batched form (include/qc_batch.h): grouped launches over many graphs and
+// sigmas, optionally captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <set>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "qc_batch.h"
+#include "qc_handle.h"
+
+using namespace qc;
+
+struct BfsGroup {
+    int bw = 0, nw = 0, planes = 7;
+    BfsJob *d_jobs = nullptr;
+    int n_jobs = 0;
+};
+struct KGroup {
+    int K = 0;
+    NodeJob *d_jobs = nullptr;
+    int n_jobs = 0;
+};
+
+struct qc_batch_s {
+    std::vector<qc_graph> graphs;
+    std::vector<double> sigmas;
+    std::vector<int64_t> offsets;  // [n_graphs + 1]
+    uint32_t tie = 0;
+    uint32_t flags = 0;
+    int precision = QC_PREC_FP64ACC;
+
+    GraphDev *d_descs = nullptr;
+    unsigned long long *d_recheck = nullptr;
+    std::vector<BfsGroup> bfs;
+    std::vector<KGroup> hist;
+    std::vector<KGroup> pot;
+    NodeJob *d_ggd_jobs = nullptr;
+    int n_ggd_jobs = 0;
+    NodeJob *d_jump_jobs = nullptr;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float *cap_psi = nullptr, *cap_v = nullptr;
+    int32_t *cap_labels = nullptr;
+    hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+void free_batch(qc_batch b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    dfree(b->d_descs);
+    dfree(b->d_recheck);
+    for (auto &g : b->bfs) dfree(g.d_jobs);
+    for (auto &g : b->hist) dfree(g.d_jobs);
+    for (auto &g : b->pot) dfree(g.d_jobs);
+    dfree(b->d_ggd_jobs);
+    dfree(b->d_jump_jobs);
+    delete b;
+}
+
+template <class J>
+qc_status upload_jobs(J **d, const std::vector<J> &h)
+{
+    QC_TRY(dalloc(d, h.size()));
+    return upload(*d, h);
+}
+
+// Order jobs so that consecutive workgroups of one XCD (workgroups are handed
+// to the 8 XCDs round-robin by index) stay on the same graph: each graph's
+// jobs are dealt to one XCD list (the least loaded), and the lists are then
+// interleaved. The graphs' CSR and LDS-resident state thus stay in fewer L2s.
+template <class J>
+std::vector<J> xcd_order(const std::vector<std::vector<J>> &per_graph, const std::vector<double> &cost)
+{
+    constexpr int kXcd = 8;
+    std::vector<std::vector<J>> lanes(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    std::vector<int> order(per_graph.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int gi : order) {
+        if (per_graph[gi].empty()) continue;
+        // big graphs are spread over every XCD; small ones stay on one
+        const double share = cost[gi] / kXcd;
+        const bool spread = per_graph[gi].size() >= (size_t)(4 * kXcd);
+        if (spread) {
+            for (size_t j = 0; j < per_graph[gi].size(); ++j) {
+                int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                lanes[x].push_back(per_graph[gi][j]);
+                load[x] += cost[gi] / per_graph[gi].size();
+            }
+        } else {
+            int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (auto &j : per_graph[gi]) lanes[x].push_back(j);
+            load[x] += cost[gi];
+        }
+        (void)share;
+    }
+    std::vector<J> out;
+    size_t longest = 0;
+    for (auto &l : lanes) longest = std::max(longest, l.size());
+    for (size_t r = 0; r < longest; ++r)
+        for (int x = 0; x < kXcd; ++x)
+            if (r < lanes[x].size()) out.push_back(lanes[x][r]);
+    return out;
+}
+
+qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st)
+{
+    const int S = (int)b->sigmas.size();
+    const int64_t total = b->offsets.back();
+    QC_HIP(launch_fill_u64(b->d_recheck, 1, st));
+    for (auto &g : b->bfs) {
+        StageTimer t(QC_STAGE_BFS, st);
+        QC_HIP(launch_bfs(g.bw, g.nw, g.planes, b->d_descs, g.d_jobs, g.n_jobs, st));
+    }
+    for (auto &g : b->hist) {
+        StageTimer t(QC_STAGE_HIST, st);
+        QC_HIP(launch_hist(g.K, b->d_descs, g.d_jobs, g.n_jobs, st));
+    }
+    for (auto &g : b->pot) {
+        StageTimer t(QC_STAGE_POTENTIAL, st);
+        QC_HIP(launch_potential(b->precision, g.K, b->d_descs, g.d_jobs, g.n_jobs, psi_out, v_out,
+                                total, st));
+    }
+    {
+        StageTimer t(QC_STAGE_GGD, st);
+        QC_HIP(launch_ggd_parent((int)b->tie, b->d_descs, b->d_ggd_jobs, b->n_ggd_jobs, 0, S, st));
+    }
+    {
+        StageTimer t(QC_STAGE_JUMP, st);
+        QC_HIP(launch_pointer_jump(b->d_descs, b->d_jump_jobs, (int)b->graphs.size(), 0, S,
+                                   labels_out, total, st));
+    }
+    return QC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double *sigmas,
+                          int32_t n_sigmas, uint32_t tie_mode, uint32_t flags, void *stream,
+                          qc_batch *out)
+{
+    if (!graphs || !out || n_graphs < 1 || n_graphs > 65536) return QC_E_INVAL;
+    if (tie_mode > QC_TIE_MERGE) return QC_E_INVAL;
+    if (flags & ~(uint32_t)(QC_BATCH_HIPGRAPH | QC_BATCH_FP32C)) return QC_E_INVAL;
+    QC_TRY(validate_sigmas(sigmas, n_sigmas));
+    std::set<qc_graph> seen;
+    for (int i = 0; i < n_graphs; ++i) {
+        if (!graphs[i] || !seen.insert(graphs[i]).second) return QC_E_INVAL;
+    }
+    hipStream_t st = as_stream(stream);
+
+    qc_batch b = new qc_batch_s();
+    b->graphs.assign(graphs, graphs + n_graphs);
+    b->sigmas.assign(sigmas, sigmas + n_sigmas);
+    b->tie = tie_mode;
+    b->flags = flags;
+    b->precision = (flags & QC_BATCH_FP32C) ? QC_PREC_FP32C : QC_PREC_FP64ACC;
+    auto fail = [&](qc_status s) { free_batch(b); return s; };
+
+    // Per-graph set-up: resident matrix, largest distance, sigma tables.
+    b->offsets.assign(n_graphs + 1, 0);
+    for (int i = 0; i < n_graphs; ++i) {
+        qc_graph g = graphs[i];
+        if (!g->d_dist) {
+            qc_status s = dalloc(&g->d_dist_owned, (size_t)g->n * g->n + 16);
+            if (s) return fail(s);
+            g->d_dist = g->d_dist_owned;
+        }
+        if (g->dmax < 0) {
+            qc_status s = run_distances(g, st);
+            if (s) return fail(s);
+        }
+        qc_status s = load_sigmas(g, sigmas, n_sigmas, st);
+        if (s) return fail(s);
+        g->have_pot = true;
+        g->pot_precision = (uint32_t)b->precision;
+        b->offsets[i + 1] = b->offsets[i] + g->n;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(QC_E_DEVICE);
+
+    qc_status s;
+    if ((s = dalloc(&b->d_recheck, 1)) || (s = dalloc(&b->d_descs, (size_t)n_graphs))) return fail(s);
+    std::vector<GraphDev> descs(n_graphs);
+    for (int i = 0; i < n_graphs; ++i) {
+        descs[i] = graphs[i]->desc();
+        descs[i].recheck = b->d_recheck;
+    }
+    if ((s = upload(b->d_descs, descs))) return fail(s);
+
+    // BFS jobs grouped by launch shape (batch width, words per thread,
+    // planes), in XCD order.
+    std::map<std::tuple<int, int, int>, std::vector<int>> by_class;
+    for (int i = 0; i < n_graphs; ++i) {
+        const BfsPlan &p = graphs[i]->plan;
+        by_class[std::make_tuple(p.bw, p.nw, p.planes)].push_back(i);
+    }
+    for (auto &kv : by_class) {
+        std::vector<std::vector<BfsJob>> per;
+        std::vector<double> cost;
+        for (int gi : kv.second) {
+            qc_graph g = graphs[gi];
+            std::vector<BfsJob> js;
+            for (int bidx = 0; bidx < g->plan.n_batches; ++bidx) js.push_back(BfsJob{gi, bidx * g->plan.bw});
+            per.push_back(js);
+            cost.push_back((double)g->plan.n_batches * (double)(g->nnz + g->n) * (g->dmax + 2));
+        }
+        std::vector<BfsJob> jobs = xcd_order(per, cost);
+        BfsGroup grp;
+        grp.bw = std::get<0>(kv.first);
+        grp.nw = std::get<1>(kv.first);
+        grp.planes = std::get<2>(kv.first);
+        grp.n_jobs = (int)jobs.size();
+        if ((s = upload_jobs(&grp.d_jobs, jobs))) return fail(s);
+        b->bfs.push_back(grp);
+    }
+    // Histogram and potential jobs grouped by bin count.
+    std::map<int, std::vector<int>> by_k;
+    for (int i = 0; i < n_graphs; ++i) by_k[graphs[i]->K].push_back(i);
+    for (auto &kv : by_k) {
+        const int K = kv.first;
+        std::vector<NodeJob> hj, pj;
+        for (int gi : kv.second) {
+            const int n = graphs[gi]->n;
+            for (int r = 0; r < n; r += hist_rows_per_job(K)) hj.push_back(NodeJob{gi, r, 0});
+            for (int r = 0; r < n; r += kNodesPerJob) pj.push_back(NodeJob{gi, r, b->offsets[gi]});
+        }
+        KGroup h, p;
+        h.K = p.K = K;
+        h.n_jobs = (int)hj.size();
+        p.n_jobs = (int)pj.size();
+        if ((s = upload_jobs(&h.d_jobs, hj)) || (s = upload_jobs(&p.d_jobs, pj))) return fail(s);
+        b->hist.push_back(h);
+        b->pot.push_back(p);
+    }
+    std::vector<NodeJob> gj, jj;
+    for (int gi = 0; gi < n_graphs; ++gi) {
+        for (int r = 0; r < graphs[gi]->n; r += kNodesPerJob) gj.push_back(NodeJob{gi, r, 0});
+        jj.push_back(NodeJob{gi, 0, b->offsets[gi]});
+    }
+    b->n_ggd_jobs = (int)gj.size();
+    if ((s = upload_jobs(&b->d_ggd_jobs, gj)) || (s = upload_jobs(&b->d_jump_jobs, jj))) return fail(s);
+    // Each graph's own descriptor now reflects the batch's sigma list.
+    for (int i = 0; i < n_graphs; ++i)
+        if ((s = push_desc(graphs[i], st))) return fail(s);
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(QC_E_DEVICE);
+    *out = b;
+    return QC_OK;
+}
+
+qc_status qc_batch_node_offsets(qc_batch b, int64_t *offsets)
+{
+    if (!b || !offsets) return QC_E_INVAL;
+    std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+    return QC_OK;
+}
+
+qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, void *stream)
+{
+    if (!b || !labels_out) return QC_E_INVAL;
+    hipStream_t st = as_stream(stream);
+    const bool use_graph = (b->flags & QC_BATCH_HIPGRAPH) && st != nullptr;
+    if (!use_graph) return enqueue(b, psi_out, v_out, labels_out, st);
+
+    const bool same = b->exec && b->cap_psi == psi_out && b->cap_v == v_out &&
+                      b->cap_labels == labels_out && b->cap_stream == st;
+    if (!same) {
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        QC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        qc_status s = enqueue(b, psi_out, v_out, labels_out, st);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (s != QC_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
+        QC_HIP(e);
+        b->graph = graph;
+        QC_HIP(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
+        b->cap_psi = psi_out;
+        b->cap_v = v_out;
+        b->cap_labels = labels_out;
+        b->cap_stream = st;
+    }
+    QC_HIP(hipGraphLaunch(b->exec, st));
+    return QC_OK;
+}
+
+qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out)
+{
+    if (!b || !count_out) return QC_E_INVAL;
+    unsigned long long c = 0;
+    QC_HIP(hipDeviceSynchronize());
+    QC_HIP(hipMemcpy(&c, b->d_recheck, sizeof c, hipMemcpyDeviceToHost));
+    *count_out = (int64_t)c;
+    return QC_OK;
+}
+
+qc_status qc_batch_destroy(qc_batch b)
+{
+    if (!b) return QC_E_INVAL;
+    free_batch(b);
+    return QC_OK;
+}
+
+}  // extern "C"

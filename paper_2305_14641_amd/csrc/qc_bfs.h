@@ -1,0 +1,265 @@
+// Multi-source BFS kernel template (instantiated per batch width by
+// qc_bfs_<bw>.hip).
+//
+// One workgroup owns a batch of BW consecutive sources s0..s0+BW-1 and runs
+// the level-synchronous search of all of them at once. LDS holds three bit
+// fields per node: `seen` (the batch sources that have reached the node),
+// `front` (those that reached it at the previous level) and `nxt` (those
+// reaching it at the current level). A level is:
+//   A. edge-parallel pull: for every edge (r, c), the sources that reached c
+//      at the previous level and have not reached r reach r now:
+//        nxt[r] |= front[c] & ~seen[r]            (LDS atomic OR)
+//   B. word-owner update: every thread owns whole 32-bit words of the fields;
+//      it moves nxt into front and seen and records the level in the
+//      distance bit-planes of each newly reached (node, source) pair.
+//
+// Distances live in registers for the whole search, as P bit-planes of the
+// level (plane p holds bit p of every pair's distance; P = 7 covers every
+// distance up to 126, fewer planes suffice once the graph's largest distance
+// is known). Each batch therefore writes its BW output rows exactly once, at
+// the end. The graph is undirected, so node v's distances to the batch
+// sources are the entries (s0+b, v) of the row-major matrix: rows
+// s0..s0+BW-1 are this workgroup's.
+//
+// The edge list (packed (row << 16) | col, rows ascending, padded with no-op
+// (0, 0) entries to a multiple of 4) is streamed every level with 16-byte
+// global loads; every thread takes 8 consecutive edges (the next 8 in
+// flight), issues their 8 front gathers together, and merges each run of
+// edges of one row into a single seen read and at most one atomic.
+#pragma once
+
+#include "qc_internal.h"
+
+namespace qc {
+
+template <int BW> struct BfsWord {
+    using T = uint32_t;
+    static constexpr int kBits = 32;
+    static constexpr int kPer = 32 / BW;  // nodes per word
+};
+template <> struct BfsWord<64> {
+    using T = unsigned long long;
+    static constexpr int kBits = 64;
+    static constexpr int kPer = 1;
+};
+
+// 4-bit mask -> 4 bytes of 0x01 / 0x00 (bit i selects byte i).
+__device__ __forceinline__ uint32_t spread4(uint32_t m4)
+{
+    return (m4 * 0x00204081u) & 0x01010101u;
+}
+
+template <int BW>
+__device__ __forceinline__ typename BfsWord<BW>::T field_of(const typename BfsWord<BW>::T *a, int v)
+{
+    using W = BfsWord<BW>;
+    if constexpr (BW >= 32) {
+        return a[v];
+    } else {
+        const uint32_t w = a[v / W::kPer];
+        return (w >> ((v % W::kPer) * BW)) & ((1u << BW) - 1u);
+    }
+}
+
+// Deliver the OR `x` of the front fields of some neighbours of row r:
+// nxt[r] |= x & ~seen[r].
+template <int BW>
+__device__ __forceinline__ void pull_row(int r, typename BfsWord<BW>::T x,
+                                         const typename BfsWord<BW>::T *seen,
+                                         typename BfsWord<BW>::T *nxt)
+{
+    using W = BfsWord<BW>;
+    using T = typename W::T;
+    if (x) {
+        const T y = x & ~field_of<BW>(seen, r);
+        if (y) atomicOr(&nxt[r / W::kPer], (T)(y << ((r % W::kPer) * BW)));
+    }
+}
+
+// Pull along 8 consecutive edges (rows ascending).
+template <int BW>
+__device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
+                                         const typename BfsWord<BW>::T *front,
+                                         const typename BfsWord<BW>::T *seen,
+                                         typename BfsWord<BW>::T *nxt)
+{
+    using T = typename BfsWord<BW>::T;
+    const uint32_t e[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    T x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = field_of<BW>(front, (int)(e[k] & 0xFFFFu));
+    T acc = x[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        if ((e[k] >> 16) == (e[k - 1] >> 16)) {
+            acc |= x[k];
+        } else {
+            pull_row<BW>((int)(e[k - 1] >> 16), acc, seen, nxt);
+            acc = x[k];
+        }
+    }
+    pull_row<BW>((int)(e[7] >> 16), acc, seen, nxt);
+}
+
+template <int BW, int NW, int P>
+__global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict__ graphs,
+                                                     const BfsJob *__restrict__ jobs)
+{
+    using W = BfsWord<BW>;
+    using T = typename W::T;
+    constexpr int NWW = (BW == 64) ? NW / 2 : NW;   // words of type T per thread
+    constexpr int kLdsWords = NWW * kBfsThreads;
+    constexpr int kLevels = (P >= 7) ? kMaxDist : ((1 << P) - 1);  // largest encodable level
+
+    __shared__ T seen[kLdsWords];
+    __shared__ T front[kLdsWords];
+    __shared__ T nxt[kLdsWords];
+
+    const BfsJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int s0 = job.s0;
+    const int nb = min(BW, n - s0);
+    const int nwords = (n + W::kPer - 1) / W::kPer;
+    const int tid = threadIdx.x;
+    const int nquads = (int)((G.nnz + 3) >> 2);
+    const global_u4 quads = (global_u4)G.edges;
+
+    T plane[NWW][P];
+#pragma unroll
+    for (int j = 0; j < NWW; ++j)
+#pragma unroll
+        for (int p = 0; p < P; ++p) plane[j][p] = 0;
+
+    // Level 0: each source has reached itself (distance 0: no plane bits).
+#pragma unroll
+    for (int j = 0; j < NWW; ++j) {
+        const int w = j * kBfsThreads + tid;
+        T bits = 0;
+        if (w < nwords) {
+#pragma unroll
+            for (int q = 0; q < W::kPer; ++q) {
+                const int b = w * W::kPer + q - s0;
+                if (b >= 0 && b < nb) bits |= (T)1 << (q * BW + b);
+            }
+        }
+        seen[w] = bits;
+        front[w] = bits;
+        nxt[w] = 0;
+    }
+    __syncthreads();
+
+    const u32x4 zero4 = {0u, 0u, 0u, 0u};
+    int last = 0;
+    int overflow = 0;
+    for (int level = 1;; ++level) {
+        // A. pull over every edge, 8 consecutive edges per thread.
+        int q = 2 * tid;
+        u32x4 ca = (q < nquads) ? quads[q] : zero4;
+        u32x4 cb = (q + 1 < nquads) ? quads[q + 1] : zero4;
+        for (; q < nquads; q += 2 * kBfsThreads) {
+            const int qn = q + 2 * kBfsThreads;
+            const u32x4 na = (qn < nquads) ? quads[qn] : zero4;
+            const u32x4 nb4 = (qn + 1 < nquads) ? quads[qn + 1] : zero4;
+            pull_oct<BW>(ca, cb, front, seen, nxt);
+            ca = na;
+            cb = nb4;
+        }
+        __syncthreads();
+        // B. move the new bits of owned words into front / seen / planes.
+        int any = 0;
+#pragma unroll
+        for (int j = 0; j < NWW; ++j) {
+            const int w = j * kBfsThreads + tid;
+            if (w < nwords) {
+                const T y = nxt[w];
+                front[w] = y;
+                if (y) {
+                    nxt[w] = 0;
+                    seen[w] |= y;
+                    any = 1;
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+                        if ((level >> p) & 1) plane[j][p] |= y;
+                }
+            }
+        }
+        if (!__syncthreads_or(any)) break;
+        last = level;
+        if (level > kLevels) {
+            // this level does not fit the planes (P = 7: a distance above 126)
+            overflow = (P >= 7) ? 1 : 2;
+            break;
+        }
+    }
+
+    // Decode the planes of every owned word into distance bytes and write
+    // rows s0..s0+nb-1, columns = owned nodes. Unreached pairs get -1 (0xFF).
+    int8_t *__restrict__ out = G.dist;
+#pragma unroll
+    for (int j = 0; j < NWW; ++j) {
+        const int w = j * kBfsThreads + tid;
+        if (w < nwords) {
+            const T sw = seen[w];
+#pragma unroll
+            for (int t = 0; t < W::kBits / 4; ++t) {
+                // pairs 4t..4t+3 of the word -> one dword of 4 distance bytes
+                uint32_t d = spread4((uint32_t)(~sw >> (4 * t)) & 0xFu) * 0xFFu;
+#pragma unroll
+                for (int p = 0; p < P; ++p) d |= spread4((uint32_t)(plane[j][p] >> (4 * t)) & 0xFu) << p;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int i = 4 * t + k;       // pair index in the word
+                    const int qn = i / BW;         // node within the word
+                    const int b = i % BW;          // source within the batch
+                    const int v = w * W::kPer + qn;
+                    if (v < n && b < nb)
+                        out[(int64_t)(s0 + b) * n + v] = (int8_t)((d >> (8 * k)) & 0xFFu);
+                }
+            }
+        }
+    }
+    if (tid == 0) {
+        atomicMax(&G.status[0], last);
+        if (overflow) atomicOr(&G.status[1], overflow);
+    }
+}
+
+template <int BW, int NW, int P>
+hipError_t launch_bfs_t(const GraphDev *graphs, const BfsJob *jobs, int n_jobs, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_bfs<BW, NW, P>), dim3(n_jobs), dim3(kBfsThreads), 0, stream, graphs, jobs);
+    return hipGetLastError();
+}
+
+template <int BW, int P>
+hipError_t launch_bfs_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                        hipStream_t stream)
+{
+    switch (nw) {
+    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1, P>(graphs, jobs, n_jobs, stream);
+            return hipErrorInvalidValue;
+    case 2: return launch_bfs_t<BW, 2, P>(graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_t<BW, 4, P>(graphs, jobs, n_jobs, stream);
+    case 6: return launch_bfs_t<BW, 6, P>(graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_t<BW, 8, P>(graphs, jobs, n_jobs, stream);
+    case 10: return launch_bfs_t<BW, 10, P>(graphs, jobs, n_jobs, stream);
+    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P>(graphs, jobs, n_jobs, stream);
+             return hipErrorInvalidValue;  // 7 planes x 12 words exceed the registers
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int BW>
+hipError_t launch_bfs_bw(int nw, int planes, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                         hipStream_t stream)
+{
+    switch (planes) {
+    case 4: return launch_bfs_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
+    case 5: return launch_bfs_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);
+    case 7: return launch_bfs_p<BW, 7>(nw, graphs, jobs, n_jobs, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace qc

@@ -1,0 +1,6 @@
+// Multi-source BFS instantiations for a batch width of 8 sources.
+#include "qc_bfs.h"
+
+namespace qc {
+template hipError_t launch_bfs_bw<8>(int, int, const GraphDev *, const BfsJob *, int, hipStream_t);
+}  // namespace qc

@@ -1,0 +1,143 @@
+// The graph handle and the helpers the API, batch and serving code share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <vector>
+
+#include "qc.h"
+#include "qc_host.h"
+#include "qc_internal.h"
+
+using qc::BfsJob;
+using qc::BfsPlan;
+using qc::GraphDev;
+using qc::NodeJob;
+
+struct qc_graph_s {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t n_components = 0;
+    BfsPlan plan{};
+
+    // device CSR
+    int32_t *d_row_ptr = nullptr;
+    int32_t *d_col = nullptr;
+    uint32_t *d_edges = nullptr;
+
+    // distances and histograms
+    int8_t *d_dist_owned = nullptr;   // library-owned matrix (n*n, 16-byte padded)
+    int8_t *d_dist = nullptr;         // current resident matrix (owned or caller's)
+    int32_t *d_hist = nullptr;
+    int K = 0;
+    int32_t dmax = -1;
+    bool have_dist = false;
+
+    // potentials
+    int n_sigmas = 0;
+    int pot_cap = 0;                  // sigmas the buffers below hold
+    float *d_psi = nullptr, *d_v = nullptr;
+    double *d_v64 = nullptr;          // canonical FP64 V [S][n] (FP64ACC potentials)
+    int32_t *d_parent = nullptr;
+    double *d_w64 = nullptr, *d_u64 = nullptr, *d_inv_a = nullptr;
+    float *d_w32c = nullptr;
+    int w_cap = 0;                    // sigma*K entries the weight buffers hold
+    bool have_pot = false;
+    uint32_t pot_precision = 0;
+    std::vector<double> sigmas_loaded;  // sigma list whose tables are on the device
+
+    // status words, descriptor, job tables
+    int32_t *d_status = nullptr;              // [2]
+    unsigned long long *d_recheck = nullptr;  // [1]
+    GraphDev *d_desc = nullptr;
+    BfsJob *d_bfs_jobs = nullptr;
+    NodeJob *d_node_jobs = nullptr;           // kNodesPerJob nodes each
+    int n_node_jobs = 0;
+    NodeJob *d_hist_jobs = nullptr;           // hist_rows_per_job(K) rows each
+    int n_hist_jobs = 0;
+    int hist_jobs_k = 0;
+
+    GraphDev desc() const
+    {
+        GraphDev d;
+        memset(&d, 0, sizeof d);
+        d.n = n;
+        d.K = K;
+        d.dmax = dmax;
+        d.n_sigmas = n_sigmas;
+        d.nnz = nnz;
+        d.row_ptr = d_row_ptr;
+        d.col = d_col;
+        d.edges = d_edges;
+        d.dist = d_dist;
+        d.hist = d_hist;
+        d.psi = d_psi;
+        d.v = d_v;
+        d.v64 = (pot_precision == QC_PREC_FP64ACC) ? d_v64 : nullptr;
+        d.w64 = d_w64;
+        d.u64 = d_u64;
+        d.inv_a = d_inv_a;
+        d.w32c = d_w32c;
+        d.parent = d_parent;
+        d.status = d_status;
+        d.recheck = d_recheck;
+        return d;
+    }
+};
+
+
+namespace qc {
+
+qc_status from_hip(hipError_t e);
+
+#define QC_TRY(expr)                                  \
+    do {                                              \
+        qc_status _st = (expr);                       \
+        if (_st != QC_OK) return _st;                 \
+    } while (0)
+#define QC_HIP(expr) QC_TRY(from_hip(expr))
+
+template <class T>
+qc_status dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return e == hipErrorOutOfMemory ? QC_E_OOM : QC_E_DEVICE;
+    }
+    return QC_OK;
+}
+
+template <class T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+// Upload a small host array synchronously (set-up only, never in a timed path).
+template <class T>
+qc_status upload(T *dst, const std::vector<T> &src)
+{
+    if (src.empty()) return QC_OK;
+    return from_hip(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+inline hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+qc_status check_device(int *dev_out);
+qc_status push_desc(qc_graph g, hipStream_t st);
+qc_status ensure_hist_jobs(qc_graph g);
+qc_status set_plan(qc_graph g, const BfsPlan &p);
+qc_status run_distances(qc_graph g, hipStream_t st);
+qc_status ensure_sigma_buffers(qc_graph g, int S);
+// Load the weight tables of a sigma list into g (no-op if already loaded).
+qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStream_t st);
+void destroy(qc_graph g);
+
+}  // namespace qc

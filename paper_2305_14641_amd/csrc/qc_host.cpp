@@ -89,24 +89,36 @@ int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::v
     return comps;
 }
 
-BfsPlan plan_bfs(int32_t n)
+int planes_for(int32_t dmax)
+{
+    if (dmax >= 0 && dmax <= 15) return 4;
+    if (dmax >= 0 && dmax <= 31) return 5;
+    return 7;
+}
+
+BfsPlan plan_bfs(int32_t n, int32_t dmax)
 {
     static const int kAllowed[] = {1, 2, 4, 6, 8, 10, 12};
+    const int planes = planes_for(dmax);
+    // 7 planes leave registers for 10 words per thread, 4-5 planes for 12
+    const int max_nw = planes >= 7 ? 10 : 12;
     for (int bw : {64, 32, 16, 8, 4}) {
         const int64_t words = ((int64_t)n * bw + 31) / 32;  // 32-bit words of one bit field
         const int64_t need = (words + kBfsThreads - 1) / kBfsThreads;
         for (int nw : kAllowed) {
+            if (nw > max_nw) break;
             if (bw == 64 && (nw % 2)) continue;
             if (nw >= need) {
                 BfsPlan p;
                 p.bw = bw;
                 p.nw = nw;
+                p.planes = planes;
                 p.n_batches = (int)((n + bw - 1) / bw);
                 return p;
             }
         }
     }
-    BfsPlan none = {0, 0, 0};
+    BfsPlan none = {0, 0, 0, 0};
     return none;
 }
 

@@ -21,11 +21,14 @@ qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
 // Number of connected components (union-find over the canonical CSR).
 int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col);
 
-// BFS batch width (sources per workgroup) and 32-bit words per thread for a
-// graph of n nodes: the widest batch whose distance bytes fit the register
-// budget of one 1024-thread workgroup.
-struct BfsPlan { int bw; int nw; int n_batches; };
-BfsPlan plan_bfs(int32_t n);
+// BFS launch shape for a graph of n nodes whose largest finite distance is
+// dmax (or -1 while unknown): `planes` distance bit-planes (enough for dmax,
+// 7 when unknown), and the widest batch of sources whose three LDS bit
+// fields and register planes fit one 1024-thread workgroup, with nw 32-bit
+// words per thread per field.
+struct BfsPlan { int bw; int nw; int planes; int n_batches; };
+BfsPlan plan_bfs(int32_t n, int32_t dmax);
+int planes_for(int32_t dmax);
 
 // Histogram row length for a largest finite distance dmax.
 inline int bins_for(int dmax) { return dmax < 32 ? 32 : (dmax < 64 ? 64 : 128); }

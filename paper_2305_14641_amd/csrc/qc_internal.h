@@ -14,8 +14,14 @@ constexpr int kMaxDist = 126;
 constexpr int kMaxNodes = 65536;
 // Threads per workgroup of the multi-source BFS.
 constexpr int kBfsThreads = 1024;
-// 32-bit words of `seen` bits one BFS thread owns at most (see bfs_plan).
-constexpr int kBfsMaxWordsPerThread = 12;
+// 32-bit words of each LDS bit field one BFS thread owns at most (the three
+// fields of 13 x 1024 words fill 156 KB of the 160 KB LDS).
+constexpr int kBfsMaxWordsPerThread = 13;
+
+// Global-memory vector type for 16-byte loads through an explicit global
+// address-space pointer (keeps loads off the flat path).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 *global_u4;
 
 // Device-visible description of one graph and its resident buffers.
 // Kernels receive an array of these plus a job table, so one launch can
@@ -33,6 +39,7 @@ struct GraphDev {
     int32_t *hist;            // [n*K]
     float *psi;               // [n_sigmas*n] resident
     float *v;                 // [n_sigmas*n] resident
+    double *v64;              // [n_sigmas*n] canonical FP64 V, or null (FP32C potentials)
     const double *w64;        // [n_sigmas*K] exp(-k^2/a), host C library exp
     const double *u64;        // [n_sigmas*K] k^2 * w / a
     const double *inv_a;      // [n_sigmas] 1/a, a = (2 sigma) sigma
@@ -61,9 +68,14 @@ constexpr float kTieTau = 1.9073486328125e-06f;  // 2^-19
 hipError_t launch_set_desc(GraphDev *dst, const GraphDev &src, hipStream_t stream);
 
 // Multi-source BFS over `n_jobs` (graph, source-batch) jobs; every graph of the
-// launch must share the batch width `bw` and words-per-thread `nw`.
-hipError_t launch_bfs(int bw, int nw, const GraphDev *graphs, const BfsJob *jobs,
+// launch must share the batch width `bw`, words-per-thread `nw` and the
+// number of distance bit-planes `planes` (4, 5 or 7; levels < 2^planes).
+hipError_t launch_bfs(int bw, int nw, int planes, const GraphDev *graphs, const BfsJob *jobs,
                       int n_jobs, hipStream_t stream);
+// One batch width (qc_bfs_<bw>.hip).
+template <int BW>
+hipError_t launch_bfs_bw(int nw, int planes, const GraphDev *graphs, const BfsJob *jobs,
+                         int n_jobs, hipStream_t stream);
 
 // Histograms of the resident distance rows (one job = hist_rows_per_job(K)
 // rows of one graph). `K` is the shared bin count (32, 64 or 128).
@@ -85,6 +97,18 @@ hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob
 hipError_t launch_pointer_jump(const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
                                int sigma_base, int n_sig, int32_t *labels_base,
                                int64_t labels_ld, hipStream_t stream);
+
+// Stage timing (qc_timing.cpp): Timer brackets one launch when enabled.
+class StageTimer {
+  public:
+    StageTimer(int stage, hipStream_t stream);
+    ~StageTimer();
+  private:
+    int stage_;
+    hipStream_t stream_;
+    void *start_ = nullptr;
+    void *stop_ = nullptr;
+};
 
 // Fill kernel (used instead of hipMemsetAsync so work can be graph-captured).
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t stream);

@@ -10,215 +10,16 @@
 
 namespace qc {
 
-// ===========================================================================
-// Multi-source BFS.
-//
-// One workgroup owns a batch of BW consecutive sources s0..s0+BW-1 and runs
-// the level-synchronous search of all of them at once. LDS holds two bit
-// fields per node: `seen` (which sources have reached the node) and `nxt`
-// (which reach it at the current level). A level is:
-//   A. edge-parallel pull: for every edge (r, c), the sources that have seen c
-//      but not r reach r now:  nxt[r] |= seen[c] & ~seen[r]   (LDS atomic OR)
-//   B. word-owner update: every thread owns whole 32-bit words of the fields;
-//      it folds nxt into seen and records the level as the distance byte of
-//      each newly reached (node, source) pair.
-// Using `seen` rather than the previous frontier in A is exact: a source that
-// reached c at an earlier level would already have reached r.
-//
-// The distance bytes of every (owned node, batch source) pair live in
-// registers for the whole search (8 VGPRs per owned 32-bit word), so each
-// batch writes its BW output rows exactly once, when it is done. The graph is
-// undirected, so node v's distances to the batch sources are the entries
-// (s0+b, v) of the row-major matrix: rows s0..s0+BW-1 are this workgroup's.
-// ===========================================================================
-
-template <int BW> struct BfsWord {
-    using T = uint32_t;
-    static constexpr int kBits = 32;
-    static constexpr int kPer = 32 / BW;  // nodes per word
-};
-template <> struct BfsWord<64> {
-    using T = unsigned long long;
-    static constexpr int kBits = 64;
-    static constexpr int kPer = 1;
-};
-
-// 4-bit mask -> 4 bytes of 0xFF / 0x00 (bit i selects byte i).
-__device__ __forceinline__ uint32_t expand4(uint32_t m4)
-{
-    return ((m4 * 0x00204081u) & 0x01010101u) * 0xFFu;
-}
-
-template <int BW>
-__device__ __forceinline__ typename BfsWord<BW>::T field_of(const typename BfsWord<BW>::T *a, int v)
-{
-    using W = BfsWord<BW>;
-    if constexpr (BW >= 32) {
-        return a[v];
-    } else {
-        const uint32_t w = a[v / W::kPer];
-        return (w >> ((v % W::kPer) * BW)) & ((1u << BW) - 1u);
-    }
-}
-
-// Apply newly reached bits `y` of word j at `level`: each byte starts as 0xFF
-// (unreached) and is set exactly once, so XOR with (0xFF ^ level) writes level.
-template <int NREG>
-__device__ __forceinline__ void record_level(uint32_t (&d)[NREG], unsigned long long y, uint32_t kx)
-{
-#pragma unroll
-    for (int t = 0; t < NREG; ++t) {
-        const uint32_t m4 = (uint32_t)(y >> (4 * t)) & 0xFu;
-        if (m4) d[t] ^= expand4(m4) & kx;
-    }
-}
-
-template <int BW, int NW>
-__global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict__ graphs,
-                                                     const BfsJob *__restrict__ jobs)
-{
-    using W = BfsWord<BW>;
-    using T = typename W::T;
-    constexpr int NWW = (BW == 64) ? NW / 2 : NW;   // words of type T per thread
-    constexpr int NREG = W::kBits / 4;              // distance VGPRs per word
-    constexpr int kLdsWords = NWW * kBfsThreads;
-
-    __shared__ T seen[kLdsWords];
-    __shared__ T nxt[kLdsWords];
-
-    const BfsJob job = jobs[blockIdx.x];
-    const GraphDev &G = graphs[job.g];
-    const int n = G.n;
-    const int s0 = job.s0;
-    const int nb = min(BW, n - s0);
-    const int nwords = (n + W::kPer - 1) / W::kPer;
-    const int tid = threadIdx.x;
-    const int64_t nnz = G.nnz;
-    const uint32_t *__restrict__ edges = G.edges;
-
-    uint32_t dist[NWW][NREG];
-#pragma unroll
-    for (int j = 0; j < NWW; ++j)
-#pragma unroll
-        for (int t = 0; t < NREG; ++t) dist[j][t] = 0xFFFFFFFFu;
-
-    // Level 0: each source has reached itself.
-#pragma unroll
-    for (int j = 0; j < NWW; ++j) {
-        const int w = j * kBfsThreads + tid;
-        T bits = 0;
-        if (w < nwords) {
-#pragma unroll
-            for (int q = 0; q < W::kPer; ++q) {
-                const int b = w * W::kPer + q - s0;
-                if (b >= 0 && b < nb) bits |= (T)1 << (q * BW + b);
-            }
-        }
-        seen[w] = bits;
-        nxt[w] = 0;
-        record_level<NREG>(dist[j], (unsigned long long)bits, 0xFFFFFFFFu);
-    }
-    __syncthreads();
-
-    int last = 0;
-    bool overflow = false;
-    for (int level = 1;; ++level) {
-        // A. pull over every edge.
-        for (int64_t e = tid; e < nnz; e += kBfsThreads) {
-            const uint32_t rc = edges[e];
-            const int r = (int)(rc >> 16);
-            const int c = (int)(rc & 0xFFFFu);
-            const T x = field_of<BW>(seen, c);
-            if (x) {
-                const T y = x & ~field_of<BW>(seen, r);
-                if (y) atomicOr(&nxt[r / W::kPer], (T)(y << ((r % W::kPer) * BW)));
-            }
-        }
-        __syncthreads();
-        // B. fold the new bits of owned words into seen and the distance bytes.
-        int any = 0;
-        const uint32_t kx = (0xFFu ^ (uint32_t)level) * 0x01010101u;
-#pragma unroll
-        for (int j = 0; j < NWW; ++j) {
-            const int w = j * kBfsThreads + tid;
-            if (w < nwords) {
-                const T y = nxt[w];
-                if (y) {
-                    nxt[w] = 0;
-                    seen[w] |= y;
-                    any = 1;
-                    record_level<NREG>(dist[j], (unsigned long long)y, kx);
-                }
-            }
-        }
-        if (!__syncthreads_or(any)) break;
-        last = level;
-        if (level > kMaxDist) { overflow = true; break; }
-    }
-
-    // Rows s0..s0+nb-1, columns = owned nodes.
-    int8_t *__restrict__ out = G.dist;
-#pragma unroll
-    for (int j = 0; j < NWW; ++j) {
-        const int w = j * kBfsThreads + tid;
-        if (w < nwords) {
-#pragma unroll
-            for (int q = 0; q < W::kPer; ++q) {
-                const int v = w * W::kPer + q;
-                if (v < n) {
-#pragma unroll
-                    for (int b = 0; b < BW; ++b) {
-                        if (b < nb) {
-                            const int i = q * BW + b;
-                            const uint32_t byte = (dist[j][i / 4] >> (8 * (i % 4))) & 0xFFu;
-                            out[(int64_t)(s0 + b) * n + v] = (int8_t)byte;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    if (tid == 0) {
-        atomicMax(&G.status[0], last);
-        if (overflow) atomicOr(&G.status[1], 1);
-    }
-}
-
-template <int BW, int NW>
-static hipError_t launch_bfs_t(const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
-                               hipStream_t stream)
-{
-    hipLaunchKernelGGL((k_bfs<BW, NW>), dim3(n_jobs), dim3(kBfsThreads), 0, stream, graphs, jobs);
-    return hipGetLastError();
-}
-
-template <int BW>
-static hipError_t launch_bfs_bw(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
-                                hipStream_t stream)
-{
-    switch (nw) {
-    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1>(graphs, jobs, n_jobs, stream);
-            return hipErrorInvalidValue;
-    case 2: return launch_bfs_t<BW, 2>(graphs, jobs, n_jobs, stream);
-    case 4: return launch_bfs_t<BW, 4>(graphs, jobs, n_jobs, stream);
-    case 6: return launch_bfs_t<BW, 6>(graphs, jobs, n_jobs, stream);
-    case 8: return launch_bfs_t<BW, 8>(graphs, jobs, n_jobs, stream);
-    case 10: return launch_bfs_t<BW, 10>(graphs, jobs, n_jobs, stream);
-    case 12: return launch_bfs_t<BW, 12>(graphs, jobs, n_jobs, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_bfs(int bw, int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
-                      hipStream_t stream)
+hipError_t launch_bfs(int bw, int nw, int planes, const GraphDev *graphs, const BfsJob *jobs,
+                      int n_jobs, hipStream_t stream)
 {
     if (n_jobs <= 0) return hipSuccess;
     switch (bw) {
-    case 4: return launch_bfs_bw<4>(nw, graphs, jobs, n_jobs, stream);
-    case 8: return launch_bfs_bw<8>(nw, graphs, jobs, n_jobs, stream);
-    case 16: return launch_bfs_bw<16>(nw, graphs, jobs, n_jobs, stream);
-    case 32: return launch_bfs_bw<32>(nw, graphs, jobs, n_jobs, stream);
-    case 64: return launch_bfs_bw<64>(nw, graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_bw<4>(nw, planes, graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_bw<8>(nw, planes, graphs, jobs, n_jobs, stream);
+    case 16: return launch_bfs_bw<16>(nw, planes, graphs, jobs, n_jobs, stream);
+    case 32: return launch_bfs_bw<32>(nw, planes, graphs, jobs, n_jobs, stream);
+    case 64: return launch_bfs_bw<64>(nw, planes, graphs, jobs, n_jobs, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -252,10 +53,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
         const int64_t total = (int64_t)n * n;
         const int64_t r0 = (int64_t)row * n;
         const int64_t r1 = r0 + n;
-        for (int64_t c = (r0 & ~(int64_t)15) + lane * 16; c < r1; c += 64 * 16) {
+        const int64_t first = (r0 & ~(int64_t)15) + lane * 16;
+        // Whole 16-byte chunks inside the buffer come from one global load
+        // (the next one already in flight); the last partial chunk of the
+        // buffer is read byte by byte.
+        auto load = [&](int64_t c) -> u32x4 {
+            const u32x4 z = {0u, 0u, 0u, 0u};
+            if (c >= r1 || c + 16 > total) return z;
+            return *(global_u4)(base + c);
+        };
+        u32x4 cur = load(first);
+        for (int64_t c = first; c < r1; c += 64 * 16) {
+            const u32x4 ahead = load(c + 64 * 16);
             if (c + 16 <= total) {
-                const uint4 x = *reinterpret_cast<const uint4 *>(base + c);
-                const uint32_t wv[4] = {x.x, x.y, x.z, x.w};
+                const uint32_t wv[4] = {cur.x, cur.y, cur.z, cur.w};
                 const bool inside = (c >= r0) && (c + 16 <= r1);
 #pragma unroll
                 for (int p = 0; p < 16; ++p) {
@@ -273,6 +84,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
+            cur = ahead;
         }
     }
     __syncthreads();
@@ -302,13 +114,18 @@ hipError_t launch_hist(int K, const GraphDev *graphs, const NodeJob *jobs, int n
 
 // ===========================================================================
 // psi and V (Eq. 2; Algorithm 1 regrouped by distance value):
-//   psi_i = sum_k h[i][k] w_k,  V_i = sum_k h[i][k] u_k / psi_i,
-//   w_k = exp(-k^2 / (2 sigma^2)),  u_k = k^2 w_k / (2 sigma^2).
+//   psi_i = sum_k h[i][k] w_k,  V_i = (1/a) sum_k k^2 h[i][k] w_k / psi_i,
+//   w_k = exp(-k^2 / a),  a = 2 sigma^2.
 // One thread per node, all sigmas of the graph; the histogram row stays in
-// registers. FP64ACC: FP64 fused multiply-adds (the FP64 vector rate is half
-// the FP32 rate, and one FMA64 per term is far cheaper than a compensated
-// FP32 sum). FP32C: FP32 with error-free products (FMA) and TwoSum, weights
-// split as hi + lo FP32 pairs.
+// registers.
+// FP64ACC: the canonical FP64 evaluation — S2 = sum h_k*w_k and
+//   S1 = sum (k^2 h_k)*w_k in ascending k from +0.0, each product and sum
+//   rounded separately (no contraction), V = (1/a)*(S1/S2). psi and V are
+//   returned as the FP32 roundings of S2 and V; V itself stays resident in
+//   FP64 for the descent's near-tie decisions. These are the IEEE operations,
+//   in the same order, of the CPU oracle's canonical form.
+// FP32C: FP32 only, error-free products (FMA) and TwoSum accumulation, the
+//   weights split as hi + lo FP32 pairs.
 // ===========================================================================
 
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
@@ -316,6 +133,31 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
     s = a + b;
     const float z = s - a;
     e = (a - (s - z)) + (b - z);
+}
+
+template <int K>
+__device__ __forceinline__ void canonical_sums(const int32_t (&h)[K], int kmax,
+                                               const double *__restrict__ w, double &s2,
+                                               double &s1)
+{
+#pragma clang fp contract(off)
+    double a2 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k < kmax) {
+            const double hk = (double)h[k];
+            a2 = a2 + hk * w[k];
+            a1 = a1 + ((double)(k * k) * hk) * w[k];
+        }
+    }
+    s2 = a2;
+    s1 = a1;
+}
+
+__device__ __forceinline__ double canonical_ratio(double s1, double s2, double inv_a)
+{
+#pragma clang fp contract(off)
+    return inv_a * (s1 / s2);
 }
 
 template <int K, int PREC>
@@ -337,20 +179,14 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
 
     for (int s = 0; s < G.n_sigmas; ++s) {
         float psi32, v32;
+        const int64_t o = (int64_t)s * n + i;
         if constexpr (PREC == 0) {
-            const double *__restrict__ w = G.w64 + (int64_t)s * G.K;
-            const double *__restrict__ u = G.u64 + (int64_t)s * G.K;
-            double p = 0.0, q = 0.0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (k < kmax) {
-                    const double hk = (double)h[k];
-                    p = __fma_rn(hk, w[k], p);
-                    q = __fma_rn(hk, u[k], q);
-                }
-            }
-            psi32 = (float)p;
-            v32 = (float)(q / p);
+            double s2, s1;
+            canonical_sums<K>(h, kmax, G.w64 + (int64_t)s * G.K, s2, s1);
+            const double v64 = canonical_ratio(s1, s2, G.inv_a[s]);
+            psi32 = (float)s2;
+            v32 = (float)v64;
+            G.v64[o] = v64;
         } else {
             const float *__restrict__ wt = G.w32c + (int64_t)s * G.K * 4;
             float ps = 0.f, pe = 0.f, qs = 0.f, qe = 0.f;
@@ -360,7 +196,7 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
                     const float hk = (float)h[k];   // exact: counts < 2^24
                     const float whi = wt[4 * k + 0], wlo = wt[4 * k + 1];
                     const float uhi = wt[4 * k + 2], ulo = wt[4 * k + 3];
-                    // psi: TwoProduct(hk, whi) + hk*wlo, then TwoSum into (ps, pe)
+                    // TwoProduct(hk, hi) + hk*lo, then TwoSum into (sum, err)
                     float t = hk * whi;
                     float te = __fmaf_rn(hk, whi, -t) + hk * wlo;
                     float s1, e1;
@@ -379,7 +215,6 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
             psi32 = p;
             v32 = __fdiv_rn(q, p);
         }
-        const int64_t o = (int64_t)s * n + i;
         G.psi[o] = psi32;
         G.v[o] = v32;
         const int64_t ou = job.out_off + (int64_t)s * out_ld + i;
@@ -432,6 +267,7 @@ hipError_t launch_potential(int precision, int K, const GraphDev *graphs, const 
 // take identical decisions, exact ties included.
 // ===========================================================================
 
+// On-demand canonical FP64 V of one node (used when no FP64 table is resident).
 __device__ __noinline__ double canonical_v(const int32_t *__restrict__ h, int kmax,
                                            const double *__restrict__ w, double inv_a)
 {
@@ -443,6 +279,13 @@ __device__ __noinline__ double canonical_v(const int32_t *__restrict__ h, int km
         s1 = s1 + ((double)(k * k) * hk) * w[k];
     }
     return inv_a * (s1 / s2);
+}
+
+__device__ __forceinline__ double fp64_v(const GraphDev &G, int s, int node)
+{
+    if (G.v64) return G.v64[(int64_t)s * G.n + node];
+    return canonical_v(G.hist + (int64_t)node * G.K, G.dmax + 1, G.w64 + (int64_t)s * G.K,
+                       G.inv_a[s]);
 }
 
 __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev *__restrict__ graphs,
@@ -468,6 +311,7 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
         else if (vj < m2) m2 = vj;
     }
     int parent = i;
+    bool rechecked = false;
     if (j1 >= 0) {
         const float tau = kTieTau;
         bool ambiguous = (m2 - m1 <= tau * m2);
@@ -476,27 +320,27 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
         if (!ambiguous) {
             parent = (m1 < vi) ? j1 : i;
         } else {
-            const int K = G.K;
-            const int kmax = G.dmax + 1;
-            const double *__restrict__ w = G.w64 + (int64_t)s * K;
-            const double inv_a = G.inv_a[s];
-            const double vi64 = canonical_v(G.hist + (int64_t)i * K, kmax, w, inv_a);
+            const double vi64 = fp64_v(G, s, i);
             double bv = DBL_MAX;
             int best = -1;
             for (int e = e0; e < e1; ++e) {
                 const int j = col[e];
                 const float vj = V[j];
                 if (vj - m1 <= tau * vj) {
-                    const double d = canonical_v(G.hist + (int64_t)j * K, kmax, w, inv_a);
+                    const double d = fp64_v(G, s, j);
                     if (d < bv) { bv = d; best = j; }
                 }
             }
             if (tie_mode == 0) parent = (bv < vi64) ? best : i;
             else parent = (bv < vi64 || (bv == vi64 && best < i)) ? best : i;
-            atomicAdd(G.recheck, 1ull);
+            rechecked = true;
         }
     }
     G.parent[(int64_t)s * n + i] = parent;
+    // one counter update per wavefront
+    const unsigned long long m = __ballot(rechecked);
+    if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1))
+        atomicAdd(G.recheck, (unsigned long long)__popcll(m));
 }
 
 hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob *jobs,

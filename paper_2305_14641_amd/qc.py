@@ -37,8 +37,21 @@ GRAPH_CANONICALIZE = 1
 EXPORTED = [
     "qc_status_str", "qc_device_count", "qc_graph_create", "qc_graph_destroy",
     "qc_graph_info", "qc_distances", "qc_get_histograms", "qc_potential",
-    "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync",
+    "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync", "qc_timing_enable",
+    "qc_timing_read",
+    "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
+    "qc_batch_destroy",
 ]
+
+BATCH_HIPGRAPH = 1
+BATCH_FP32C = 2
+
+STAGE_BFS = 0
+STAGE_HIST = 1
+STAGE_POTENTIAL = 2
+STAGE_GGD = 3
+STAGE_JUMP = 4
+STAGE_NAMES = ["bfs", "hist", "potential", "ggd_parent", "pointer_jump"]
 
 
 class QCError(RuntimeError):
@@ -75,6 +88,13 @@ def lib():
         L.qc_ggd_labels.argtypes = [P, I32, U32, P, P]
         L.qc_last_recheck_count.argtypes = [P, P]
         L.qc_graph_sync.argtypes = [P, P]
+        L.qc_timing_enable.argtypes = [I32]
+        L.qc_timing_read.argtypes = [I32, P, P]
+        L.qc_batch_create.argtypes = [P, I32, P, I32, U32, U32, P, P]
+        L.qc_batch_node_offsets.argtypes = [P, P]
+        L.qc_batch_run.argtypes = [P, P, P, P, P]
+        L.qc_batch_recheck_count.argtypes = [P, P]
+        L.qc_batch_destroy.argtypes = [P]
         for name in EXPORTED[1:]:
             getattr(L, name).restype = I32
         _lib = L
@@ -94,6 +114,19 @@ def device_count() -> int:
     c = ctypes.c_int32(0)
     _check(lib().qc_device_count(ctypes.byref(c)), "qc_device_count")
     return int(c.value)
+
+
+def timing_enable(on: bool = True):
+    """Bracket every kernel launch with HIP events (on its own stream)."""
+    _check(lib().qc_timing_enable(1 if on else 0), "qc_timing_enable")
+
+
+def timing_read(stage: int) -> tuple:
+    """(summed device milliseconds, launch count) of one stage."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().qc_timing_read(int(stage), ctypes.byref(ms), ctypes.byref(cnt)), "qc_timing_read")
+    return float(ms.value), int(cnt.value)
 
 
 def _stream_ptr(stream=None):
@@ -214,6 +247,56 @@ class Graph:
         want = getattr(torch, dtype)
         if not t.is_cuda or t.dtype != want or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
             raise ValueError(f"expected a contiguous CUDA {dtype} tensor of shape {shape}")
+
+
+class Batch:
+    """Many graphs x one sigma list in grouped launches (include/qc_batch.h)."""
+
+    def __init__(self, graphs, sigmas, tie_mode=TIE_STRICT, hipgraph=True, fp32c=False,
+                 stream=None):
+        self.graphs = list(graphs)          # keeps the Graph handles alive
+        arr = (ctypes.c_void_p * len(self.graphs))(*[G.handle.value for G in self.graphs])
+        sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).reshape(-1))
+        flags = (BATCH_HIPGRAPH if hipgraph else 0) | (BATCH_FP32C if fp32c else 0)
+        h = ctypes.c_void_p()
+        _check(lib().qc_batch_create(arr, len(self.graphs), sig.ctypes.data_as(ctypes.c_void_p),
+                                     sig.shape[0], int(tie_mode), flags, _stream_ptr(stream),
+                                     ctypes.byref(h)), "qc_batch_create")
+        self._h = h
+        self.sigmas = sig
+        off = np.zeros(len(self.graphs) + 1, dtype=np.int64)
+        _check(lib().qc_batch_node_offsets(h, off.ctypes.data_as(ctypes.c_void_p)),
+               "qc_batch_node_offsets")
+        self.offsets = off
+        self.total = int(off[-1])
+
+    def outputs(self):
+        import torch
+        S = self.sigmas.shape[0]
+        psi = torch.empty((S, self.total), dtype=torch.float32, device="cuda")
+        v = torch.empty((S, self.total), dtype=torch.float32, device="cuda")
+        lab = torch.empty((S, self.total), dtype=torch.int32, device="cuda")
+        return psi, v, lab
+
+    def run(self, psi, v, labels, stream=None):
+        _check(lib().qc_batch_run(self._h, _dptr(psi), _dptr(v), _dptr(labels),
+                                  _stream_ptr(stream)), "qc_batch_run")
+
+    def recheck_count(self) -> int:
+        c = ctypes.c_int64(0)
+        _check(lib().qc_batch_recheck_count(self._h, ctypes.byref(c)), "qc_batch_recheck_count")
+        return int(c.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().qc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cluster(g, sigmas, tie_mode=TIE_STRICT, precision=PREC_FP64ACC, dist_out=None):

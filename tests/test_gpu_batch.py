@@ -1,0 +1,89 @@
+"""The batched form (include/qc_batch.h) against the plain per-graph calls and
+the oracle: bitwise-identical outputs, HIP-graph replays identical to eager
+runs, and oracle parity on a subset of the batched sigma-sweep graphs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_14641_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_2305_14641_amd import qc
+    assert torch.cuda.is_available()
+    # a spread of sizes from the sweep's draw (every BFS width class appears)
+    idx = [0, 3, 7, 12, 20, 33, 41, 50, 58, 63]
+    graphs = [gg.config4_graph(i) for i in idx] + [gg.path_graph(1), gg.star_graph(30)]
+    sigmas = gg.sigmas_c4()[::4]
+    print(f"[gpu] batch of {len(graphs)} graphs, n={[g.n for g in graphs]}", flush=True)
+    return torch, qc, graphs, sigmas
+
+
+@pytest.mark.parametrize("tie", [0, 1])
+def test_batch_equals_plain_and_oracle(setup, tie):
+    torch, qc, graphs, sigmas = setup
+    handles = [qc.Graph.from_graph(g) for g in graphs]
+    b = qc.Batch(handles, sigmas, tie_mode=tie, hipgraph=True)
+    psi, v, lab = b.outputs()
+    runs = []
+    for r in range(3):      # capture, then replays with eager work in between
+        b.run(psi, v, lab)
+        torch.cuda.synchronize()
+        runs.append((psi.cpu().numpy().copy(), v.cpu().numpy().copy(), lab.cpu().numpy().copy()))
+        _ = torch.ones(1000, device="cuda").sum().item()
+    for r in runs[1:]:
+        for a, c in zip(runs[0], r):
+            assert a.tobytes() == c.tobytes()
+    psi_b, v_b, lab_b = runs[0]
+    for i, (g, G) in enumerate(zip(graphs, handles)):
+        o0, o1 = b.offsets[i], b.offsets[i + 1]
+        p_, v_ = G.potential(sigmas)
+        assert p_.cpu().numpy().tobytes() == np.ascontiguousarray(psi_b[:, o0:o1]).tobytes()
+        assert v_.cpu().numpy().tobytes() == np.ascontiguousarray(v_b[:, o0:o1]).tobytes()
+        for s in range(len(sigmas)):
+            l_ = G.labels(s, tie).cpu().numpy()
+            np.testing.assert_array_equal(l_, lab_b[s, o0:o1])
+    # oracle parity on the graphs small enough for a quick full check
+    for i, g in enumerate(graphs):
+        if g.n > 6000:
+            continue
+        o0, o1 = b.offsets[i], b.offsets[i + 1]
+        dist, dmax = oracle.distances(g.n, g.row_ptr, g.col)
+        hist = oracle.hist_rows(dist, dmax + 1)
+        for s, sigma in enumerate(sigmas):
+            psi_c, v_c = oracle.potential_canonical(hist, sigma)
+            np.testing.assert_allclose(psi_b[s, o0:o1], psi_c, rtol=1e-6, atol=0)
+            np.testing.assert_allclose(v_b[s, o0:o1], v_c, rtol=1e-6, atol=0)
+            lab_ref = oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v_c, tie))
+            np.testing.assert_array_equal(lab_b[s, o0:o1], lab_ref)
+    b.close()
+
+
+def test_batch_without_hipgraph_and_fp32c(setup):
+    torch, qc, graphs, sigmas = setup
+    handles = [qc.Graph.from_graph(g) for g in graphs[:5]]
+    b1 = qc.Batch(handles, sigmas, hipgraph=False)
+    o1 = b1.outputs()
+    b1.run(*o1)
+    b2 = qc.Batch(handles, sigmas, hipgraph=False, fp32c=True)
+    o2 = b2.outputs()
+    b2.run(*o2)
+    torch.cuda.synchronize()
+    # FP32C and FP64ACC agree to the FP32 bound and give identical labels
+    np.testing.assert_allclose(o2[1].cpu().numpy(), o1[1].cpu().numpy(), rtol=2e-6)
+    np.testing.assert_array_equal(o2[2].cpu().numpy(), o1[2].cpu().numpy())
+
+
+def test_batch_rejects_bad_arguments(setup):
+    torch, qc, graphs, sigmas = setup
+    G = qc.Graph.from_graph(graphs[-1])
+    with pytest.raises(qc.QCError):
+        qc.Batch([G, G], sigmas)          # a graph twice
+    with pytest.raises(qc.QCError):
+        qc.Batch([G], [1.0, -2.0])
+    with pytest.raises(qc.QCError):
+        qc.Batch([G], sigmas, tie_mode=3)
