@@ -53,8 +53,8 @@ qc_status set_plan(qc_graph g, const BfsPlan &p)
     }
     std::vector<BfsJob> jobs(p.n_batches);
     for (int b = 0; b < p.n_batches; ++b) jobs[b] = BfsJob{0, b * p.bw};
-    dfree(g->d_bfs_jobs);
-    QC_TRY(dalloc(&g->d_bfs_jobs, jobs.size()));
+    gfree(g, g->d_bfs_jobs);
+    QC_TRY(galloc(g, &g->d_bfs_jobs, jobs.size()));
     QC_TRY(upload(g->d_bfs_jobs, jobs));
     g->plan = p;
     return QC_OK;
@@ -63,11 +63,11 @@ qc_status set_plan(qc_graph g, const BfsPlan &p)
 qc_status ensure_hist_jobs(qc_graph g)
 {
     if (g->d_hist_jobs && g->hist_jobs_k == g->K) return QC_OK;
-    dfree(g->d_hist_jobs);
+    gfree(g, g->d_hist_jobs);
     const int rows = hist_rows_per_job(g->K);
     std::vector<NodeJob> jobs;
     for (int i = 0; i < g->n; i += rows) jobs.push_back(NodeJob{0, i, 0});
-    QC_TRY(dalloc(&g->d_hist_jobs, jobs.size()));
+    QC_TRY(galloc(g, &g->d_hist_jobs, jobs.size()));
     QC_TRY(upload(g->d_hist_jobs, jobs));
     g->n_hist_jobs = (int)jobs.size();
     g->hist_jobs_k = g->K;
@@ -81,8 +81,8 @@ qc_status run_distances(qc_graph g, hipStream_t st)
     QC_TRY(push_desc(g, st));
     {
         StageTimer t(QC_STAGE_BFS, st);
-        QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->plan.planes, g->d_desc, g->d_bfs_jobs,
-                          g->plan.n_batches, st));
+        QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->plan.planes, g->plan.wide, g->d_desc,
+                          g->d_bfs_jobs, g->plan.n_batches, st));
     }
     if (g->dmax < 0) {
         int32_t status[2];
@@ -94,8 +94,8 @@ qc_status run_distances(qc_graph g, hipStream_t st)
         g->K = bins_for(g->dmax);
         // later runs need only enough planes for dmax: maybe a wider batch
         QC_TRY(set_plan(g, plan_bfs(g->n, g->dmax)));
-        dfree(g->d_hist);
-        QC_TRY(dalloc(&g->d_hist, (size_t)g->n * g->K));
+        gfree(g, g->d_hist);
+        QC_TRY(galloc(g, &g->d_hist, (size_t)g->n * g->K));
         QC_TRY(ensure_hist_jobs(g));
         QC_TRY(push_desc(g, st));
     }
@@ -110,25 +110,25 @@ qc_status run_distances(qc_graph g, hipStream_t st)
 qc_status ensure_sigma_buffers(qc_graph g, int S)
 {
     if (S > g->pot_cap) {
-        dfree(g->d_psi);
-        dfree(g->d_v);
-        dfree(g->d_v64);
-        dfree(g->d_parent);
-        QC_TRY(dalloc(&g->d_psi, (size_t)S * g->n));
-        QC_TRY(dalloc(&g->d_v, (size_t)S * g->n));
-        QC_TRY(dalloc(&g->d_v64, (size_t)S * g->n));
-        QC_TRY(dalloc(&g->d_parent, (size_t)S * g->n));
+        gfree(g, g->d_psi);
+        gfree(g, g->d_v);
+        gfree(g, g->d_v64);
+        gfree(g, g->d_parent);
+        QC_TRY(galloc(g, &g->d_psi, (size_t)S * g->n));
+        QC_TRY(galloc(g, &g->d_v, (size_t)S * g->n));
+        QC_TRY(galloc(g, &g->d_v64, (size_t)S * g->n));
+        QC_TRY(galloc(g, &g->d_parent, (size_t)S * g->n));
         g->pot_cap = S;
     }
     if (S * g->K > g->w_cap) {
-        dfree(g->d_w64);
-        dfree(g->d_u64);
-        dfree(g->d_inv_a);
-        dfree(g->d_w32c);
-        QC_TRY(dalloc(&g->d_w64, (size_t)S * g->K));
-        QC_TRY(dalloc(&g->d_u64, (size_t)S * g->K));
-        QC_TRY(dalloc(&g->d_inv_a, (size_t)S));
-        QC_TRY(dalloc(&g->d_w32c, (size_t)S * g->K * 4));
+        gfree(g, g->d_w64);
+        gfree(g, g->d_u64);
+        gfree(g, g->d_inv_a);
+        gfree(g, g->d_w32c);
+        QC_TRY(galloc(g, &g->d_w64, (size_t)S * g->K));
+        QC_TRY(galloc(g, &g->d_u64, (size_t)S * g->K));
+        QC_TRY(galloc(g, &g->d_inv_a, (size_t)S));
+        QC_TRY(galloc(g, &g->d_w32c, (size_t)S * g->K * 4));
         g->w_cap = S * g->K;
     }
     return QC_OK;
@@ -156,29 +156,29 @@ qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStr
     return QC_OK;
 }
 
-void destroy(qc_graph g)
+void destroy(qc_graph g, bool sync)
 {
     if (!g) return;
-    (void)hipDeviceSynchronize();
-    dfree(g->d_row_ptr);
-    dfree(g->d_col);
-    dfree(g->d_edges);
-    dfree(g->d_dist_owned);
-    dfree(g->d_hist);
-    dfree(g->d_psi);
-    dfree(g->d_v);
-    dfree(g->d_v64);
-    dfree(g->d_parent);
-    dfree(g->d_w64);
-    dfree(g->d_u64);
-    dfree(g->d_inv_a);
-    dfree(g->d_w32c);
-    dfree(g->d_status);
-    dfree(g->d_recheck);
-    dfree(g->d_desc);
-    dfree(g->d_bfs_jobs);
-    dfree(g->d_node_jobs);
-    dfree(g->d_hist_jobs);
+    if (sync) (void)hipDeviceSynchronize();
+    gfree(g, g->d_row_ptr);
+    gfree(g, g->d_col);
+    gfree(g, g->d_edges);
+    gfree(g, g->d_dist_owned);
+    gfree(g, g->d_hist);
+    gfree(g, g->d_psi);
+    gfree(g, g->d_v);
+    gfree(g, g->d_v64);
+    gfree(g, g->d_parent);
+    gfree(g, g->d_w64);
+    gfree(g, g->d_u64);
+    gfree(g, g->d_inv_a);
+    gfree(g, g->d_w32c);
+    gfree(g, g->d_status);
+    gfree(g, g->d_recheck);
+    gfree(g, g->d_desc);
+    gfree(g, g->d_bfs_jobs);
+    gfree(g, g->d_node_jobs);
+    gfree(g, g->d_hist_jobs);
     delete g;
 }
 
@@ -224,6 +224,17 @@ qc_status qc_device_count(int32_t *count_out)
 qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                           uint32_t flags, void *stream, qc_graph *out)
 {
+    return create_graph(n, nnz, row_ptr, col_idx, flags, as_stream(stream), nullptr, 0, out);
+}
+
+}  // extern "C"
+
+namespace qc {
+
+qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                       uint32_t flags, hipStream_t st, char *region, size_t region_bytes,
+                       qc_graph *out)
+{
     if (!out) return QC_E_INVAL;
     if (flags & ~(uint32_t)QC_GRAPH_CANONICALIZE) return QC_E_INVAL;
     std::vector<int32_t> rp, col;
@@ -233,10 +244,11 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
 
     qc_graph g = new qc_graph_s();
     g->device = dev;
+    g->bump_base = region;
+    g->bump_size = region_bytes;
     g->n = n;
     g->nnz = (int64_t)col.size();
     g->n_components = count_components(n, rp, col);
-    hipStream_t st = as_stream(stream);
 
     // packed edges, padded with no-op (0, 0) entries to a multiple of 4
     std::vector<uint32_t> edges(((g->nnz + 3) / 4) * 4 + 4, 0u);
@@ -248,11 +260,11 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
     g->n_node_jobs = (int)njobs.size();
 
     qc_status st_ = QC_OK;
-    auto fail = [&](qc_status s) { destroy(g); return s; };
-    if ((st_ = dalloc(&g->d_row_ptr, rp.size())) || (st_ = dalloc(&g->d_col, col.size())) ||
-        (st_ = dalloc(&g->d_edges, edges.size())) || (st_ = dalloc(&g->d_status, 2)) ||
-        (st_ = dalloc(&g->d_recheck, 1)) || (st_ = dalloc(&g->d_desc, 1)) ||
-        (st_ = dalloc(&g->d_node_jobs, njobs.size())))
+    auto fail = [&](qc_status s) { destroy(g, region == nullptr); return s; };
+    if ((st_ = galloc(g, &g->d_row_ptr, rp.size())) || (st_ = galloc(g, &g->d_col, col.size())) ||
+        (st_ = galloc(g, &g->d_edges, edges.size())) || (st_ = galloc(g, &g->d_status, 2)) ||
+        (st_ = galloc(g, &g->d_recheck, 1)) || (st_ = galloc(g, &g->d_desc, 1)) ||
+        (st_ = galloc(g, &g->d_node_jobs, njobs.size())))
         return fail(st_);
     if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
         (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
@@ -263,6 +275,10 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
     *out = g;
     return QC_OK;
 }
+
+}  // namespace qc
+
+extern "C" {
 
 qc_status qc_graph_destroy(qc_graph g)
 {
@@ -289,7 +305,7 @@ qc_status qc_distances(qc_graph g, int8_t *dist_out, int32_t *dmax_out, void *st
         if (((uintptr_t)dist_out) % 16) return QC_E_INVAL;  // rows are read in 16-byte chunks
         g->d_dist = dist_out;
     } else {
-        if (!g->d_dist_owned) QC_TRY(dalloc(&g->d_dist_owned, (size_t)g->n * g->n + 16));
+        if (!g->d_dist_owned) QC_TRY(galloc(g, &g->d_dist_owned, (size_t)g->n * g->n + 16));
         g->d_dist = g->d_dist_owned;
     }
     QC_TRY(run_distances(g, st));

@@ -101,19 +101,30 @@ __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
     pull_row<BW>((int)(e[7] >> 16), acc, seen, nxt);
 }
 
-template <int BW, int NW, int P>
-__global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict__ graphs,
-                                                     const BfsJob *__restrict__ jobs)
+// WIDE = false: 1024 threads, three fields (pull from `front`).
+// WIDE = true : 512 threads, two fields (pull from `seen`, which is also
+//   exact: a source that reached c before the previous level has already
+//   reached r), so twice the words fit the LDS and each thread has 256
+//   registers for its planes: twice the sources per batch on mid-size graphs.
+template <bool WIDE> struct BfsShape {
+    static constexpr int kThreads = WIDE ? kBfsThreadsWide : kBfsThreads;
+};
+
+template <int BW, int NW, int P, bool WIDE>
+__global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev *__restrict__ graphs,
+                                                                  const BfsJob *__restrict__ jobs)
 {
     using W = BfsWord<BW>;
     using T = typename W::T;
+    constexpr int kT = BfsShape<WIDE>::kThreads;
     constexpr int NWW = (BW == 64) ? NW / 2 : NW;   // words of type T per thread
-    constexpr int kLdsWords = NWW * kBfsThreads;
+    constexpr int kLdsWords = NWW * kT;
     constexpr int kLevels = (P >= 7) ? kMaxDist : ((1 << P) - 1);  // largest encodable level
 
     __shared__ T seen[kLdsWords];
-    __shared__ T front[kLdsWords];
     __shared__ T nxt[kLdsWords];
+    __shared__ T front_store[WIDE ? 1 : kLdsWords];
+    T *const front = WIDE ? seen : front_store;
 
     const BfsJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
@@ -134,7 +145,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict_
     // Level 0: each source has reached itself (distance 0: no plane bits).
 #pragma unroll
     for (int j = 0; j < NWW; ++j) {
-        const int w = j * kBfsThreads + tid;
+        const int w = j * kT + tid;
         T bits = 0;
         if (w < nwords) {
 #pragma unroll
@@ -144,7 +155,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict_
             }
         }
         seen[w] = bits;
-        front[w] = bits;
+        if constexpr (!WIDE) front[w] = bits;
         nxt[w] = 0;
     }
     __syncthreads();
@@ -157,8 +168,8 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict_
         int q = 2 * tid;
         u32x4 ca = (q < nquads) ? quads[q] : zero4;
         u32x4 cb = (q + 1 < nquads) ? quads[q + 1] : zero4;
-        for (; q < nquads; q += 2 * kBfsThreads) {
-            const int qn = q + 2 * kBfsThreads;
+        for (; q < nquads; q += 2 * kT) {
+            const int qn = q + 2 * kT;
             const u32x4 na = (qn < nquads) ? quads[qn] : zero4;
             const u32x4 nb4 = (qn + 1 < nquads) ? quads[qn + 1] : zero4;
             pull_oct<BW>(ca, cb, front, seen, nxt);
@@ -170,10 +181,10 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict_
         int any = 0;
 #pragma unroll
         for (int j = 0; j < NWW; ++j) {
-            const int w = j * kBfsThreads + tid;
+            const int w = j * kT + tid;
             if (w < nwords) {
                 const T y = nxt[w];
-                front[w] = y;
+                if constexpr (!WIDE) front[w] = y;
                 if (y) {
                     nxt[w] = 0;
                     seen[w] |= y;
@@ -195,18 +206,23 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict_
 
     // Decode the planes of every owned word into distance bytes and write
     // rows s0..s0+nb-1, columns = owned nodes. Unreached pairs get -1 (0xFF).
+    // Only the loop over words is unrolled (so the planes keep static register
+    // indices); the loop over the word's dwords shifts by a variable amount.
     int8_t *__restrict__ out = G.dist;
 #pragma unroll
     for (int j = 0; j < NWW; ++j) {
-        const int w = j * kBfsThreads + tid;
+        const int w = j * kT + tid;
         if (w < nwords) {
             const T sw = seen[w];
+            T lp[P];
 #pragma unroll
+            for (int p = 0; p < P; ++p) lp[p] = plane[j][p];
+#pragma unroll 1
             for (int t = 0; t < W::kBits / 4; ++t) {
                 // pairs 4t..4t+3 of the word -> one dword of 4 distance bytes
                 uint32_t d = spread4((uint32_t)(~sw >> (4 * t)) & 0xFu) * 0xFFu;
 #pragma unroll
-                for (int p = 0; p < P; ++p) d |= spread4((uint32_t)(plane[j][p] >> (4 * t)) & 0xFu) << p;
+                for (int p = 0; p < P; ++p) d |= spread4((uint32_t)(lp[p] >> (4 * t)) & 0xFu) << p;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int i = 4 * t + k;       // pair index in the word
@@ -225,10 +241,11 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs(const GraphDev *__restrict_
     }
 }
 
-template <int BW, int NW, int P>
+template <int BW, int NW, int P, bool WIDE>
 hipError_t launch_bfs_t(const GraphDev *graphs, const BfsJob *jobs, int n_jobs, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_bfs<BW, NW, P>), dim3(n_jobs), dim3(kBfsThreads), 0, stream, graphs, jobs);
+    hipLaunchKernelGGL((k_bfs<BW, NW, P, WIDE>), dim3(n_jobs), dim3(BfsShape<WIDE>::kThreads), 0,
+                       stream, graphs, jobs);
     return hipGetLastError();
 }
 
@@ -237,23 +254,52 @@ hipError_t launch_bfs_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int 
                         hipStream_t stream)
 {
     switch (nw) {
-    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1, P>(graphs, jobs, n_jobs, stream);
+    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1, P, false>(graphs, jobs, n_jobs, stream);
             return hipErrorInvalidValue;
-    case 2: return launch_bfs_t<BW, 2, P>(graphs, jobs, n_jobs, stream);
-    case 4: return launch_bfs_t<BW, 4, P>(graphs, jobs, n_jobs, stream);
-    case 6: return launch_bfs_t<BW, 6, P>(graphs, jobs, n_jobs, stream);
-    case 8: return launch_bfs_t<BW, 8, P>(graphs, jobs, n_jobs, stream);
-    case 10: return launch_bfs_t<BW, 10, P>(graphs, jobs, n_jobs, stream);
-    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P>(graphs, jobs, n_jobs, stream);
+    case 2: return launch_bfs_t<BW, 2, P, false>(graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_t<BW, 4, P, false>(graphs, jobs, n_jobs, stream);
+    case 6: return launch_bfs_t<BW, 6, P, false>(graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_t<BW, 8, P, false>(graphs, jobs, n_jobs, stream);
+    case 10: return launch_bfs_t<BW, 10, P, false>(graphs, jobs, n_jobs, stream);
+    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P, false>(graphs, jobs, n_jobs, stream);
              return hipErrorInvalidValue;  // 7 planes x 12 words exceed the registers
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int BW>
-hipError_t launch_bfs_bw(int nw, int planes, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
-                         hipStream_t stream)
+// Two-field, 512-thread shapes (planes 4 or 5 only).
+template <int BW, int P>
+hipError_t launch_bfs_wide_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                             hipStream_t stream)
 {
+    if constexpr (P >= 7 || BW < 8) {
+        return hipErrorInvalidValue;
+    } else {
+        switch (nw) {
+        case 16: return launch_bfs_t<BW, 16, P, true>(graphs, jobs, n_jobs, stream);
+        case 24: return launch_bfs_t<BW, 24, P, true>(graphs, jobs, n_jobs, stream);
+        case 32: return launch_bfs_t<BW, 32, P, true>(graphs, jobs, n_jobs, stream);
+        case 38: if constexpr (P == 4) return launch_bfs_t<BW, 38, P, true>(graphs, jobs, n_jobs, stream);
+                 return hipErrorInvalidValue;  // 5 planes x 38 words exceed the registers
+        case 39: if constexpr (P == 4 && BW != 64)
+                     return launch_bfs_t<BW, 39, P, true>(graphs, jobs, n_jobs, stream);
+                 return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+template <int BW>
+hipError_t launch_bfs_bw(int nw, int planes, bool wide, const GraphDev *graphs, const BfsJob *jobs,
+                         int n_jobs, hipStream_t stream)
+{
+    if (wide) {
+        switch (planes) {
+        case 4: return launch_bfs_wide_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
+        case 5: return launch_bfs_wide_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (planes) {
     case 4: return launch_bfs_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
     case 5: return launch_bfs_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);

@@ -17,6 +17,10 @@ using qc::NodeJob;
 
 struct qc_graph_s {
     int device = 0;
+    // When set, every device buffer of the handle is carved from this region
+    // (a serving request's slice of the server arena) instead of hipMalloc.
+    char *bump_base = nullptr;
+    size_t bump_size = 0, bump_off = 0;
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t n_components = 0;
@@ -120,6 +124,28 @@ void dfree(T *&p)
     p = nullptr;
 }
 
+// Device buffer of a graph handle: from its arena region when it has one.
+template <class T>
+qc_status galloc(qc_graph g, T **p, size_t count)
+{
+    if (!g->bump_base) return dalloc(p, count);
+    const size_t bytes = (((count ? count : 1) * sizeof(T)) + 255) & ~(size_t)255;
+    if (g->bump_off + bytes > g->bump_size) {
+        *p = nullptr;
+        return QC_E_OOM;
+    }
+    *p = (T *)(g->bump_base + g->bump_off);
+    g->bump_off += bytes;
+    return QC_OK;
+}
+
+template <class T>
+void gfree(qc_graph g, T *&p)
+{
+    if (!g->bump_base) dfree(p);
+    p = nullptr;
+}
+
 // Upload a small host array synchronously (set-up only, never in a timed path).
 template <class T>
 qc_status upload(T *dst, const std::vector<T> &src)
@@ -138,6 +164,12 @@ qc_status run_distances(qc_graph g, hipStream_t st);
 qc_status ensure_sigma_buffers(qc_graph g, int S);
 // Load the weight tables of a sigma list into g (no-op if already loaded).
 qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStream_t st);
-void destroy(qc_graph g);
+// Release a handle; `sync` waits for the whole device first (handles that
+// live in an arena region are released after their own stream has drained).
+void destroy(qc_graph g, bool sync = true);
+// qc_graph_create with an optional arena region for every device buffer.
+qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                       uint32_t flags, hipStream_t stream, char *region, size_t region_bytes,
+                       qc_graph *out);
 
 }  // namespace qc

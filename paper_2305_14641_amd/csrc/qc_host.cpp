@@ -96,16 +96,25 @@ int planes_for(int32_t dmax)
     return 7;
 }
 
-BfsPlan plan_bfs(int32_t n, int32_t dmax)
+BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, bool wide)
 {
-    static const int kAllowed[] = {1, 2, 4, 6, 8, 10, 12};
+    static const int kNarrow[] = {1, 2, 4, 6, 8, 10, 12};
+    static const int kWide[] = {16, 24, 32, 38, 39};
     const int planes = planes_for(dmax);
-    // 7 planes leave registers for 10 words per thread, 4-5 planes for 12
-    const int max_nw = planes >= 7 ? 10 : 12;
+    BfsPlan none = {0, 0, planes, 0, wide};
+    if (wide && planes >= 7) return none;
+    const int threads = wide ? kBfsThreadsWide : kBfsThreads;
+    // registers (no spills): three-field shape 10 words per thread with 7
+    // planes, 12 with 4-5; two-field shape 39 words with 4 planes, 32 with 5
+    const int max_nw = wide ? (planes <= 4 ? 39 : 32) : (planes >= 7 ? 10 : 12);
     for (int bw : {64, 32, 16, 8, 4}) {
+        if (wide && bw < 8) continue;
         const int64_t words = ((int64_t)n * bw + 31) / 32;  // 32-bit words of one bit field
-        const int64_t need = (words + kBfsThreads - 1) / kBfsThreads;
-        for (int nw : kAllowed) {
+        const int64_t need = (words + threads - 1) / threads;
+        const int *opts = wide ? kWide : kNarrow;
+        const int nopts = wide ? 5 : 7;
+        for (int k = 0; k < nopts; ++k) {
+            const int nw = opts[k];
             if (nw > max_nw) break;
             if (bw == 64 && (nw % 2)) continue;
             if (nw >= need) {
@@ -114,12 +123,19 @@ BfsPlan plan_bfs(int32_t n, int32_t dmax)
                 p.nw = nw;
                 p.planes = planes;
                 p.n_batches = (int)((n + bw - 1) / bw);
+                p.wide = wide;
                 return p;
             }
         }
     }
-    BfsPlan none = {0, 0, 0, 0};
     return none;
+}
+
+BfsPlan plan_bfs(int32_t n, int32_t dmax)
+{
+    const BfsPlan narrow = plan_bfs_shape(n, dmax, false);
+    const BfsPlan wide = plan_bfs_shape(n, dmax, true);
+    return (wide.bw > narrow.bw) ? wide : narrow;
 }
 
 static void split_f32(double x, float &hi, float &lo)

@@ -26,8 +26,12 @@ int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::v
 // 7 when unknown), and the widest batch of sources whose three LDS bit
 // fields and register planes fit one 1024-thread workgroup, with nw 32-bit
 // words per thread per field.
-struct BfsPlan { int bw; int nw; int planes; int n_batches; };
+// `wide` selects the two-field 512-thread shape (only with 4-5 planes), used
+// when it allows a wider batch than the three-field shape.
+struct BfsPlan { int bw; int nw; int planes; int n_batches; bool wide; };
 BfsPlan plan_bfs(int32_t n, int32_t dmax);
+// The three-field or two-field plan alone (bw = 0 when n does not fit).
+BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, bool wide);
 int planes_for(int32_t dmax);
 
 // Histogram row length for a largest finite distance dmax.

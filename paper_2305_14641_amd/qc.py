@@ -46,6 +46,22 @@ EXPORTED = [
 BATCH_HIPGRAPH = 1
 BATCH_FP32C = 2
 
+EXPORTED += ["qc_request_footprint", "qc_server_create", "qc_server_submit", "qc_server_poll",
+             "qc_server_wait", "qc_server_stats", "qc_server_destroy"]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
+                ("tie_mode", ctypes.c_uint32), ("want_potentials", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("n_sigmas", ctypes.c_int32), ("dmax", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
 STAGE_BFS = 0
 STAGE_HIST = 1
 STAGE_POTENTIAL = 2
@@ -95,8 +111,17 @@ def lib():
         L.qc_batch_run.argtypes = [P, P, P, P, P]
         L.qc_batch_recheck_count.argtypes = [P, P]
         L.qc_batch_destroy.argtypes = [P]
+        L.qc_request_footprint.argtypes = [I32, I64, I32]
+        L.qc_request_footprint.restype = I64
+        L.qc_server_create.argtypes = [P, P]
+        L.qc_server_submit.argtypes = [P, I32, I64, P, P, P, I32, P]
+        L.qc_server_poll.argtypes = [P, I64, P]
+        L.qc_server_wait.argtypes = [P, I64, P, P, P, P]
+        L.qc_server_stats.argtypes = [P, P, P]
+        L.qc_server_destroy.argtypes = [P]
         for name in EXPORTED[1:]:
-            getattr(L, name).restype = I32
+            if name != "qc_request_footprint":
+                getattr(L, name).restype = I32
         _lib = L
     return _lib
 
@@ -290,6 +315,74 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().qc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def request_footprint(n: int, nnz: int, n_sigmas: int) -> int:
+    return int(lib().qc_request_footprint(int(n), int(nnz), int(n_sigmas)))
+
+
+class Server:
+    """Continuous-batching request loop (include/qc_server.h)."""
+
+    def __init__(self, max_slots=4, hbm_budget_bytes=16 << 30, tie_mode=TIE_STRICT,
+                 want_potentials=False):
+        o = ServerOpts(int(max_slots), int(hbm_budget_bytes), int(tie_mode),
+                       1 if want_potentials else 0)
+        h = ctypes.c_void_p()
+        _check(lib().qc_server_create(ctypes.byref(o), ctypes.byref(h)), "qc_server_create")
+        self._h = h
+        self._meta = {}
+        self.want_potentials = want_potentials
+
+    def submit(self, n, row_ptr, col, sigmas) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).reshape(-1))
+        rid = ctypes.c_int64(0)
+        _check(lib().qc_server_submit(self._h, int(n), int(c.shape[0]),
+                                      rp.ctypes.data_as(ctypes.c_void_p),
+                                      c.ctypes.data_as(ctypes.c_void_p),
+                                      sig.ctypes.data_as(ctypes.c_void_p), sig.shape[0],
+                                      ctypes.byref(rid)), "qc_server_submit")
+        self._meta[rid.value] = (int(n), sig.shape[0])
+        return int(rid.value)
+
+    def poll(self, rid) -> bool:
+        d = ctypes.c_int32(0)
+        _check(lib().qc_server_poll(self._h, int(rid), ctypes.byref(d)), "qc_server_poll")
+        return bool(d.value)
+
+    def wait(self, rid):
+        """(labels [S, n] int32, psi, V [S, n] float32 or None, info dict)."""
+        n, S = self._meta.pop(rid)
+        lab = np.empty((S, n), dtype=np.int32)
+        psi = np.empty((S, n), dtype=np.float32) if self.want_potentials else None
+        v = np.empty((S, n), dtype=np.float32) if self.want_potentials else None
+        info = RequestInfo()
+        st = lib().qc_server_wait(self._h, int(rid), lab.ctypes.data_as(ctypes.c_void_p),
+                                  psi.ctypes.data_as(ctypes.c_void_p) if psi is not None else None,
+                                  v.ctypes.data_as(ctypes.c_void_p) if v is not None else None,
+                                  ctypes.byref(info))
+        _check(st, f"request {rid}")
+        d = {k: getattr(info, k) for k, _ in RequestInfo._fields_}
+        return lab, psi, v, d
+
+    def stats(self) -> dict:
+        b = ctypes.c_int64(0)
+        r = ctypes.c_int32(0)
+        _check(lib().qc_server_stats(self._h, ctypes.byref(b), ctypes.byref(r)), "qc_server_stats")
+        return {"peak_bytes_in_flight": int(b.value), "peak_requests_in_flight": int(r.value)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().qc_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -92,6 +92,16 @@ def test_null_pointers_rejected():
         assert getattr(L, fn)(*args) == qc.QC_E_INVAL, fn
 
 
+def test_request_footprint_host_only():
+    n, nnz, S = 19717, 88726, 2
+    fp = qc.request_footprint(n, nnz, S)
+    assert fp >= n * n + 4 * (n + 1) + 4 * nnz + 24 * n * S
+    assert fp < n * n * 1.2
+    assert qc.request_footprint(n, nnz, 3) > fp
+    assert qc.request_footprint(0, 1, 1) == -1
+    assert qc.request_footprint(10, 4, 0) == -1
+
+
 def test_valid_graph_without_gpu_reports_device():
     if qc.device_count() > 0:
         pytest.skip("a gfx950 device is visible")

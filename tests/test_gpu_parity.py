@@ -133,14 +133,17 @@ def test_config3_full(torch_cuda):
 
 @pytest.mark.parametrize("n,deg,seed", [
     (3000, 5.0, 21),     # batch width 64
-    (9000, 4.0, 22),     # 32
+    (9000, 4.0, 22),     # 32, then 64 (two-field shape) once dmax is known
+    (15000, 4.0, 26),    # 16, then 32 (two-field shape)
     (20001, 3.0, 23),    # 16
-    (40000, 3.0, 24),    # 8
-    (50003, 3.0, 25),    # 4
+    (40000, 3.0, 24),    # 8, then 16 (two-field shape)
+    (50003, 3.0, 25),    # 4, then 8
 ])
 def test_batch_width_classes_sampled(torch_cuda, n, deg, seed):
-    """Every BFS batch width, ragged last batch: sampled rows bit-exact, all
-    histograms bit-exact (oracle without the matrix), labels bit-exact."""
+    """Every BFS launch shape, ragged last batch: the first run (7 planes)
+    and the re-planned run (planes for dmax, maybe a wider batch) give the
+    same matrix; sampled rows bit-exact, all histograms bit-exact (oracle
+    without the matrix), labels bit-exact."""
     from paper_2305_14641_amd import qc
     torch = torch_cuda
     g = gg.dcsbm(n, [0.5, 0.3, 0.2], deg, seed=seed)
@@ -154,7 +157,10 @@ def test_batch_width_classes_sampled(torch_cuda, n, deg, seed):
     ref_rows, _ = oracle.bfs_rows(n, g.row_ptr, g.col, rows)
     got_rows = dist[torch.as_tensor(rows.astype(np.int64), device="cuda")].cpu().numpy()
     np.testing.assert_array_equal(got_rows, ref_rows)
-    del dist
+    dist2 = torch.empty_like(dist)
+    assert G.distances(dist2) == dmax        # second run: the re-planned shape
+    assert torch.equal(dist, dist2)
+    del dist, dist2
     hist = G.histograms().cpu().numpy()
     ref_hist, ref_dmax = oracle.hist_all(n, g.row_ptr, g.col, hist.shape[1])
     assert dmax == ref_dmax
