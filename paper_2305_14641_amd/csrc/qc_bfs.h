@@ -7,11 +7,11 @@
 // `front` (those that reached it at the previous level) and `nxt` (those
 // reaching it at the current level). A level is:
 //   A. edge-parallel pull: for every edge (r, c), the sources that reached c
-//      at the previous level and have not reached r reach r now:
-//        nxt[r] |= front[c] & ~seen[r]            (LDS atomic OR)
+//      at the previous level are offered to r:
+//        nxt[r] |= front[c]        (LDS atomic OR, no return, no branch)
 //   B. word-owner update: every thread owns whole 32-bit words of the fields;
-//      it moves nxt into front and seen and records the level in the
-//      distance bit-planes of each newly reached (node, source) pair.
+//      the new pairs are nxt & ~seen; it moves them into front and seen and
+//      records the level in the distance bit-planes.
 //
 // Distances live in registers for the whole search, as P bit-planes of the
 // level (plane p holds bit p of every pair's distance; P = 7 covers every
@@ -24,8 +24,7 @@
 // The edge list (packed (row << 16) | col, rows ascending, padded with no-op
 // (0, 0) entries to a multiple of 4) is streamed every level with 16-byte
 // global loads; every thread takes 8 consecutive edges (the next 8 in
-// flight), issues their 8 front gathers together, and merges each run of
-// edges of one row into a single seen read and at most one atomic.
+// flight), issues their 8 front gathers together, then 8 atomics.
 #pragma once
 
 #include "qc_internal.h"
@@ -61,44 +60,37 @@ __device__ __forceinline__ typename BfsWord<BW>::T field_of(const typename BfsWo
     }
 }
 
-// Deliver the OR `x` of the front fields of some neighbours of row r:
-// nxt[r] |= x & ~seen[r].
+// Pull along 8 consecutive edges (rows ascending): the 8 gathers of the
+// source field are issued together (one wait); the OR over each run of edges
+// of one row is formed with selects (no branches), and only the last edge of
+// a run with something to deliver issues a no-return LDS atomic into nxt[r].
+// Bits r has already seen are harmless: the word's owner masks with seen.
 template <int BW>
-__device__ __forceinline__ void pull_row(int r, typename BfsWord<BW>::T x,
-                                         const typename BfsWord<BW>::T *seen,
+__device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
+                                         const typename BfsWord<BW>::T *src,
                                          typename BfsWord<BW>::T *nxt)
 {
     using W = BfsWord<BW>;
     using T = typename W::T;
-    if (x) {
-        const T y = x & ~field_of<BW>(seen, r);
-        if (y) atomicOr(&nxt[r / W::kPer], (T)(y << ((r % W::kPer) * BW)));
-    }
-}
-
-// Pull along 8 consecutive edges (rows ascending).
-template <int BW>
-__device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
-                                         const typename BfsWord<BW>::T *front,
-                                         const typename BfsWord<BW>::T *seen,
-                                         typename BfsWord<BW>::T *nxt)
-{
-    using T = typename BfsWord<BW>::T;
     const uint32_t e[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
     T x[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = field_of<BW>(front, (int)(e[k] & 0xFFFFu));
-    T acc = x[0];
+    for (int k = 0; k < 8; ++k) x[k] = field_of<BW>(src, (int)(e[k] & 0xFFFFu));
+    T acc = 0;
 #pragma unroll
-    for (int k = 1; k < 8; ++k) {
-        if ((e[k] >> 16) == (e[k - 1] >> 16)) {
-            acc |= x[k];
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t r = e[k] >> 16;
+        if (k == 0) {
+            acc = x[0];
         } else {
-            pull_row<BW>((int)(e[k - 1] >> 16), acc, seen, nxt);
-            acc = x[k];
+            acc = (r == (e[(k + 7) & 7] >> 16)) ? (acc | x[k]) : x[k];
         }
+        bool last = true;
+        if (k < 7) last = (e[(k + 1) & 7] >> 16) != r;
+        if (last && acc)
+            __hip_atomic_fetch_or(&nxt[r / W::kPer], (T)(acc << ((r % W::kPer) * BW)),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    pull_row<BW>((int)(e[7] >> 16), acc, seen, nxt);
 }
 
 // WIDE = false: 1024 threads, three fields (pull from `front`).
@@ -160,19 +152,20 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
     }
     __syncthreads();
 
-    const u32x4 zero4 = {0u, 0u, 0u, 0u};
     int last = 0;
     int overflow = 0;
     for (int level = 1;; ++level) {
-        // A. pull over every edge, 8 consecutive edges per thread.
+        // A. pull over every edge, 8 consecutive edges per thread. Quad index
+        //    nquads is the all-zero padding quad: loads clamp to it instead of
+        //    branching, so the next 8 edges stay in flight.
         int q = 2 * tid;
-        u32x4 ca = (q < nquads) ? quads[q] : zero4;
-        u32x4 cb = (q + 1 < nquads) ? quads[q + 1] : zero4;
+        u32x4 ca = quads[min(q, nquads)];
+        u32x4 cb = quads[min(q + 1, nquads)];
         for (; q < nquads; q += 2 * kT) {
             const int qn = q + 2 * kT;
-            const u32x4 na = (qn < nquads) ? quads[qn] : zero4;
-            const u32x4 nb4 = (qn + 1 < nquads) ? quads[qn + 1] : zero4;
-            pull_oct<BW>(ca, cb, front, seen, nxt);
+            const u32x4 na = quads[min(qn, nquads)];
+            const u32x4 nb4 = quads[min(qn + 1, nquads)];
+            pull_oct<BW>(ca, cb, front, nxt);
             ca = na;
             cb = nb4;
         }
@@ -183,16 +176,16 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
         for (int j = 0; j < NWW; ++j) {
             const int w = j * kT + tid;
             if (w < nwords) {
-                const T y = nxt[w];
+                const T raw = nxt[w];
+                const T sw = seen[w];
+                const T y = raw & ~sw;        // newly reached (node, source) pairs
+                nxt[w] = 0;
                 if constexpr (!WIDE) front[w] = y;
-                if (y) {
-                    nxt[w] = 0;
-                    seen[w] |= y;
-                    any = 1;
+                if (y) seen[w] = sw | y;
+                any |= (y != 0);
 #pragma unroll
-                    for (int p = 0; p < P; ++p)
-                        if ((level >> p) & 1) plane[j][p] |= y;
-                }
+                for (int p = 0; p < P; ++p)
+                    if ((level >> p) & 1) plane[j][p] |= y;   // uniform branch
             }
         }
         if (!__syncthreads_or(any)) break;

@@ -54,17 +54,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
         const int64_t r0 = (int64_t)row * n;
         const int64_t r1 = r0 + n;
         const int64_t first = (r0 & ~(int64_t)15) + lane * 16;
-        // Whole 16-byte chunks inside the buffer come from one global load
-        // (the next one already in flight); the last partial chunk of the
-        // buffer is read byte by byte.
-        auto load = [&](int64_t c) -> u32x4 {
-            const u32x4 z = {0u, 0u, 0u, 0u};
-            if (c >= r1 || c + 16 > total) return z;
-            return *(global_u4)(base + c);
-        };
-        u32x4 cur = load(first);
+        // Whole 16-byte chunks inside the buffer come from one global load,
+        // the next one in flight; its address is clamped to the buffer's last
+        // whole chunk (no branch), and the buffer's final partial chunk is
+        // read byte by byte. total < 16 never takes the vector path.
+        const bool vec_ok = total >= 16;
+        const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
+        const u32x4 z4 = {0u, 0u, 0u, 0u};
+        u32x4 cur = vec_ok ? *(global_u4)(base + min(first, last_whole)) : z4;
         for (int64_t c = first; c < r1; c += 64 * 16) {
-            const u32x4 ahead = load(c + 64 * 16);
+            const u32x4 ahead = vec_ok ? *(global_u4)(base + min(c + 64 * 16, last_whole)) : z4;
             if (c + 16 <= total) {
                 const uint32_t wv[4] = {cur.x, cur.y, cur.z, cur.w};
                 const bool inside = (c >= r0) && (c + 16 <= r1);
