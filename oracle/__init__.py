@@ -72,6 +72,8 @@ def lib():
         L.qco_find_centers.restype = None
         L.qco_potential_literal.argtypes = [I, P, P, P, D, D, P, P]
         L.qco_potential_literal.restype = None
+        L.qco_potential_dense.argtypes = [I, I, P, D, P, P]
+        L.qco_potential_dense.restype = None
         L.qco_num_threads.argtypes = []
         L.qco_num_threads.restype = I
         _lib = L
@@ -176,6 +178,17 @@ def potential_literal(n, row_ptr, col, sigma, weight=None, cap=2.0) -> tuple:
         w = np.ascontiguousarray(weight, dtype=np.float64)
         wp = _p(w)
     lib().qco_potential_literal(n, _p(rp), _p(c), wp, float(cap), float(sigma), _p(psi), _p(v))
+    return psi, v
+
+
+def potential_dense(dist_rows: np.ndarray, sigma: float) -> tuple:
+    """Algorithm 1 on dense float32 distance rows; entries that are not
+    finite and >= 0 mean "no path" (Section 3.2's fully connected workload)."""
+    d = np.ascontiguousarray(dist_rows, dtype=np.float32)
+    nrows, n = d.shape
+    psi = np.empty(nrows)
+    v = np.empty(nrows)
+    lib().qco_potential_dense(n, nrows, _p(d), float(sigma), _p(psi), _p(v))
     return psi, v
 
 

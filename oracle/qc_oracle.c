@@ -284,6 +284,29 @@ void qco_potential_literal(int n, const int32_t *row_ptr, const int32_t *col,
     }
 }
 
+/* Algorithm 1 on a dense real-valued distance matrix (one row per node, as
+ * the paper's GPU experiment runs it on fully connected graphs, Section 3.2).
+ * Only finite entries >= 0 are distances; any other entry (negative, NaN,
+ * infinite) means "no path" and is skipped. */
+void qco_potential_dense(int n, int nrows, const float *dist, double sigma, double *psi, double *v)
+{
+    const double two_s2 = 2.0 * sigma * sigma;
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < nrows; ++r) {
+        const float *row = dist + (size_t)r * n;
+        double sum1 = 0.0, sum2 = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (!(row[j] >= 0.0f) || isinf(row[j])) continue;
+            double d = (double)row[j];
+            double e = exp(-(d * d) / two_s2);
+            sum1 = sum1 + (d * d) * e;
+            sum2 = sum2 + e;
+        }
+        psi[r] = sum2;
+        v[r] = (1.0 / two_s2) * (sum1 / sum2);
+    }
+}
+
 int qco_num_threads(void)
 {
     int t = 1;

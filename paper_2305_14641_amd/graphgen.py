@@ -237,6 +237,19 @@ def poisson_arrivals(n_req: int, rate: float, seed: int = 77) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate, n_req))
 
 
+def dense_points(n: int, dim: int = 8, clusters: int = 6, seed: int = 0) -> np.ndarray:
+    """Fully connected workload: Euclidean distances (float32 [n, n]) between
+    n points drawn around `clusters` Gaussian centres in `dim` dimensions."""
+    rng = np.random.default_rng(seed)
+    centres = rng.normal(0.0, 3.0, (clusters, dim))
+    x = centres[rng.integers(0, clusters, n)] + rng.normal(0.0, 1.0, (n, dim))
+    sq = (x * x).sum(axis=1)
+    d2 = np.maximum(sq[:, None] + sq[None, :] - 2.0 * x @ x.T, 0.0)
+    d = np.sqrt(d2)
+    np.fill_diagonal(d, 0.0)
+    return d.astype(np.float32)
+
+
 # ---------------------------------------------------------------------------
 # Small named graphs (ids as in the usual textbook constructions).
 

@@ -199,3 +199,31 @@ def test_literal_reading_cap2_equals_hop_distance_capped():
         psi_x, v_x = closed_form(h, 1.3)
         assert abs(psi[i] - float(psi_x)) <= 1e-13 * float(psi_x)
         assert abs(v[i] - float(v_x)) <= 1e-13 * float(v_x)
+
+
+def test_dense_form_vs_mpmath_and_literal():
+    """Algorithm 1 on a dense float matrix: a 50-digit evaluation of the same
+    float entries, and equality with the literal-reading function when the
+    matrix is the literal distance of a graph."""
+    d = gg.dense_points(40, dim=3, clusters=3, seed=4)
+    d[3, 7] = d[7, 3] = -1.0                     # missing pairs are skipped
+    d[3, 9] = np.nan
+    d[3, 11] = np.inf
+    for sigma in (0.7, 2.5):
+        psi, v = oracle.potential_dense(d, sigma)
+        a = 2 * mpmath.mpf(sigma) ** 2
+        for i in (0, 3, 39):
+            ds = [mpmath.mpf(float(x)) for x in d[i] if np.isfinite(x) and x >= 0]
+            psi_x = mpmath.fsum(mpmath.e ** (-(x * x) / a) for x in ds)
+            v_x = mpmath.fsum(x * x * mpmath.e ** (-(x * x) / a) for x in ds) / (a * psi_x)
+            assert abs(psi[i] - float(psi_x)) <= 1e-14 * float(psi_x)
+            assert abs(v[i] - float(v_x)) <= 1e-14 * float(v_x)
+    g = gg.config1()
+    lit = np.full((g.n, g.n), 2.0, dtype=np.float32)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    lit[rows, g.col] = 1.0
+    np.fill_diagonal(lit, 0.0)
+    psi_d, v_d = oracle.potential_dense(lit, 1.3)
+    psi_l, v_l = oracle.potential_literal(g.n, g.row_ptr, g.col, 1.3, cap=2.0)
+    np.testing.assert_allclose(psi_d, psi_l, rtol=1e-14)
+    np.testing.assert_allclose(v_d, v_l, rtol=1e-14)
