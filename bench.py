@@ -42,6 +42,24 @@ def bfs_bytes(g) -> float:
     return float(g.n) * g.n + 4.0 * (g.n + 1) + 4.0 * g.nnz
 
 
+PROFILE = os.path.join(ROOT, "profiles", "bench_c4_kernels_and_traffic.json")
+
+
+def profiled_traffic():
+    """HBM bytes per k_bfs launch measured by rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (scaled by a copy-kernel calibration) for the kernel sources as they are
+    now; None when no such profile exists or a kernel source changed since."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    prof = json.load(open(PROFILE))
+    for rel, digest in prof.get("kernel_sources_sha256", {}).items():
+        path = os.path.join(ROOT, rel)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+            return None
+    return prof["k_bfs_tuned"]["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(graphs, sigmas, budget_s: float) -> dict:
     """The oracle (as it stands) on the first graphs of the workload, in order
     of increasing size, until about `budget_s` seconds of CPU work."""
@@ -70,6 +88,156 @@ def cpu_baseline(graphs, sigmas, budget_s: float) -> dict:
     }
 
 
+def _gen_request(r):
+    from paper_2305_14641_amd import graphgen as gg
+    g, sig = gg.config5_graph(r)
+    return g.n, g.row_ptr, g.col, sig
+
+
+def serve(args):
+    """Serving form on the request stream: open-loop Poisson arrivals, p50/p99
+    latency (scheduled arrival -> labels on the host), graphs/s, and the same
+    requests run one at a time."""
+    import concurrent.futures as cf
+    import threading
+    import torch
+    from paper_2305_14641_amd import graphgen as gg
+    from paper_2305_14641_amd import qc
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        reqs = list(ex.map(_gen_request, range(args.serve), chunksize=4))
+    log(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f}s "
+        f"(N {min(r[0] for r in reqs)}..{max(r[0] for r in reqs)})")
+    budget = int(args.serve_budget_gib * (1 << 30))
+    # the plain path: one request at a time through the same server (1 slot)
+    srv1 = qc.Server(max_slots=1, hbm_budget_bytes=budget)
+    rid = srv1.submit(*reqs[0][:3], reqs[0][3])
+    srv1.wait(rid)                                   # warm-up
+    t0 = time.perf_counter()
+    for r in reqs:
+        srv1.wait(srv1.submit(r[0], r[1], r[2], r[3]))
+    plain_s = time.perf_counter() - t0
+    srv1.close()
+    results = {"requests": len(reqs), "slots": args.serve_slots,
+               "plain_graphs_per_s": len(reqs) / plain_s, "rates": []}
+    for rate in args.serve_rates:
+        arrivals = gg.poisson_arrivals(len(reqs), rate, seed=77)
+        srv = qc.Server(max_slots=args.serve_slots, hbm_budget_bytes=budget)
+        ids = [None] * len(reqs)
+        lat = [None] * len(reqs)
+        start = time.perf_counter() + 0.05
+
+        def submitter():
+            for k, r in enumerate(reqs):
+                delay = start + arrivals[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                ids[k] = srv.submit(r[0], r[1], r[2], r[3])
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        for k in range(len(reqs)):
+            while ids[k] is None:
+                time.sleep(0.0005)
+            _, _, _, info = srv.wait(ids[k])
+            lat[k] = info["t_done"] - (start + arrivals[k])
+        th.join()
+        end = time.perf_counter()
+        stats = srv.stats()
+        srv.close()
+        lat_ms = np.sort(np.array(lat) * 1e3)
+        entry = {"rate_per_s": rate, "p50_ms": float(np.percentile(lat_ms, 50)),
+                 "p99_ms": float(np.percentile(lat_ms, 99)),
+                 "graphs_per_s": len(reqs) / (end - start), **stats}
+        results["rates"].append(entry)
+        log(f"rate {rate}/s: p50 {entry['p50_ms']:.1f} ms, p99 {entry['p99_ms']:.1f} ms, "
+            f"{entry['graphs_per_s']:.1f} graphs/s, peak in flight {stats['peak_requests_in_flight']}")
+    return results
+
+
+def quality_sweep(qc, gg, torch) -> dict:
+    """Section 4.2's measures of the GPU labels against the planted blocks of
+    the 64 sweep graphs, for each of the 32 widths (a synthetic analogue of
+    the paper's sensitivity study), as means and spreads over the graphs."""
+    from paper_2305_14641_amd import quality
+    graphs = gg.config4()
+    sigmas = gg.sigmas_c4()
+    handles = [qc.Graph.from_graph(g) for g in graphs]
+    b = qc.Batch(handles, sigmas, tie_mode=qc.TIE_STRICT, hipgraph=False)
+    psi, v, lab = b.outputs()
+    b.run(psi, v, lab)
+    torch.cuda.synchronize()
+    lab = lab.cpu().numpy()
+    rows = []
+    for s, sigma in enumerate(sigmas):
+        per = []
+        for i, g in enumerate(graphs):
+            o0, o1 = b.offsets[i], b.offsets[i + 1]
+            per.append(quality.scores(g.row_ptr, g.col, g.blocks, lab[s, o0:o1]))
+        keys = ["modularity", "nmi", "ari", "fmi"]
+        row = {"sigma": sigma}
+        for k in keys:
+            vals = np.array([p_[k] for p_ in per])
+            row[k] = float(vals.mean())
+            row[k + "_std"] = float(vals.std())
+        cl = np.array([p_["clusters"] / g.n for p_, g in zip(per, graphs)])
+        row["clusters_per_node"] = float(cl.mean())
+        rows.append(row)
+        log(f"sigma {sigma:6.3f}: Q {row['modularity']:.3f} NMI {row['nmi']:.3f} "
+            f"ARI {row['ari']:.3f} FMI {row['fmi']:.3f} clusters/node {row['clusters_per_node']:.4f}")
+    b.close()
+    return {"metric": "clustering quality vs planted blocks across the sigma sweep",
+            "config": {"workload": "64 DC-SBM graphs (seeds 100-163), 32 sigmas geomspace(0.25, 8), "
+                                   "strict ties; GPU labels"},
+            "rows": rows}
+
+
+def dense_leg(args, qc, torch) -> dict:
+    """Algorithm 1 on a fully connected graph with float distances (the
+    paper's GPU experiment shape): one pass for one width (HBM-bound) and for
+    eight widths (ALU-bound), timed with HIP events on the launch stream."""
+    from paper_2305_14641_amd import graphgen as gg
+    n = args.dense_n
+    t0 = time.perf_counter()
+    d = torch.as_tensor(gg.dense_points(n, dim=16, clusters=8, seed=3)).cuda()
+    log(f"dense: generated {n} x {n} matrix in {time.perf_counter() - t0:.1f}s")
+    out = {"workload": f"fully connected: {n} points of an 8-cluster Gaussian mixture in 16-D, "
+                       "Euclidean float32 distances", "n": n}
+    for S in (1, 8):
+        sig = list(np.geomspace(0.5, 8.0, S)) if S > 1 else [2.0]
+        psi = torch.empty((S, n), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(psi)
+        for _ in range(2):
+            qc.potential_dense(d, sig, psi=psi, v=v)
+        torch.cuda.synchronize()
+        qc.timing_enable(True)
+        reps = max(args.steps, 3)
+        for _ in range(reps):
+            qc.potential_dense(d, sig, psi=psi, v=v)
+        torch.cuda.synchronize()
+        ms, cnt = qc.timing_read(qc.STAGE_DENSE)
+        qc.timing_enable(False)
+        per = ms / reps
+        terms = float(n) * n * S
+        gbs = 4.0 * n * n / (per * 1e-3) / 1e9
+        out[f"s{S}"] = {"ms": per, "launches": cnt / reps, "pair_terms_per_s": terms / (per * 1e-3),
+                        "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        log(f"dense S={S}: {per:.3f} ms, {terms / (per * 1e-3):.3e} pair-terms/s, {gbs:.0f} GB/s")
+    if not args.no_cpu_baseline:
+        import oracle
+        rows = d[:256].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.potential_dense(rows, 2.0)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"pair_terms_per_s": rows.size / dt, "cores": oracle.num_threads(),
+                             "sample": "first 256 rows, one width"}
+    del d
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,19 +247,39 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the fully connected (dense float distance) leg")
+    ap.add_argument("--dense-n", type=int, default=20000)
+    ap.add_argument("--quality", action="store_true",
+                    help="sigma-sweep quality study: label quality vs the planted blocks")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="run the serving form on the first SERVE requests of the stream instead")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[10, 50, 200, 500])
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.serve:
+        res = serve(args)
+        print(json.dumps({"metric": "serving: p50/p99 latency and graphs/s on the request stream",
+                          "config": {"workload": "serving: Poisson stream of DC-SBM clustering "
+                                                 "requests, N log-uniform [500, 5e4], 1-8 sigmas"},
+                          **res}))
+        return
 
     import torch
     from paper_2305_14641_amd import graphgen as gg
     from paper_2305_14641_amd import qc
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.quality:
+        print(json.dumps(quality_sweep(qc, gg, torch)))
+        return
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
 
@@ -184,6 +372,28 @@ def main():
                  "bitwise_equal_to_batched": True}
         log(f"plain: {pdt * 1e3:.2f} ms/step")
 
+    # -- BF16 matrix-core sweep variant: time and error vs the FP64 values ----
+    bf16 = None
+    if not args.no_plain:
+        qc.timing_enable(True)
+        worst_psi = worst_v = 0.0
+        for i, (g, G) in enumerate(zip(graphs, handles)):
+            pb, vb = G.potential(sigmas, precision=qc.PREC_BF16)
+            o = batch.offsets[i]
+            pr, vr = psi[:, o:o + g.n].double(), v[:, o:o + g.n].double()
+            worst_psi = max(worst_psi, float(((pb.double() - pr).abs() / pr.abs()).max()))
+            nz = vr != 0
+            worst_v = max(worst_v, float(((vb.double() - vr).abs()[nz] / vr.abs()[nz]).max()))
+        torch.cuda.synchronize()
+        ms, cnt = qc.timing_read(qc.STAGE_POTENTIAL)
+        qc.timing_enable(False)
+        bf16 = {"potential_ms_per_step": ms, "launches": cnt,
+                "fp64_potential_ms_per_step": stages["potential"]["ms_per_step"],
+                "max_rel_err_psi": worst_psi, "max_rel_err_v": worst_v}
+        log(f"bf16 sweep: {ms:.3f} ms, max rel err psi {worst_psi:.2e} V {worst_v:.2e}")
+
+    dense = None if args.no_dense else dense_leg(args, qc, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(graphs, sigmas, args.cpu_budget_s)
@@ -217,11 +427,14 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_bfs",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
             "algorithmic_bytes_per_launch": bytes_step / bfs_launches,
         },
         "hist_kernel_gbs": hist_gbs,
         "plain": plain,
+        "bf16_sweep": bf16,
+        "dense": dense,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result))

@@ -164,6 +164,35 @@ qc_status qc_potential(qc_graph g, const double *sigmas, int32_t n_sigmas,
 qc_status qc_ggd_labels(qc_graph g, int32_t sigma_index, uint32_t tie_mode,
                         int32_t *labels_out, void *stream);
 
+/*
+ * Algorithm 1 on a dense matrix of real-valued distances supplied by the
+ * caller: the fully connected workload of the paper's GPU experiment
+ * (Section 3.2, Fig. 3), and Section 3.1's distance read literally (an
+ * edge's weight for an edge, a cap above every weight for a missing edge)
+ * once the caller has written it out densely. Needs no graph handle.
+ *   dist      device, float[n_rows * ld] row-major; row i holds d(i, j) for
+ *             j < n_cols. Finite entries >= 0 are distances; any other
+ *             entry (negative, NaN, infinite) means "no path" and is skipped.
+ *             The self distance must be present (normally 0) if it is to be
+ *             counted, as in Eq. 2. Rows whose start is 16-byte aligned
+ *             (aligned `dist`, ld % 4 == 0) are read with 16-byte loads.
+ *   n_rows    0 <= n_rows (0: nothing to do); n_cols >= 0; ld >= n_cols
+ *   sigmas    host, double[n_sigmas], each finite and >= 1e-100;
+ *             1 <= n_sigmas <= 1024
+ *   psi_out   device, double[n_sigmas][n_rows]: psi_i = sum_j e^{-d_ij^2/2 sigma^2}
+ *   v_out     device, double[n_sigmas][n_rows]: V_i of Algorithm 1
+ * Sums are accumulated in FP64; each exponential is evaluated to about one
+ * FP32 ulp, so psi and V are within 1e-6 relative of an FP64 evaluation.
+ * A row with no counted entry gives psi = 0 and V = NaN (0/0).
+ * The matrix is streamed once per group of up to 8 widths.
+ * Errors: QC_E_INVAL for a NULL pointer with n_rows > 0, negative sizes,
+ * ld < n_cols, or an invalid sigma; QC_E_DEVICE for a launch failure (or
+ * when no gfx950 device is current).
+ */
+qc_status qc_potential_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64_t ld,
+                             const double *sigmas, int32_t n_sigmas, double *psi_out,
+                             double *v_out, void *stream);
+
 /* Number of node decisions the last qc_ggd_labels call (or batch run)
  * re-decided in FP64 (waits for the stream). */
 qc_status qc_last_recheck_count(qc_graph g, int64_t *count_out);
@@ -186,7 +215,8 @@ enum {
     QC_STAGE_POTENTIAL = 2,  /* psi / V */
     QC_STAGE_GGD = 3,        /* descent parents (with FP64 re-check) */
     QC_STAGE_JUMP = 4,       /* pointer jumping to labels */
-    QC_N_STAGES = 5
+    QC_STAGE_DENSE = 5,      /* qc_potential_dense */
+    QC_N_STAGES = 6
 };
 qc_status qc_timing_enable(int32_t on);  /* on = 1 also clears earlier records */
 qc_status qc_timing_read(int32_t stage, double *total_ms, int64_t *launches);

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqc_hip.so")
 
-SOURCES = ["qc_kernels.hip", "qc_bfs_4.hip", "qc_bfs_8.hip", "qc_bfs_16.hip", "qc_bfs_32.hip",
+SOURCES = ["qc_kernels.hip", "qc_dense.hip", "qc_bfs_4.hip", "qc_bfs_8.hip", "qc_bfs_16.hip", "qc_bfs_32.hip",
            "qc_bfs_64.hip", "qc_api.cpp", "qc_host.cpp", "qc_timing.cpp", "qc_batch.cpp",
            "qc_server.cpp"]
 

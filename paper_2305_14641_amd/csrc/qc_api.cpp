@@ -44,6 +44,13 @@ qc_status push_desc(qc_graph g, hipStream_t st)
     return from_hip(launch_set_desc(g->d_desc, g->desc(), st));
 }
 
+uint32_t batch_target(qc_graph g, int s0, int bw)
+{
+    uint64_t t = 0;
+    for (int s = s0; s < s0 + bw && s < g->n; ++s) t += (uint64_t)g->comp_size[s];
+    return (uint32_t)t;
+}
+
 qc_status set_plan(qc_graph g, const BfsPlan &p)
 {
     if (p.bw <= 0) return QC_E_INVAL;
@@ -52,7 +59,8 @@ qc_status set_plan(qc_graph g, const BfsPlan &p)
         return QC_OK;
     }
     std::vector<BfsJob> jobs(p.n_batches);
-    for (int b = 0; b < p.n_batches; ++b) jobs[b] = BfsJob{0, b * p.bw};
+    for (int b = 0; b < p.n_batches; ++b)
+        jobs[b] = BfsJob{0, b * p.bw, batch_target(g, b * p.bw, p.bw), 0u};
     gfree(g, g->d_bfs_jobs);
     QC_TRY(galloc(g, &g->d_bfs_jobs, jobs.size()));
     QC_TRY(upload(g->d_bfs_jobs, jobs));
@@ -125,6 +133,8 @@ qc_status ensure_sigma_buffers(qc_graph g, int S)
         gfree(g, g->d_u64);
         gfree(g, g->d_inv_a);
         gfree(g, g->d_w32c);
+        gfree(g, g->d_wbf16);
+        QC_TRY(galloc(g, &g->d_wbf16, (size_t)S * g->K * 2));
         QC_TRY(galloc(g, &g->d_w64, (size_t)S * g->K));
         QC_TRY(galloc(g, &g->d_u64, (size_t)S * g->K));
         QC_TRY(galloc(g, &g->d_inv_a, (size_t)S));
@@ -140,7 +150,8 @@ qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStr
     if (sig != g->sigmas_loaded) {
         std::vector<double> w64, u64, inv_a;
         std::vector<float> w32c;
-        weight_tables(sigmas, n_sigmas, g->K, w64, u64, inv_a, w32c);
+        std::vector<uint16_t> wbf16;
+        weight_tables(sigmas, n_sigmas, g->K, w64, u64, inv_a, w32c, wbf16);
         QC_TRY(ensure_sigma_buffers(g, n_sigmas));
         // The weight tables are tiny; a synchronous upload keeps host buffers
         // safe. A repeated sigma list reuses the tables already on the device.
@@ -149,6 +160,7 @@ qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStr
         QC_TRY(upload(g->d_u64, u64));
         QC_TRY(upload(g->d_inv_a, inv_a));
         QC_TRY(upload(g->d_w32c, w32c));
+        QC_TRY(upload(g->d_wbf16, wbf16));
         g->sigmas_loaded = sig;
         g->n_sigmas = n_sigmas;
         QC_TRY(push_desc(g, st));
@@ -173,6 +185,7 @@ void destroy(qc_graph g, bool sync)
     gfree(g, g->d_u64);
     gfree(g, g->d_inv_a);
     gfree(g, g->d_w32c);
+    gfree(g, g->d_wbf16);
     gfree(g, g->d_status);
     gfree(g, g->d_recheck);
     gfree(g, g->d_desc);
@@ -248,7 +261,7 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     g->bump_size = region_bytes;
     g->n = n;
     g->nnz = (int64_t)col.size();
-    g->n_components = count_components(n, rp, col);
+    g->n_components = count_components(n, rp, col, &g->comp_size);
 
     // packed edges, padded with no-op (0, 0) entries to a multiple of 4
     std::vector<uint32_t> edges(((g->nnz + 3) / 4) * 4 + 4, 0u);
@@ -329,7 +342,7 @@ qc_status qc_potential(qc_graph g, const double *sigmas, int32_t n_sigmas, float
 {
     if (!g) return QC_E_INVAL;
     QC_TRY(validate_sigmas(sigmas, n_sigmas));
-    if (precision > QC_PREC_FP32C) return QC_E_INVAL;
+    if (precision > QC_PREC_BF16) return QC_E_INVAL;
     hipStream_t st = as_stream(stream);
     if (!g->have_dist) QC_TRY(qc_distances(g, nullptr, nullptr, stream));
 
@@ -376,6 +389,26 @@ qc_status qc_last_recheck_count(qc_graph g, int64_t *count_out)
     QC_HIP(hipDeviceSynchronize());
     QC_HIP(hipMemcpy(&c, g->d_recheck, sizeof c, hipMemcpyDeviceToHost));
     *count_out = (int64_t)c;
+    return QC_OK;
+}
+
+qc_status qc_potential_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64_t ld,
+                             const double *sigmas, int32_t n_sigmas, double *psi_out,
+                             double *v_out, void *stream)
+{
+    if (n_rows < 0 || n_cols < 0 || ld < n_cols) return QC_E_INVAL;
+    QC_TRY(validate_sigmas(sigmas, n_sigmas));
+    // below 1e-100, d^2 / (2 sigma^2) could overflow for the largest floats
+    for (int32_t s = 0; s < n_sigmas; ++s)
+        if (sigmas[s] < 1e-100) return QC_E_INVAL;
+    if (n_rows == 0) return QC_OK;
+    if (!psi_out || !v_out || (n_cols > 0 && !dist)) return QC_E_INVAL;
+    // one workgroup per 4 rows: the grid's x dimension bounds the row count
+    if ((n_rows + 3) / 4 > (int64_t)INT32_MAX) return QC_E_INVAL;
+    int dev = 0;
+    QC_TRY(check_device(&dev));
+    QC_HIP(launch_dense(dist, n_rows, n_cols, ld, sigmas, n_sigmas, psi_out, v_out,
+                        as_stream(stream)));
     return QC_OK;
 }
 

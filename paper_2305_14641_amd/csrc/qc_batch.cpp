@@ -214,7 +214,9 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         for (int gi : kv.second) {
             qc_graph g = graphs[gi];
             std::vector<BfsJob> js;
-            for (int bidx = 0; bidx < g->plan.n_batches; ++bidx) js.push_back(BfsJob{gi, bidx * g->plan.bw});
+            for (int bidx = 0; bidx < g->plan.n_batches; ++bidx)
+                js.push_back(BfsJob{gi, bidx * g->plan.bw,
+                                    batch_target(g, bidx * g->plan.bw, g->plan.bw), 0u});
             per.push_back(js);
             cost.push_back((double)g->plan.n_batches * (double)(g->nnz + g->n) * (g->dmax + 2));
         }

@@ -116,6 +116,7 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
     __shared__ T seen[kLdsWords];
     __shared__ T nxt[kLdsWords];
     __shared__ T front_store[WIDE ? 1 : kLdsWords];
+    __shared__ uint32_t found_pairs;
     T *const front = WIDE ? seen : front_store;
 
     const BfsJob job = jobs[blockIdx.x];
@@ -150,7 +151,9 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
         if constexpr (!WIDE) front[w] = bits;
         nxt[w] = 0;
     }
+    if (tid == 0) found_pairs = (uint32_t)nb;   // level 0: every source itself
     __syncthreads();
+    uint32_t found_before = (uint32_t)nb;
 
     int last = 0;
     int overflow = 0;
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
         }
         __syncthreads();
         // B. move the new bits of owned words into front / seen / planes.
-        int any = 0;
+        uint32_t cnt = 0;
 #pragma unroll
         for (int j = 0; j < NWW; ++j) {
             const int w = j * kT + tid;
@@ -182,19 +185,26 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
                 nxt[w] = 0;
                 if constexpr (!WIDE) front[w] = y;
                 if (y) seen[w] = sw | y;
-                any |= (y != 0);
+                cnt += (uint32_t)__popcll((unsigned long long)y);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     if ((level >> p) & 1) plane[j][p] |= y;   // uniform branch
             }
         }
-        if (!__syncthreads_or(any)) break;
+        // one LDS atomic per wavefront with the wavefront's count of new pairs
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if ((tid & 63) == 0 && cnt) atomicAdd(&found_pairs, cnt);
+        __syncthreads();
+        const uint32_t found = found_pairs;
+        if (found == found_before) break;   // nothing new: every search ended
+        found_before = found;
         last = level;
         if (level > kLevels) {
             // this level does not fit the planes (P = 7: a distance above 126)
             overflow = (P >= 7) ? 1 : 2;
             break;
         }
+        if (found >= job.target) break;     // every reachable pair found: skip the empty level
     }
 
     // Decode the planes of every owned word into distance bytes and write

@@ -24,6 +24,7 @@ struct qc_graph_s {
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t n_components = 0;
+    std::vector<int32_t> comp_size;   // size of each node's component (host)
     BfsPlan plan{};
 
     // device CSR
@@ -47,6 +48,7 @@ struct qc_graph_s {
     int32_t *d_parent = nullptr;
     double *d_w64 = nullptr, *d_u64 = nullptr, *d_inv_a = nullptr;
     float *d_w32c = nullptr;
+    uint16_t *d_wbf16 = nullptr;
     int w_cap = 0;                    // sigma*K entries the weight buffers hold
     bool have_pot = false;
     uint32_t pot_precision = 0;
@@ -84,6 +86,7 @@ struct qc_graph_s {
         d.u64 = d_u64;
         d.inv_a = d_inv_a;
         d.w32c = d_w32c;
+        d.wbf16 = d_wbf16;
         d.parent = d_parent;
         d.status = d_status;
         d.recheck = d_recheck;
@@ -160,6 +163,8 @@ qc_status check_device(int *dev_out);
 qc_status push_desc(qc_graph g, hipStream_t st);
 qc_status ensure_hist_jobs(qc_graph g);
 qc_status set_plan(qc_graph g, const BfsPlan &p);
+// Reachable (source, node) pairs of the batch of sources s0..s0+bw-1.
+uint32_t batch_target(qc_graph g, int s0, int bw);
 qc_status run_distances(qc_graph g, hipStream_t st);
 qc_status ensure_sigma_buffers(qc_graph g, int S);
 // Load the weight tables of a sigma list into g (no-op if already loaded).

@@ -2,6 +2,7 @@
 #include "qc_host.h"
 
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <numeric>
@@ -73,7 +74,8 @@ static int32_t uf_find(std::vector<int32_t> &p, int32_t x)
     return x;
 }
 
-int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col)
+int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                         std::vector<int32_t> *comp_size)
 {
     std::vector<int32_t> p(n);
     std::iota(p.begin(), p.end(), 0);
@@ -86,6 +88,12 @@ int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::v
                 --comps;
             }
         }
+    if (comp_size) {
+        std::vector<int32_t> size(n, 0);
+        for (int32_t i = 0; i < n; ++i) ++size[uf_find(p, i)];
+        comp_size->assign(n, 0);
+        for (int32_t i = 0; i < n; ++i) (*comp_size)[i] = size[uf_find(p, i)];
+    }
     return comps;
 }
 
@@ -144,13 +152,25 @@ static void split_f32(double x, float &hi, float &lo)
     lo = (float)(x - (double)hi);
 }
 
+static uint16_t to_bf16(double x)
+{
+    // FP32 first, then round to nearest even at 8 significant bits
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 void weight_tables(const double *sigmas, int n_sigmas, int K, std::vector<double> &w64,
-                   std::vector<double> &u64, std::vector<double> &inv_a, std::vector<float> &w32c)
+                   std::vector<double> &u64, std::vector<double> &inv_a, std::vector<float> &w32c,
+                   std::vector<uint16_t> &wbf16)
 {
     w64.assign((size_t)n_sigmas * K, 0.0);
     u64.assign((size_t)n_sigmas * K, 0.0);
     inv_a.assign(n_sigmas, 0.0);
     w32c.assign((size_t)n_sigmas * K * 4, 0.0f);
+    wbf16.assign((size_t)n_sigmas * K * 2, 0);
     for (int s = 0; s < n_sigmas; ++s) {
         const double a = (2.0 * sigmas[s]) * sigmas[s];
         inv_a[s] = 1.0 / a;
@@ -162,6 +182,8 @@ void weight_tables(const double *sigmas, int n_sigmas, int K, std::vector<double
             float *c = &w32c[((size_t)s * K + k) * 4];
             split_f32(w, c[0], c[1]);
             split_f32(u, c[2], c[3]);
+            wbf16[((size_t)s * K + k) * 2 + 0] = to_bf16(w);
+            wbf16[((size_t)s * K + k) * 2 + 1] = to_bf16(u);
         }
     }
 }

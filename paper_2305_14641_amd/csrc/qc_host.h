@@ -18,8 +18,10 @@ qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
                        bool canonicalize, std::vector<int32_t> &rp_out,
                        std::vector<int32_t> &col_out);
 
-// Number of connected components (union-find over the canonical CSR).
-int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col);
+// Number of connected components (union-find over the canonical CSR); if
+// comp_size is given it receives, for every node, the size of its component.
+int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                         std::vector<int32_t> *comp_size = nullptr);
 
 // BFS launch shape for a graph of n nodes whose largest finite distance is
 // dmax (or -1 while unknown): `planes` distance bit-planes (enough for dmax,
@@ -42,9 +44,10 @@ inline int bins_for(int dmax) { return dmax < 32 ? 32 : (dmax < 64 ? 64 : 128); 
 //   u64[s*K + k] = (k*k) * w64 / a_s
 //   inv_a[s]     = 1 / a_s
 //   w32c[(s*K + k)*4 + {0,1,2,3}] = FP32 hi/lo splits of w64 and u64
+//   wbf16[(s*K + k)*2 + {0,1}] = BF16 roundings of w64 and u64
 void weight_tables(const double *sigmas, int n_sigmas, int K, std::vector<double> &w64,
                    std::vector<double> &u64, std::vector<double> &inv_a,
-                   std::vector<float> &w32c);
+                   std::vector<float> &w32c, std::vector<uint16_t> &wbf16);
 
 // Check a sigma list (count 1..1024, every value finite and > 0).
 qc_status validate_sigmas(const double *sigmas, int32_t n_sigmas);

@@ -46,16 +46,21 @@ struct GraphDev {
     const double *u64;        // [n_sigmas*K] k^2 * w / a
     const double *inv_a;      // [n_sigmas] 1/a, a = (2 sigma) sigma
     const float *w32c;        // [n_sigmas*K*4] FP32 (w_hi, w_lo, u_hi, u_lo)
+    const uint16_t *wbf16;    // [n_sigmas*K*2] BF16 (w, u) pairs for the matrix-core variant
     int32_t *parent;          // [n_sigmas*n] descent parents
     int32_t *status;          // [2]: 0 largest finite distance, 1 overflow flag
     unsigned long long *recheck;  // count of FP64 re-decided nodes
 };
 
-struct BfsJob { int32_t g; int32_t s0; };                  // graph index, first source
+// graph index, first source, and the number of (source, node) pairs the
+// batch's sources can reach (sum of their component sizes): the search stops
+// as soon as that many pairs have been found.
+struct BfsJob { int32_t g; int32_t s0; uint32_t target; uint32_t pad; };
 struct NodeJob { int32_t g; int32_t i0; int64_t out_off; };  // graph, first node, output offset
 
-// Rows of the distance matrix one histogram job covers, by bin count.
-inline int hist_rows_per_job(int K) { return K >= 128 ? 4 : 8; }
+// Rows of the distance matrix one histogram job covers, by bin count
+// (wavefronts per workgroup x rows per wavefront; see launch_hist).
+inline int hist_rows_per_job(int K) { return 32; }
 // Nodes per job of the potential and descent kernels.
 constexpr int kNodesPerJob = 256;
 
@@ -112,6 +117,13 @@ class StageTimer {
     void *start_ = nullptr;
     void *stop_ = nullptr;
 };
+
+// Algorithm 1 over a dense float distance matrix (qc_dense.hip): rows
+// [0, n_rows) of `dist` (row stride `ld` floats), every width of `sigmas`
+// (host); writes psi and V as FP64 [n_sigmas][n_rows].
+hipError_t launch_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64_t ld,
+                        const double *sigmas, int n_sigmas, double *psi, double *v,
+                        hipStream_t stream);
 
 // Fill kernel (used instead of hipMemsetAsync so work can be graph-captured).
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t stream);

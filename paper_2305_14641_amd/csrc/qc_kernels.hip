@@ -26,75 +26,75 @@ hipError_t launch_bfs(int bw, int nw, int planes, bool wide, const GraphDev *gra
 
 // ===========================================================================
 // Distance histograms h[i][k] = #{j : d(i,j) = k} from resident int8 rows.
-// One wavefront per row; every lane counts into its own LDS column
-// (bins[k][lane]) so increments never collide, then lane k sums bin k over
-// the 64 columns with a rotated start to stay free of bank conflicts.
-// Loads are aligned 16-byte chunks; bytes outside the row are masked.
+// One wavefront per row (RPW rows per wavefront per job); every lane counts
+// into its own LDS column (bins[k][lane]) so increments never collide, with
+// one extra bin that absorbs unreachable entries (-1 read as 255), which
+// keeps the per-byte work branch-free. Lane k then sums bin k over the 64
+// columns with a rotated start, free of bank conflicts.
+// Loads are aligned 16-byte chunks; only chunks that straddle the row's ends
+// check bytes against the row.
 // ===========================================================================
 
-template <int K, int WAVES>
+template <int K, int WAVES, int RPW>
 __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict__ graphs,
                                                      const NodeJob *__restrict__ jobs)
 {
-    __shared__ uint32_t bins[WAVES][K][64];
+    __shared__ uint32_t bins[WAVES][K + 1][64];
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
     const int wave = threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
-    const int row = job.i0 + wave;
-    const bool active = row < n;
+    const int8_t *__restrict__ base = G.dist;
+    const int64_t total = (int64_t)n * n;
+    const bool vec_ok = total >= 16;
+    const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
+    const u32x4 z4 = {0u, 0u, 0u, 0u};
 
+    for (int rr = 0; rr < RPW; ++rr) {
+        const int row = job.i0 + rr * WAVES + wave;
+        const bool active = row < n;
 #pragma unroll
-    for (int k = 0; k < K; ++k) bins[wave][k][lane] = 0;
-
-    if (active) {
-        const int8_t *__restrict__ base = G.dist;
-        const int64_t total = (int64_t)n * n;
-        const int64_t r0 = (int64_t)row * n;
-        const int64_t r1 = r0 + n;
-        const int64_t first = (r0 & ~(int64_t)15) + lane * 16;
-        // Whole 16-byte chunks inside the buffer come from one global load,
-        // the next one in flight; its address is clamped to the buffer's last
-        // whole chunk (no branch), and the buffer's final partial chunk is
-        // read byte by byte. total < 16 never takes the vector path.
-        const bool vec_ok = total >= 16;
-        const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
-        const u32x4 z4 = {0u, 0u, 0u, 0u};
-        u32x4 cur = vec_ok ? *(global_u4)(base + min(first, last_whole)) : z4;
-        for (int64_t c = first; c < r1; c += 64 * 16) {
-            const u32x4 ahead = vec_ok ? *(global_u4)(base + min(c + 64 * 16, last_whole)) : z4;
-            if (c + 16 <= total) {
-                const uint32_t wv[4] = {cur.x, cur.y, cur.z, cur.w};
-                const bool inside = (c >= r0) && (c + 16 <= r1);
+        for (int k = 0; k <= K; ++k) bins[wave][k][lane] = 0;
+        if (active) {
+            const int64_t r0 = (int64_t)row * n;
+            const int64_t r1 = r0 + n;
+            const int64_t first = (r0 & ~(int64_t)15) + lane * 16;
+            // the next chunk is in flight; its address is clamped to the
+            // buffer's last whole chunk (no branch); total < 16 never loads
+            u32x4 cur = vec_ok ? *(global_u4)(base + min(first, last_whole)) : z4;
+            for (int64_t c = first; c < r1; c += 64 * 16) {
+                const u32x4 ahead = vec_ok ? *(global_u4)(base + min(c + 64 * 16, last_whole)) : z4;
+                if (c >= r0 && c + 16 <= r1) {
+                    // whole chunk inside the row (and so inside the buffer)
+                    const uint32_t wv[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
-                for (int p = 0; p < 16; ++p) {
-                    const int d = (int)(int8_t)((wv[p / 4] >> (8 * (p % 4))) & 0xFFu);
-                    const int64_t f = c + p;
-                    if ((inside || (f >= r0 && f < r1)) && d >= 0 && d < K)
-                        __hip_atomic_fetch_add(&bins[wave][d][lane], 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    for (int p = 0; p < 16; ++p) {
+                        const uint32_t u = (wv[p / 4] >> (8 * (p % 4))) & 0xFFu;
+                        __hip_atomic_fetch_add(&bins[wave][min(u, (uint32_t)K)][lane], 1u,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                } else {
+                    for (int64_t f = max(c, r0); f < c + 16 && f < r1; ++f) {
+                        const uint32_t u = (uint32_t)(uint8_t)base[f];
+                        __hip_atomic_fetch_add(&bins[wave][min(u, (uint32_t)K)][lane], 1u,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                 }
-            } else {
-                for (int64_t f = c; f < c + 16 && f < total; ++f) {
-                    const int d = (int)base[f];
-                    if (f >= r0 && f < r1 && d >= 0 && d < K)
-                        __hip_atomic_fetch_add(&bins[wave][d][lane], 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
+                cur = ahead;
             }
-            cur = ahead;
         }
-    }
-    __syncthreads();
-    if (active) {
-        int32_t *__restrict__ h = G.hist + (int64_t)row * G.K;
-        for (int k = lane; k < K; k += 64) {
-            uint32_t s = 0;
-            for (int l = 0; l < 64; ++l) s += bins[wave][k][(l + k) & 63];
-            h[k] = (int32_t)s;
+        __syncthreads();
+        if (active) {
+            int32_t *__restrict__ h = G.hist + (int64_t)row * G.K;
+            for (int k = lane; k < K; k += 64) {
+                uint32_t sum = 0;
+                for (int l = 0; l < 64; ++l) sum += bins[wave][k][(l + k) & 63];
+                h[k] = (int32_t)sum;
+            }
+            for (int k = K + lane; k < G.K; k += 64) h[k] = 0;
         }
-        for (int k = K + lane; k < G.K; k += 64) h[k] = 0;
+        __syncthreads();
     }
 }
 
@@ -103,9 +103,9 @@ hipError_t launch_hist(int K, const GraphDev *graphs, const NodeJob *jobs, int n
 {
     if (n_jobs <= 0) return hipSuccess;
     switch (K) {
-    case 32: hipLaunchKernelGGL((k_hist<32, 8>), dim3(n_jobs), dim3(512), 0, stream, graphs, jobs); break;
-    case 64: hipLaunchKernelGGL((k_hist<64, 8>), dim3(n_jobs), dim3(512), 0, stream, graphs, jobs); break;
-    case 128: hipLaunchKernelGGL((k_hist<128, 4>), dim3(n_jobs), dim3(256), 0, stream, graphs, jobs); break;
+    case 32: hipLaunchKernelGGL((k_hist<32, 8, 4>), dim3(n_jobs), dim3(512), 0, stream, graphs, jobs); break;
+    case 64: hipLaunchKernelGGL((k_hist<64, 4, 8>), dim3(n_jobs), dim3(256), 0, stream, graphs, jobs); break;
+    case 128: hipLaunchKernelGGL((k_hist<128, 2, 16>), dim3(n_jobs), dim3(128), 0, stream, graphs, jobs); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -222,6 +222,86 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
     }
 }
 
+// BF16 matrix-core variant: for 16 nodes at a time, the histogram tile
+// (16 nodes x 32 bins, BF16) times the weight tile (32 bins x 16 columns: for
+// 8 sigmas the psi weights w_k and the V numerator weights k^2 w_k / a, BF16)
+// accumulated in FP32 by v_mfma_f32_16x16x32_bf16. BF16 keeps 8 significant
+// bits, so psi and V carry about 1e-3 relative error: an approximate sweep,
+// never used for the descent. One wavefront per 16-node tile; each job of
+// kNodesPerJob nodes is 16 tiles handled by 4 wavefronts.
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short f32_to_bf16(float f)
+{
+    // round to nearest even (counts and weights are finite and >= 0)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_potential_bf16(const GraphDev *__restrict__ graphs,
+                                                        const NodeJob *__restrict__ jobs,
+                                                        float *__restrict__ psi_out,
+                                                        float *__restrict__ v_out, int64_t out_ld)
+{
+    const NodeJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int S = G.n_sigmas;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int row = lane % 16, quad = lane / 16;
+    for (int tile = wave; tile < kNodesPerJob / 16; tile += 4) {
+        const int node0 = job.i0 + tile * 16;
+        if (node0 >= n) break;
+        // A fragments: lane holds bins 8*quad .. 8*quad+7 of node node0+row
+        bf16x8 a[K / 32];
+        const int na = node0 + row;
+#pragma unroll
+        for (int kc = 0; kc < K / 32; ++kc) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = kc * 32 + quad * 8 + t;
+                const float h = (na < n) ? (float)G.hist[(int64_t)na * G.K + k] : 0.f;
+                a[kc][t] = f32_to_bf16(h);
+            }
+        }
+        // 16 output columns per step: sigma = col / 2, (psi, numerator) = col % 2
+        for (int c0 = 0; c0 < 2 * S; c0 += 16) {
+            const int col = c0 + row;
+            const int s = col / 2, kind = col % 2;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < K / 32; ++kc) {
+                bf16x8 b;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int k = kc * 32 + quad * 8 + t;
+                    b[t] = (s < S) ? (short)G.wbf16[((int64_t)s * G.K + k) * 2 + kind] : (short)0;
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc], b, acc, 0, 0, 0);
+            }
+            // lane holds D[4*quad + r][col]; the numerator sits in the next lane
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float num = __shfl_xor(acc[r], 1);
+                const int node = node0 + 4 * quad + r;
+                if (kind == 0 && s < S && node < n) {
+                    const float psi = acc[r];
+                    const float v = num / psi;
+                    const int64_t o = (int64_t)s * n + node;
+                    G.psi[o] = psi;
+                    G.v[o] = v;
+                    const int64_t ou = job.out_off + (int64_t)s * out_ld + node;
+                    if (psi_out) psi_out[ou] = psi;
+                    if (v_out) v_out[ou] = v;
+                }
+            }
+        }
+    }
+}
+
 hipError_t launch_potential(int precision, int K, const GraphDev *graphs, const NodeJob *jobs,
                             int n_jobs, float *psi_out, float *v_out, int64_t out_ld,
                             hipStream_t stream)
@@ -234,6 +314,13 @@ hipError_t launch_potential(int precision, int K, const GraphDev *graphs, const 
         case 32: hipLaunchKernelGGL((k_potential<32, 0>), QC_POT_ARGS); break;
         case 64: hipLaunchKernelGGL((k_potential<64, 0>), QC_POT_ARGS); break;
         case 128: hipLaunchKernelGGL((k_potential<128, 0>), QC_POT_ARGS); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else if (precision == 2) {
+        switch (K) {
+        case 32: hipLaunchKernelGGL((k_potential_bf16<32>), QC_POT_ARGS); break;
+        case 64: hipLaunchKernelGGL((k_potential_bf16<64>), QC_POT_ARGS); break;
+        case 128: hipLaunchKernelGGL((k_potential_bf16<128>), QC_POT_ARGS); break;
         default: return hipErrorInvalidValue;
         }
     } else if (precision == 1) {
@@ -290,52 +377,55 @@ __device__ __forceinline__ double fp64_v(const GraphDev &G, int s, int node)
 __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev *__restrict__ graphs,
                                                     const NodeJob *__restrict__ jobs, int sigma_base)
 {
+    // blockIdx.y is the sigma: the blocks in flight share one sigma, so the
+    // gathered V values (one FP32 plane per sigma, a few MB for a whole
+    // batch) stay in L2 while the neighbour lists stream past.
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
     const int s = sigma_base + (int)blockIdx.y;
     const int i = job.i0 + (int)threadIdx.x;
-    if (i >= n || s >= G.n_sigmas) return;
-    const float *__restrict__ V = G.v + (int64_t)s * n;
-    const int32_t *__restrict__ col = G.col;
-    const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
-    const float vi = V[i];
-
-    float m1 = FLT_MAX, m2 = FLT_MAX;
-    int j1 = -1;
-    for (int e = e0; e < e1; ++e) {
-        const int j = col[e];
-        const float vj = V[j];
-        if (vj < m1) { m2 = m1; m1 = vj; j1 = j; }
-        else if (vj < m2) m2 = vj;
-    }
-    int parent = i;
     bool rechecked = false;
-    if (j1 >= 0) {
-        const float tau = kTieTau;
-        bool ambiguous = (m2 - m1 <= tau * m2);
-        const float hi = fmaxf(m1, vi), lo = fminf(m1, vi);
-        if (hi - lo <= tau * hi) ambiguous = true;
-        if (!ambiguous) {
-            parent = (m1 < vi) ? j1 : i;
-        } else {
-            const double vi64 = fp64_v(G, s, i);
-            double bv = DBL_MAX;
-            int best = -1;
-            for (int e = e0; e < e1; ++e) {
-                const int j = col[e];
-                const float vj = V[j];
-                if (vj - m1 <= tau * vj) {
-                    const double d = fp64_v(G, s, j);
-                    if (d < bv) { bv = d; best = j; }
-                }
-            }
-            if (tie_mode == 0) parent = (bv < vi64) ? best : i;
-            else parent = (bv < vi64 || (bv == vi64 && best < i)) ? best : i;
-            rechecked = true;
+    if (i < n && s < G.n_sigmas) {
+        const float *__restrict__ V = G.v + (int64_t)s * n;
+        const int32_t *__restrict__ col = G.col;
+        const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
+        const float vi = V[i];
+        float m1 = FLT_MAX, m2 = FLT_MAX;
+        int j1 = -1;
+        for (int e = e0; e < e1; ++e) {
+            const int j = col[e];
+            const float vj = V[j];
+            if (vj < m1) { m2 = m1; m1 = vj; j1 = j; }
+            else if (vj < m2) m2 = vj;
         }
+        int parent = i;
+        if (j1 >= 0) {
+            const float tau = kTieTau;
+            bool ambiguous = (m2 - m1 <= tau * m2);
+            const float hi = fmaxf(m1, vi), lo = fminf(m1, vi);
+            if (hi - lo <= tau * hi) ambiguous = true;
+            if (!ambiguous) {
+                parent = (m1 < vi) ? j1 : i;
+            } else {
+                const double vi64 = fp64_v(G, s, i);
+                double bv = DBL_MAX;
+                int best = -1;
+                for (int e = e0; e < e1; ++e) {
+                    const int j = col[e];
+                    const float vj = V[j];
+                    if (vj - m1 <= tau * vj) {
+                        const double d = fp64_v(G, s, j);
+                        if (d < bv) { bv = d; best = j; }
+                    }
+                }
+                if (tie_mode == 0) parent = (bv < vi64) ? best : i;
+                else parent = (bv < vi64 || (bv == vi64 && best < i)) ? best : i;
+                rechecked = true;
+            }
+        }
+        G.parent[(int64_t)s * n + i] = parent;
     }
-    G.parent[(int64_t)s * n + i] = parent;
     // one counter update per wavefront
     const unsigned long long m = __ballot(rechecked);
     if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1))

@@ -240,6 +240,7 @@ int64_t qc_request_footprint(int32_t n, int64_t nnz, int32_t n_sigmas)
     add(8 * S * K);                   // u64
     add(8 * S);                       // 1/a
     add(16 * S * K);                  // FP32 split weights
+    add(4 * S * K);                   // BF16 weights
     add(4 * N * S);                   // labels
     return b;
 }

@@ -38,7 +38,7 @@ EXPORTED = [
     "qc_status_str", "qc_device_count", "qc_graph_create", "qc_graph_destroy",
     "qc_graph_info", "qc_distances", "qc_get_histograms", "qc_potential",
     "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync", "qc_timing_enable",
-    "qc_timing_read",
+    "qc_timing_read", "qc_potential_dense",
     "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
     "qc_batch_destroy",
 ]
@@ -67,7 +67,8 @@ STAGE_HIST = 1
 STAGE_POTENTIAL = 2
 STAGE_GGD = 3
 STAGE_JUMP = 4
-STAGE_NAMES = ["bfs", "hist", "potential", "ggd_parent", "pointer_jump"]
+STAGE_DENSE = 5
+STAGE_NAMES = ["bfs", "hist", "potential", "ggd_parent", "pointer_jump", "dense"]
 
 
 class QCError(RuntimeError):
@@ -106,6 +107,7 @@ def lib():
         L.qc_graph_sync.argtypes = [P, P]
         L.qc_timing_enable.argtypes = [I32]
         L.qc_timing_read.argtypes = [I32, P, P]
+        L.qc_potential_dense.argtypes = [P, I64, I64, I64, P, I32, P, P, P]
         L.qc_batch_create.argtypes = [P, I32, P, I32, U32, U32, P, P]
         L.qc_batch_node_offsets.argtypes = [P, P]
         L.qc_batch_run.argtypes = [P, P, P, P, P]
@@ -390,6 +392,33 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def potential_dense(dist, sigmas, n_cols=None, psi=None, v=None, stream=None):
+    """Algorithm 1 on a dense float32 CUDA matrix of distances (rows = nodes;
+    negative = no path). `dist` may be a row-strided view (stride(1) == 1);
+    `n_cols` defaults to its width. Returns FP64 (psi, V), each [S, n_rows]."""
+    import torch
+    if not dist.is_cuda or dist.dtype != torch.float32 or dist.dim() != 2 or dist.stride(1) != 1:
+        raise ValueError("expected a CUDA float32 matrix with unit column stride")
+    n_rows, width = dist.shape
+    n_cols = width if n_cols is None else int(n_cols)
+    if not 0 <= n_cols <= width:
+        raise ValueError("n_cols outside the matrix")
+    sig = np.ascontiguousarray(sigmas, dtype=np.float64)
+    shape = (sig.shape[0], n_rows)
+    if psi is None:
+        psi = torch.empty(shape, dtype=torch.float64, device=dist.device)
+    if v is None:
+        v = torch.empty(shape, dtype=torch.float64, device=dist.device)
+    Graph._check_tensor(psi, shape, "float64")
+    Graph._check_tensor(v, shape, "float64")
+    ld = dist.stride(0) if n_rows > 1 else max(width, 1)
+    st = lib().qc_potential_dense(_dptr(dist), int(n_rows), int(n_cols), int(ld),
+                                  sig.ctypes.data_as(ctypes.c_void_p), int(sig.shape[0]),
+                                  _dptr(psi), _dptr(v), _stream_ptr(stream))
+    _check(st, "qc_potential_dense")
+    return psi, v
 
 
 def cluster(g, sigmas, tie_mode=TIE_STRICT, precision=PREC_FP64ACC, dist_out=None):

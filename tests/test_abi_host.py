@@ -116,3 +116,29 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(qc, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         qc.lib()
+
+
+def test_dense_potential_arguments_checked_on_host():
+    """qc_potential_dense validates sizes and widths before touching a device."""
+    L = qc.lib()
+    sig = np.array([1.0], dtype=np.float64)
+    sp = sig.ctypes.data_as(ctypes.c_void_p)
+    fake = ctypes.c_void_p(4096)      # never dereferenced: every call below fails validation
+    bad = [
+        (fake, -1, 4, 4, sp, 1, fake, fake),       # negative rows
+        (fake, 4, -1, 4, sp, 1, fake, fake),       # negative columns
+        (fake, 4, 8, 4, sp, 1, fake, fake),        # ld < n_cols
+        (fake, 4, 4, 4, None, 1, fake, fake),      # no sigmas
+        (fake, 4, 4, 4, sp, 0, fake, fake),        # zero sigmas
+        (None, 4, 4, 4, sp, 1, fake, fake),        # no matrix
+        (fake, 4, 4, 4, sp, 1, None, fake),        # no psi
+        (fake, 4, 4, 4, sp, 1, fake, None),        # no V
+    ]
+    for args in bad:
+        assert L.qc_potential_dense(*args, None) == qc.QC_E_INVAL, args
+    for s in (0.0, -1.0, float("nan"), float("inf"), 1e-101):
+        sig[0] = s
+        assert L.qc_potential_dense(fake, 4, 4, 4, sp, 1, fake, fake, None) == qc.QC_E_INVAL, s
+    sig[0] = 1.0
+    assert L.qc_potential_dense(None, 0, 4, 4, sp, 1, None, None, None) == qc.QC_OK   # no rows
+    assert L.qc_potential_dense(fake, 4, 4, 4, sp, 1, fake, fake, None) == qc.QC_E_DEVICE

@@ -1,0 +1,86 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times:
+
+* the batched sigma sweep (64 graphs, 32 sigmas, HIP-graph replay): for a
+  spread of graphs including the largest, every histogram, psi/V and label
+  against the oracle, and sampled distance rows;
+* the serving stream: requests of the stream as drawn (largest included),
+  labels and potentials against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_14641_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_err(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    zero = want == 0
+    assert (got[zero] == 0).all()
+    return float((np.abs(got - want)[~zero] / np.abs(want[~zero])).max()) if (~zero).any() else 0.0
+
+
+def test_batched_sweep_full_size():
+    import torch
+    from paper_2305_14641_amd import qc
+    graphs = gg.config4()
+    sigmas = gg.sigmas_c4()
+    handles = [qc.Graph.from_graph(g) for g in graphs]
+    b = qc.Batch(handles, sigmas, tie_mode=qc.TIE_STRICT, hipgraph=True)
+    psi, v, lab = b.outputs()
+    b.run(psi, v, lab)
+    b.run(psi, v, lab)          # a replay, as the benchmark times it
+    torch.cuda.synchronize()
+    psi, v, lab = psi.cpu().numpy(), v.cpu().numpy(), lab.cpu().numpy()
+    largest = int(np.argmax([g.n for g in graphs]))
+    pick = sorted({0, 9, 21, 38, 50, 63, largest})
+    print(f"[gpu] batched sweep full size: checking graphs {pick}", flush=True)
+    for gi in pick:
+        g, G = graphs[gi], handles[gi]
+        o0, o1 = b.offsets[gi], b.offsets[gi + 1]
+        hist = G.histograms().cpu().numpy()
+        ref_hist, ref_dmax = oracle.hist_all(g.n, g.row_ptr, g.col, hist.shape[1])
+        np.testing.assert_array_equal(hist, ref_hist)
+        for s, sigma in enumerate(sigmas):
+            psi_c, v_c = oracle.potential_canonical(ref_hist, sigma)
+            assert rel_err(psi[s, o0:o1], psi_c) <= 1e-6
+            assert rel_err(v[s, o0:o1], v_c) <= 1e-6
+            ref_lab = oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v_c, 0))
+            np.testing.assert_array_equal(lab[s, o0:o1], ref_lab, err_msg=f"graph {gi} sigma {sigma}")
+        # sampled distance rows, recomputed by the same kernel into a buffer
+        dist = torch.empty((g.n, g.n), dtype=torch.int8, device="cuda")
+        assert G.distances(dist) == ref_dmax
+        rows = np.random.default_rng(gi).choice(g.n, 16, replace=False).astype(np.int32)
+        ref_rows, _ = oracle.bfs_rows(g.n, g.row_ptr, g.col, rows)
+        got = dist[torch.as_tensor(rows.astype(np.int64), device="cuda")].cpu().numpy()
+        np.testing.assert_array_equal(got, ref_rows)
+        del dist
+    b.close()
+
+
+def test_serving_stream_full_size():
+    from paper_2305_14641_amd import qc
+    ids = list(range(48))
+    sizes = [gg.config5_request(r)["n"] for r in ids]
+    largest = int(np.argmax([gg.config5_request(r)["n"] for r in range(1024)]))
+    chosen = sorted(set([ids[int(np.argmax(sizes))], 3, 17, largest]))
+    reqs = [(r,) + gg.config5_graph(r) for r in chosen]
+    print(f"[gpu] serving full size: requests {chosen}, n={[g.n for _, g, _ in reqs]}", flush=True)
+    srv = qc.Server(max_slots=4, hbm_budget_bytes=32 << 30, want_potentials=True)
+    handles = [srv.submit(g.n, g.row_ptr, g.col, sig) for _, g, sig in reqs]
+    for (r, g, sig), h in zip(reqs, handles):
+        labels, psi, v, info = srv.wait(h)
+        ref_hist, ref_dmax = oracle.hist_all(g.n, g.row_ptr, g.col, 128)
+        assert info["dmax"] == ref_dmax
+        ref_hist = np.ascontiguousarray(ref_hist[:, :ref_dmax + 1])
+        for s, sigma in enumerate(sig):
+            psi_c, v_c = oracle.potential_canonical(ref_hist, sigma)
+            assert rel_err(psi[s], psi_c) <= 1e-6
+            assert rel_err(v[s], v_c) <= 1e-6
+            ref_lab = oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v_c, 0))
+            np.testing.assert_array_equal(labels[s], ref_lab, err_msg=f"request {r} sigma {sigma}")
+    srv.close()

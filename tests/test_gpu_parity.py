@@ -239,3 +239,27 @@ def test_recheck_counts_exact_ties(torch_cuda):
     lab = G.labels(0, qc.TIE_STRICT).cpu().numpy()
     assert G.recheck_count() >= 1
     assert lab[0] == 1 and (lab[1:] == np.arange(1, 51)).all()
+
+
+def test_bf16_sweep_error_and_refusal(torch_cuda):
+    """The BF16 matrix-core sweep: about 1e-3 relative error vs FP64 (BF16
+    keeps 8 significant bits), and the descent refuses its potentials."""
+    from paper_2305_14641_amd import qc
+    g = gg.config2()
+    sig = gg.SIGMAS_C2 + [0.25, 8.0]
+    G = qc.Graph.from_graph(g)
+    psi, v = G.potential(sig, precision=qc.PREC_BF16)
+    hist = G.histograms().cpu().numpy()
+    psi, v = psi.cpu().numpy(), v.cpu().numpy()
+    worst = 0.0
+    for s, sigma in enumerate(sig):
+        psi_c, v_c = oracle.potential_canonical(hist, sigma)
+        worst = max(worst, rel_err(psi[s], psi_c), rel_err(v[s], v_c))
+    print(f"[gpu] bf16 sweep worst relative error {worst:.2e}", flush=True)
+    assert worst < 1.5e-2
+    with pytest.raises(qc.QCError) as e:
+        G.labels(0)
+    assert e.value.status == qc.QC_E_STATE
+    G.potential(sig)                 # FP64 again: the descent works
+    G.labels(0)
+    G.sync()
