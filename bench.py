@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # vector lane-operations/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
 def log(msg):
@@ -194,6 +195,23 @@ def quality_sweep(qc, gg, torch) -> dict:
             "rows": rows}
 
 
+DENSE_PROFILE = os.path.join(ROOT, "profiles", "k_dense_fully_connected_n20000.json")
+
+
+def dense_profile(kernel: str):
+    """Counter figures per launch of one dense-kernel instance from the
+    committed summary, while the kernel source is unchanged since then."""
+    import hashlib
+    try:
+        prof = json.load(open(DENSE_PROFILE))
+        src = os.path.join(ROOT, "paper_2305_14641_amd", "csrc", "qc_dense.hip")
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != prof["kernel_source_sha256"]:
+            return None
+        return prof["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def dense_leg(args, qc, torch) -> dict:
     """Algorithm 1 on a fully connected graph with float distances (the
     paper's GPU experiment shape): one pass for one width (HBM-bound) and for
@@ -212,19 +230,38 @@ def dense_leg(args, qc, torch) -> dict:
         for _ in range(2):
             qc.potential_dense(d, sig, psi=psi, v=v)
         torch.cuda.synchronize()
-        qc.timing_enable(True)
+        # back-to-back launches on the current stream (the launch stream),
+        # bracketed by one pair of HIP events
         reps = max(args.steps, 3)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(reps):
             qc.potential_dense(d, sig, psi=psi, v=v)
+        e1.record()
         torch.cuda.synchronize()
-        ms, cnt = qc.timing_read(qc.STAGE_DENSE)
-        qc.timing_enable(False)
-        per = ms / reps
+        per = e0.elapsed_time(e1) / reps
+        launches = (S + 7) // 8
         terms = float(n) * n * S
-        gbs = 4.0 * n * n / (per * 1e-3) / 1e9
-        out[f"s{S}"] = {"ms": per, "launches": cnt / reps, "pair_terms_per_s": terms / (per * 1e-3),
-                        "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        alg = 4.0 * n * n * launches
+        gbs = alg / (per * 1e-3) / 1e9
+        prof = dense_profile(f"k_dense<{min(S, 8)}, true>")
+        traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
+        hbm = {"bound": "hbm", "kernel": f"k_dense<{min(S, 8)}>", "achieved": gbs,
+               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+               "algorithmic_bytes_per_launch": 4.0 * n * n}
+        alu = None
+        if prof:
+            # VALU lane-operations per second against the vector issue rate
+            # (256 CUs x 64 lanes x 2.4 GHz, no packed math)
+            ops = prof["valu_wave_instructions_per_launch"] * 64 * launches / (per * 1e-3) / 1e12
+            alu = {"bound": "alu", "kernel": f"k_dense<{min(S, 8)}>", "achieved": ops,
+                   "peak": VALU_PEAK_TOPS, "unit": "T VALU lane-ops/s", "frac": ops / VALU_PEAK_TOPS,
+                   "valu_wave_instructions_per_launch": prof["valu_wave_instructions_per_launch"]}
+        out[f"s{S}"] = {"ms": per, "launches": launches, "pair_terms_per_s": terms / (per * 1e-3),
+                        "roofline": hbm if S == 1 else (alu or hbm), "other_bound": alu if S == 1 else hbm}
         log(f"dense S={S}: {per:.3f} ms, {terms / (per * 1e-3):.3e} pair-terms/s, {gbs:.0f} GB/s")
+        del psi, v
     if not args.no_cpu_baseline:
         import oracle
         rows = d[:256].cpu().numpy()

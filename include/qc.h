@@ -43,7 +43,7 @@ typedef int32_t qc_status;
 enum {
     QC_OK = 0,
     QC_E_INVAL = 1,         /* NULL pointer, size out of range, sigma <= 0 or not finite */
-    QC_E_NOT_SYMMETRIC = 2, /* CSR not symmetric, unsorted, duplicated, or with self-loops */
+    QC_E_NOT_SYMMETRIC = 2, /* CSR not canonical: unsorted, duplicated, self-loops, or (undirected) asymmetric */
     QC_E_OOM = 3,           /* device or pinned-host allocation failed */
     QC_E_DEVICE = 4,        /* no gfx950 device visible, or a HIP call failed */
     QC_E_OVERFLOW = 5,      /* a finite hop distance above 126 */
@@ -68,7 +68,8 @@ enum { QC_PREC_FP64ACC = 0, QC_PREC_FP32C = 1, QC_PREC_BF16 = 2 };
 
 /* qc_graph_create flags. */
 enum {
-    QC_GRAPH_CANONICALIZE = 1u /* symmetrise, sort, drop duplicates and self-loops first */
+    QC_GRAPH_CANONICALIZE = 1u, /* sort, drop duplicates and self-loops (and, undirected, symmetrise) first */
+    QC_GRAPH_DIRECTED = 2u      /* rows are out-neighbours; distances follow edge direction */
 };
 
 typedef struct qc_graph_s *qc_graph;
@@ -83,13 +84,20 @@ qc_status qc_device_count(int32_t *count_out);
  * Create a graph handle from a CSR adjacency (the adjacency matrix of
  * Algorithm 1's input, stored sparsely).
  *   n        number of nodes, 1 <= n <= 65536
- *   nnz      number of stored entries (2 x undirected edges), 0 <= nnz < 2^31
+ *   nnz      number of stored entries (2 x undirected edges, or the directed
+ *            edges), 0 <= nnz < 2^31
  *   row_ptr  host, int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
  *   col_idx  host, int32[nnz], neighbours of node i in row_ptr[i]..row_ptr[i+1]-1
  *   flags    0: the CSR must already be canonical (each row strictly
  *            increasing, no self-loop, (i,j) present iff (j,i) present),
  *            else QC_E_NOT_SYMMETRIC; QC_GRAPH_CANONICALIZE: the library
  *            canonicalises a copy first (the input is left unchanged).
+ *            QC_GRAPH_DIRECTED: row i lists the heads of the edges leaving
+ *            i (no symmetry required; canonical = sorted rows, no duplicate,
+ *            no self-loop). Distances are then directed: d(i,j) is the
+ *            length of a shortest path from i to j along edge directions,
+ *            row i of the matrix holds the distances from i, and the descent
+ *            moves a node only to one of its out-neighbours.
  *   stream   stream for the upload
  *   out      host, receives the handle (unchanged on error)
  * The library copies the CSR; the caller keeps ownership of its arrays.
@@ -102,7 +110,8 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
 qc_status qc_graph_destroy(qc_graph g);
 
 /* Sizes of a handle: any output pointer may be NULL. dmax is -1 until the
- * first qc_distances / qc_potential has run. */
+ * first qc_distances / qc_potential has run. n_components counts connected
+ * components (weakly connected ones for a directed graph). */
 qc_status qc_graph_info(qc_graph g, int32_t *n, int64_t *nnz, int32_t *dmax,
                         int32_t *n_components);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -25,16 +26,25 @@ qc_status from_hip(hipError_t e)
 
 qc_status check_device(int *dev_out)
 {
+    // The architecture of each device is looked up once (device properties
+    // are slow to query) and cached; 0 unknown, 1 gfx950, 2 other.
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> arch[kMaxDevices];
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
         (void)hipGetLastError();
         return QC_E_DEVICE;
     }
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return QC_E_DEVICE;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return QC_E_DEVICE;
-    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return QC_E_DEVICE;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return QC_E_DEVICE;
+    int a = arch[dev].load(std::memory_order_relaxed);
+    if (a == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return QC_E_DEVICE;
+        a = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+        arch[dev].store(a, std::memory_order_relaxed);
+    }
+    if (a != 1) return QC_E_DEVICE;
     *dev_out = dev;
     return QC_OK;
 }
@@ -204,7 +214,7 @@ const char *qc_status_str(qc_status s)
     switch (s) {
     case QC_OK: return "QC_OK";
     case QC_E_INVAL: return "QC_E_INVAL: invalid argument";
-    case QC_E_NOT_SYMMETRIC: return "QC_E_NOT_SYMMETRIC: CSR is not a canonical undirected adjacency";
+    case QC_E_NOT_SYMMETRIC: return "QC_E_NOT_SYMMETRIC: CSR is not a canonical adjacency";
     case QC_E_OOM: return "QC_E_OOM: out of device memory";
     case QC_E_DEVICE: return "QC_E_DEVICE: no gfx950 device or a HIP call failed";
     case QC_E_OVERFLOW: return "QC_E_OVERFLOW: a finite hop distance exceeds 126";
@@ -249,9 +259,11 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
                        qc_graph *out)
 {
     if (!out) return QC_E_INVAL;
-    if (flags & ~(uint32_t)QC_GRAPH_CANONICALIZE) return QC_E_INVAL;
+    if (flags & ~(uint32_t)(QC_GRAPH_CANONICALIZE | QC_GRAPH_DIRECTED)) return QC_E_INVAL;
+    const bool directed = (flags & QC_GRAPH_DIRECTED) != 0;
     std::vector<int32_t> rp, col;
-    QC_TRY(validate_csr(n, nnz, row_ptr, col_idx, (flags & QC_GRAPH_CANONICALIZE) != 0, rp, col));
+    QC_TRY(validate_csr(n, nnz, row_ptr, col_idx, (flags & QC_GRAPH_CANONICALIZE) != 0, rp, col,
+                        directed));
     int dev = 0;
     QC_TRY(check_device(&dev));
 
@@ -261,13 +273,11 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     g->bump_size = region_bytes;
     g->n = n;
     g->nnz = (int64_t)col.size();
+    // (weakly) connected components: a source reaches at most its component,
+    // exactly all of it when the graph is undirected (the BFS's stop target)
     g->n_components = count_components(n, rp, col, &g->comp_size);
 
-    // packed edges, padded with no-op (0, 0) entries to a multiple of 4
-    std::vector<uint32_t> edges(((g->nnz + 3) / 4) * 4 + 4, 0u);
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
-            edges[e] = ((uint32_t)i << 16) | (uint32_t)col[e];
+    const std::vector<uint32_t> edges = pack_in_edges(n, rp, col, directed);
     std::vector<NodeJob> njobs;
     for (int i = 0; i < n; i += kNodesPerJob) njobs.push_back(NodeJob{0, i, 0});
     g->n_node_jobs = (int)njobs.size();

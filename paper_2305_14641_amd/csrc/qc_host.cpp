@@ -13,7 +13,7 @@ namespace qc {
 
 qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
                        bool canonicalize, std::vector<int32_t> &rp_out,
-                       std::vector<int32_t> &col_out)
+                       std::vector<int32_t> &col_out, bool directed)
 {
     if (n < 1 || n > kMaxNodes) return QC_E_INVAL;
     if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return QC_E_INVAL;
@@ -32,7 +32,7 @@ qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
                 const int32_t j = col[e];
                 if (j == i) continue;
                 adj[i].push_back(j);
-                adj[j].push_back(i);
+                if (!directed) adj[j].push_back(i);
             }
         rp_out.assign(n + 1, 0);
         col_out.clear();
@@ -53,7 +53,7 @@ qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
             if (e > row_ptr[i] && col[e] <= col[e - 1]) return QC_E_NOT_SYMMETRIC;
         }
     }
-    for (int32_t i = 0; i < n; ++i) {
+    for (int32_t i = 0; i < n && !directed; ++i) {
         for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
             const int32_t j = col[e];
             if (!std::binary_search(col + row_ptr[j], col + row_ptr[j + 1], i))
@@ -63,6 +63,28 @@ qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     rp_out.assign(row_ptr, row_ptr + n + 1);
     col_out.assign(col, col + nnz);
     return QC_OK;
+}
+
+std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
+                                    const std::vector<int32_t> &col, bool directed)
+{
+    const int64_t nnz = (int64_t)col.size();
+    std::vector<uint32_t> edges(((nnz + 3) / 4) * 4 + 4, 0u);
+    if (!directed) {
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+                edges[e] = ((uint32_t)i << 16) | (uint32_t)col[e];
+        return edges;
+    }
+    // transpose: bucket the edges tail -> head by head (counting sort), so a
+    // head's entries are contiguous and its tails ascending
+    std::vector<int64_t> start(n + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) ++start[col[e] + 1];
+    for (int32_t v = 0; v < n; ++v) start[v + 1] += start[v];
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+            edges[start[col[e]]++] = ((uint32_t)col[e] << 16) | (uint32_t)i;
+    return edges;
 }
 
 static int32_t uf_find(std::vector<int32_t> &p, int32_t x)

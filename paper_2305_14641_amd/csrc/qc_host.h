@@ -12,11 +12,19 @@ namespace qc {
 
 // Validate a CSR for qc_graph_create. Returns QC_OK, QC_E_INVAL (pointers,
 // sizes, ranges) or QC_E_NOT_SYMMETRIC (ordering, duplicates, self-loops,
-// asymmetry). With `canonicalize`, only the range checks apply and the
-// canonical form is written to rp_out / col_out.
+// and, unless `directed`, asymmetry). With `canonicalize`, only the range
+// checks apply and the canonical form is written to rp_out / col_out (rows
+// sorted, duplicates and self-loops dropped, symmetrised unless `directed`).
 qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
                        bool canonicalize, std::vector<int32_t> &rp_out,
-                       std::vector<int32_t> &col_out);
+                       std::vector<int32_t> &col_out, bool directed = false);
+
+// Packed in-edge list of a canonical CSR for the BFS pull: one entry
+// (head << 16) | tail per edge tail -> head, heads ascending, padded with
+// no-op (0, 0) entries to a multiple of 4 plus one all-zero quad. For an
+// undirected (symmetric) CSR this is the CSR itself.
+std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
+                                    const std::vector<int32_t> &col, bool directed);
 
 // Number of connected components (union-find over the canonical CSR); if
 // comp_size is given it receives, for every node, the size of its component.

@@ -26,20 +26,32 @@ hipError_t launch_bfs(int bw, int nw, int planes, bool wide, const GraphDev *gra
 
 // ===========================================================================
 // Distance histograms h[i][k] = #{j : d(i,j) = k} from resident int8 rows.
-// One wavefront per row (RPW rows per wavefront per job); every lane counts
-// into its own LDS column (bins[k][lane]) so increments never collide, with
-// one extra bin that absorbs unreachable entries (-1 read as 255), which
-// keeps the per-byte work branch-free. Lane k then sums bin k over the 64
-// columns with a rotated start, free of bank conflicts.
-// Loads are aligned 16-byte chunks; only chunks that straddle the row's ends
-// check bytes against the row.
+// One wavefront per row (RPW rows per wavefront per job). Every lane counts
+// into its own LDS column, so increments never collide; two bins share one
+// 32-bit word as 16-bit halves (a lane sees at most 1,024 bytes of a row of
+// at most 65,536 nodes, so a half cannot overflow), which halves the LDS a
+// wavefront needs and lets four workgroups share a CU. One extra bin absorbs
+// unreachable entries (-1 read as 255), keeping the per-byte work
+// branch-free. Lane k then sums bin k over the 64 columns with a rotated
+// start, free of bank conflicts.
+// Loads are aligned 16-byte chunks, kHistDepth per lane in flight while the
+// previous group is counted (the kernel is bound by HBM latency otherwise);
+// prefetch addresses are clamped to the row's last chunk (and the buffer's
+// last whole one), and only chunks that straddle the row's ends check bytes
+// against the row.
 // ===========================================================================
+
+#ifndef QC_HIST_DEPTH
+#define QC_HIST_DEPTH 4
+#endif
+constexpr int kHistDepth = QC_HIST_DEPTH;
 
 template <int K, int WAVES, int RPW>
 __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict__ graphs,
                                                      const NodeJob *__restrict__ jobs)
 {
-    __shared__ uint32_t bins[WAVES][K + 1][64];
+    constexpr int KW = (K + 2) / 2;   // words holding bins 0..K (K = unreachable)
+    __shared__ uint32_t bins[WAVES][KW][64];
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
@@ -50,38 +62,50 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     const bool vec_ok = total >= 16;
     const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
     const u32x4 z4 = {0u, 0u, 0u, 0u};
+    constexpr int64_t kStep = 64 * 16;   // bytes one wavefront covers per chunk
+
+    auto count = [&](uint32_t u) {
+        const uint32_t b = min(u, (uint32_t)K);
+        __hip_atomic_fetch_add(&bins[wave][b >> 1][lane], 1u << ((b & 1u) * 16u),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
 
     for (int rr = 0; rr < RPW; ++rr) {
         const int row = job.i0 + rr * WAVES + wave;
         const bool active = row < n;
 #pragma unroll
-        for (int k = 0; k <= K; ++k) bins[wave][k][lane] = 0;
+        for (int k = 0; k < KW; ++k) bins[wave][k][lane] = 0;
         if (active) {
             const int64_t r0 = (int64_t)row * n;
             const int64_t r1 = r0 + n;
             const int64_t first = (r0 & ~(int64_t)15) + lane * 16;
-            // the next chunk is in flight; its address is clamped to the
-            // buffer's last whole chunk (no branch); total < 16 never loads
-            u32x4 cur = vec_ok ? *(global_u4)(base + min(first, last_whole)) : z4;
-            for (int64_t c = first; c < r1; c += 64 * 16) {
-                const u32x4 ahead = vec_ok ? *(global_u4)(base + min(c + 64 * 16, last_whole)) : z4;
-                if (c >= r0 && c + 16 <= r1) {
-                    // whole chunk inside the row (and so inside the buffer)
-                    const uint32_t wv[4] = {cur.x, cur.y, cur.z, cur.w};
+            // loads past the row's last chunk re-read that chunk (an L2 hit)
+            const int64_t last_c = min((r1 - 1) & ~(int64_t)15, last_whole);
+            u32x4 cur[kHistDepth];
 #pragma unroll
-                    for (int p = 0; p < 16; ++p) {
-                        const uint32_t u = (wv[p / 4] >> (8 * (p % 4))) & 0xFFu;
-                        __hip_atomic_fetch_add(&bins[wave][min(u, (uint32_t)K)][lane], 1u,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                } else {
-                    for (int64_t f = max(c, r0); f < c + 16 && f < r1; ++f) {
-                        const uint32_t u = (uint32_t)(uint8_t)base[f];
-                        __hip_atomic_fetch_add(&bins[wave][min(u, (uint32_t)K)][lane], 1u,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int u = 0; u < kHistDepth; ++u)
+                cur[u] = vec_ok ? *(global_u4)(base + min(first + u * kStep, last_c)) : z4;
+            for (int64_t c = first; c < r1; c += kHistDepth * kStep) {
+                u32x4 ahead[kHistDepth];
+#pragma unroll
+                for (int u = 0; u < kHistDepth; ++u)
+                    ahead[u] = vec_ok ? *(global_u4)(base + min(c + (kHistDepth + u) * kStep, last_c))
+                                      : z4;
+#pragma unroll
+                for (int u = 0; u < kHistDepth; ++u) {
+                    const int64_t cc = c + u * kStep;
+                    if (cc >= r0 && cc + 16 <= r1) {
+                        // whole chunk inside the row (and so inside the buffer)
+                        const uint32_t wv[4] = {cur[u].x, cur[u].y, cur[u].z, cur[u].w};
+#pragma unroll
+                        for (int p = 0; p < 16; ++p) count((wv[p / 4] >> (8 * (p % 4))) & 0xFFu);
+                    } else if (cc < r1) {
+                        for (int64_t f = max(cc, r0); f < cc + 16 && f < r1; ++f)
+                            count((uint32_t)(uint8_t)base[f]);
                     }
                 }
-                cur = ahead;
+#pragma unroll
+                for (int u = 0; u < kHistDepth; ++u) cur[u] = ahead[u];
             }
         }
         __syncthreads();
@@ -89,7 +113,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
             int32_t *__restrict__ h = G.hist + (int64_t)row * G.K;
             for (int k = lane; k < K; k += 64) {
                 uint32_t sum = 0;
-                for (int l = 0; l < 64; ++l) sum += bins[wave][k][(l + k) & 63];
+                for (int l = 0; l < 64; ++l) sum += (bins[wave][k >> 1][(l + k) & 63] >> ((k & 1) * 16)) & 0xFFFFu;
                 h[k] = (int32_t)sum;
             }
             for (int k = K + lane; k < G.K; k += 64) h[k] = 0;

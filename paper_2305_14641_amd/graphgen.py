@@ -68,6 +68,20 @@ def csr_from_edges(n: int, u: np.ndarray, v: np.ndarray):
     return row_ptr.astype(np.int32), cols
 
 
+def csr_from_arcs(n: int, tail: np.ndarray, head: np.ndarray):
+    """Canonical directed CSR (row = tail, sorted heads, no duplicates, no
+    self-loops) from a list of arcs tail -> head."""
+    tail = np.asarray(tail, dtype=np.int64)
+    head = np.asarray(head, dtype=np.int64)
+    keep = tail != head
+    key = np.unique(tail[keep] * n + head[keep])
+    rows = key // n
+    cols = (key % n).astype(np.int32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    return row_ptr.astype(np.int32), cols
+
+
 def _largest_remainder(fracs: np.ndarray, n: int) -> np.ndarray:
     raw = fracs * n
     sizes = np.floor(raw).astype(np.int64)
@@ -163,6 +177,62 @@ def dcsbm(n: int, block_fracs, mean_degree: float, seed: int, mu: float = 0.8,
     row_ptr, col = csr_from_edges(n, eu, ev)
     return Graph(n, row_ptr, col, blocks,
                  name=f"dcsbm(n={n},blocks={nb},deg={mean_degree:g},seed={seed})")
+
+
+def dcsbm_directed(n: int, block_fracs, mean_out_degree: float, seed: int, mu: float = 0.8,
+                   exponent: float = 2.5) -> Graph:
+    """Directed degree-corrected SBM (citation-like): exactly
+    round(n * mean_out_degree) distinct arcs, tails drawn proportional to an
+    out-weight and heads to an in-weight (both truncated Pareto), the head
+    inside the tail's block with probability mu."""
+    rng = np.random.default_rng(seed)
+    fr = np.asarray(block_fracs, dtype=np.float64)
+    fr = fr / fr.sum()
+    sizes = _largest_remainder(fr, n)
+    blocks = _block_labels(rng, sizes)
+    t_out = _pareto_theta(rng, n, exponent)
+    t_in = _pareto_theta(rng, n, exponent)
+    m_target = int(round(n * mean_out_degree))
+    if m_target > n * (n - 1):
+        raise ValueError("mean out-degree too large for n")
+    cdf_out = np.cumsum(t_out / t_out.sum())
+    cdf_in = np.cumsum(t_in / t_in.sum())
+    nb = len(sizes)
+    members = [np.flatnonzero(blocks == b) for b in range(nb)]
+    cdf_blk = [np.cumsum(t_in[m] / t_in[m].sum()) if len(m) else np.zeros(0) for m in members]
+    keys = np.zeros(0, dtype=np.int64)
+    while keys.shape[0] < m_target:
+        need = m_target - keys.shape[0]
+        draw = int(need * 1.3) + 64
+        u = np.minimum(np.searchsorted(cdf_out, rng.random(draw)), n - 1)
+        inside = rng.random(draw) < mu
+        r = rng.random(draw)
+        v = np.minimum(np.searchsorted(cdf_in, r), n - 1)
+        bu = blocks[u]
+        for b in range(nb):
+            sel = np.flatnonzero(inside & (bu == b))
+            if sel.size and len(members[b]):
+                pos = np.minimum(np.searchsorted(cdf_blk[b], r[sel]), len(members[b]) - 1)
+                v[sel] = members[b][pos]
+        ok = u != v
+        new = u[ok].astype(np.int64) * n + v[ok]
+        _, first = np.unique(new, return_index=True)
+        new = new[np.sort(first)]
+        new = new[~np.isin(new, keys)]
+        keys = np.concatenate([keys, new[:need]])
+    row_ptr, col = csr_from_arcs(n, keys // n, keys % n)
+    return Graph(n, row_ptr, col, blocks,
+                 name=f"dcsbm_directed(n={n},blocks={nb},outdeg={mean_out_degree:g},seed={seed})")
+
+
+def random_digraph(n: int, p: float, seed: int) -> Graph:
+    """Directed Erdos-Renyi graph: each ordered pair an arc with probability p."""
+    rng = np.random.default_rng(seed)
+    a = rng.random((n, n)) < p
+    np.fill_diagonal(a, False)
+    t, h = np.nonzero(a)
+    row_ptr, col = csr_from_arcs(n, t, h)
+    return Graph(n, row_ptr, col, np.zeros(n, dtype=np.int32), name=f"digraph(n={n},p={p},seed={seed})")
 
 
 # ---------------------------------------------------------------------------

@@ -32,6 +32,7 @@ PREC_FP32C = 1
 PREC_BF16 = 2
 
 GRAPH_CANONICALIZE = 1
+GRAPH_DIRECTED = 2
 
 # Every symbol include/qc.h declares (checked by the tests).
 EXPORTED = [
@@ -172,14 +173,16 @@ def _dptr(t):
 class Graph:
     """A graph handle: CSR uploaded once, distances/potentials resident."""
 
-    def __init__(self, n: int, row_ptr, col, canonicalize: bool = False, stream=None):
+    def __init__(self, n: int, row_ptr, col, canonicalize: bool = False, directed: bool = False,
+                 stream=None):
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         c = np.ascontiguousarray(col, dtype=np.int32)
         self._rp, self._col = rp, c
         h = ctypes.c_void_p()
         st = lib().qc_graph_create(
             int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
-            c.ctypes.data_as(ctypes.c_void_p), GRAPH_CANONICALIZE if canonicalize else 0,
+            c.ctypes.data_as(ctypes.c_void_p),
+            (GRAPH_CANONICALIZE if canonicalize else 0) | (GRAPH_DIRECTED if directed else 0),
             _stream_ptr(stream), ctypes.byref(h))
         _check(st, "qc_graph_create")
         self._h = h

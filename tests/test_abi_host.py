@@ -142,3 +142,19 @@ def test_dense_potential_arguments_checked_on_host():
     sig[0] = 1.0
     assert L.qc_potential_dense(None, 0, 4, 4, sp, 1, None, None, None) == qc.QC_OK   # no rows
     assert L.qc_potential_dense(fake, 4, 4, 4, sp, 1, fake, fake, None) == qc.QC_E_DEVICE
+
+
+def test_directed_flag_validation_on_host():
+    """QC_GRAPH_DIRECTED drops only the symmetry requirement; order,
+    duplicates and self-loops are still checked (canonicalisation sorts and
+    dedupes without symmetrising)."""
+    D = qc.GRAPH_DIRECTED
+    arc = (3, [0, 1, 2, 2], [1, 2])                   # 0->1, 1->2: not symmetric
+    assert create(*arc) == qc.QC_E_NOT_SYMMETRIC
+    ok = qc.QC_OK if qc.device_count() > 0 else qc.QC_E_DEVICE
+    assert create(*arc, flags=D) == ok
+    assert create(2, [0, 1, 1], [0], flags=D) == qc.QC_E_NOT_SYMMETRIC        # self-loop
+    assert create(3, [0, 2, 2, 2], [2, 1], flags=D) == qc.QC_E_NOT_SYMMETRIC  # unsorted row
+    assert create(3, [0, 2, 2, 2], [1, 1], flags=D) == qc.QC_E_NOT_SYMMETRIC  # duplicate arc
+    assert create(3, [0, 3, 3, 3], [2, 1, 1], flags=D | qc.GRAPH_CANONICALIZE) == ok
+    assert create(3, [0, 1, 2, 2], [1, 2], flags=4) == qc.QC_E_INVAL           # unknown flag

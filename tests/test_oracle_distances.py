@@ -140,3 +140,50 @@ def test_generator_is_canonical_and_seeded():
     c3 = gg.config3()
     assert c3.n == 19717 and c3.nnz == 2 * int(round(19717 * 4.5 / 2))
     assert gg.config2().nnz == 2 * 5416
+
+
+# --- directed graphs: distances follow edge direction (row i = from i) -------
+
+DIGRAPHS = [gg.random_digraph(30, 0.06, seed=s) for s in range(4)] + [
+    gg.dcsbm_directed(400, [0.5, 0.3, 0.2], 2.0, seed=5)]
+
+
+@pytest.mark.parametrize("g", DIGRAPHS, ids=lambda g: g.name)
+def test_directed_bfs_matches_scipy_and_networkx(g):
+    import networkx as nx
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    d, dmax = oracle.distances(g.n, g.row_ptr, g.col)
+    a = csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    ref = shortest_path(a, directed=True, unweighted=True)
+    ref = np.where(np.isinf(ref), -1, ref).astype(np.int8)
+    np.testing.assert_array_equal(d, ref)
+    assert dmax == ref.max()
+    G = nx.DiGraph()
+    G.add_nodes_from(range(g.n))
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    G.add_edges_from(zip(rows.tolist(), g.col.tolist()))
+    for s in range(0, g.n, max(1, g.n // 7)):
+        lengths = nx.single_source_shortest_path_length(G, s)
+        want = np.full(g.n, -1, dtype=np.int8)
+        for v, l in lengths.items():
+            want[v] = l
+        np.testing.assert_array_equal(d[s], want)
+    if g.n <= 40:
+        t = tiny.hop_distances(tiny.adjacency(g.n, g.row_ptr, g.col))
+        np.testing.assert_array_equal(d, np.array([[-1 if x is None else x for x in r] for r in t]))
+
+
+def test_directed_generator_is_canonical_and_seeded():
+    g = gg.dcsbm_directed(500, [0.6, 0.4], 2.5, seed=9)
+    h = gg.dcsbm_directed(500, [0.6, 0.4], 2.5, seed=9)
+    np.testing.assert_array_equal(g.col, h.col)
+    assert g.nnz == 1250
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    assert (rows != g.col).all()
+    for i in range(g.n):
+        r = g.col[g.row_ptr[i]:g.row_ptr[i + 1]]
+        assert (np.diff(r) > 0).all()
+    # genuinely directed: most arcs have no reverse arc
+    fwd = set(zip(rows.tolist(), g.col.tolist()))
+    assert sum((b, a) in fwd for a, b in fwd) < 0.2 * len(fwd)

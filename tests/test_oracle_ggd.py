@@ -143,3 +143,19 @@ def test_cluster_end_to_end_small():
     assert r["labels"].shape == (200,)
     roots = np.unique(r["labels"])
     assert 1 <= roots.size < 200
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_directed_descent_matches_tiny(seed):
+    """On directed graphs a node descends only to an out-neighbour; the C
+    oracle's parents and labels equal the pure-Python ones."""
+    g = gg.random_digraph(12 + seed % 9, 0.15 + 0.01 * (seed % 5), seed=100 + seed)
+    adj = tiny.adjacency(g.n, g.row_ptr, g.col)
+    dist = tiny.hop_distances(adj)
+    for sigma in (0.5, 1.0, 2.5):
+        _, v = tiny.potential(dist, sigma)
+        for mode, merge in ((oracle.TIE_STRICT, False), (oracle.TIE_MERGE, True)):
+            par = oracle.ggd_parent(g.n, g.row_ptr, g.col, np.array(v), mode)
+            tpar, tlab = tiny.descend(adj, v, merge=merge)
+            np.testing.assert_array_equal(par, tpar)
+            np.testing.assert_array_equal(oracle.find_centers(par), tlab)
