@@ -364,7 +364,7 @@ def main():
         batch_nograph.run(psi, v, lab)
     torch.cuda.synchronize()
     stages = {}
-    for st_id, name in enumerate(qc.STAGE_NAMES):
+    for st_id, name in enumerate(qc.STAGE_NAMES[:qc.STAGE_DENSE]):
         ms, cnt = qc.timing_read(st_id)
         stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": cnt / args.steps,
                         "avg_launch_ms": (ms / cnt) if cnt else None}
