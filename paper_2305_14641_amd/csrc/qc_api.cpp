@@ -99,7 +99,7 @@ qc_status run_distances(qc_graph g, hipStream_t st)
     QC_TRY(push_desc(g, st));
     {
         StageTimer t(QC_STAGE_BFS, st);
-        QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->plan.planes, g->plan.wide, g->d_desc,
+        QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->plan.planes, g->plan.shape, g->d_desc,
                           g->d_bfs_jobs, g->plan.n_batches, st));
     }
     if (g->dmax < 0) {

@@ -16,7 +16,7 @@ using namespace qc;
 
 struct BfsGroup {
     int bw = 0, nw = 0, planes = 7;
-    bool wide = false;
+    int shape = 0;
     BfsJob *d_jobs = nullptr;
     int n_jobs = 0;
 };
@@ -122,7 +122,7 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
     QC_HIP(launch_fill_u64(b->d_recheck, 1, st));
     for (auto &g : b->bfs) {
         StageTimer t(QC_STAGE_BFS, st);
-        QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.wide, b->d_descs, g.d_jobs, g.n_jobs, st));
+        QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, st));
     }
     for (auto &g : b->hist) {
         StageTimer t(QC_STAGE_HIST, st);
@@ -203,10 +203,10 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
 
     // BFS jobs grouped by launch shape (batch width, words per thread,
     // planes), in XCD order.
-    std::map<std::tuple<int, int, int, bool>, std::vector<int>> by_class;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by_class;
     for (int i = 0; i < n_graphs; ++i) {
         const BfsPlan &p = graphs[i]->plan;
-        by_class[std::make_tuple(p.bw, p.nw, p.planes, p.wide)].push_back(i);
+        by_class[std::make_tuple(p.bw, p.nw, p.planes, p.shape)].push_back(i);
     }
     for (auto &kv : by_class) {
         std::vector<std::vector<BfsJob>> per;
@@ -225,7 +225,7 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         grp.bw = std::get<0>(kv.first);
         grp.nw = std::get<1>(kv.first);
         grp.planes = std::get<2>(kv.first);
-        grp.wide = std::get<3>(kv.first);
+        grp.shape = std::get<3>(kv.first);
         grp.n_jobs = (int)jobs.size();
         if ((s = upload_jobs(&grp.d_jobs, jobs))) return fail(s);
         b->bfs.push_back(grp);

@@ -9,6 +9,8 @@
 //   A. edge-parallel pull: for every edge (r, c), the sources that reached c
 //      at the previous level are offered to r:
 //        nxt[r] |= front[c]        (LDS atomic OR, no return, no branch)
+//      (level 1, whose frontier is the sources themselves, is pushed from
+//      them along their CSR rows instead);
 //   B. word-owner update: every thread owns whole 32-bit words of the fields;
 //      the new pairs are nxt & ~seen; it moves them into front and seen and
 //      records the level in the distance bit-planes.
@@ -17,9 +19,10 @@
 // level (plane p holds bit p of every pair's distance; P = 7 covers every
 // distance up to 126, fewer planes suffice once the graph's largest distance
 // is known). Each batch therefore writes its BW output rows exactly once, at
-// the end. The graph is undirected, so node v's distances to the batch
-// sources are the entries (s0+b, v) of the row-major matrix: rows
-// s0..s0+BW-1 are this workgroup's.
+// the end. Bit b at node v means that source s0+b has reached v, so the
+// pair's distance is entry (s0+b, v) of the row-major matrix (the edge list
+// holds in-edges, so for a directed graph this is the distance from the
+// source): rows s0..s0+BW-1 are this workgroup's.
 //
 // The edge list (packed (row << 16) | col, rows ascending, padded with no-op
 // (0, 0) entries to a multiple of 4) is streamed every level with 16-byte
@@ -93,22 +96,62 @@ __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
     }
 }
 
-// WIDE = false: 1024 threads, three fields (pull from `front`).
-// WIDE = true : 512 threads, two fields (pull from `seen`, which is also
-//   exact: a source that reached c before the previous level has already
-//   reached r), so twice the words fit the LDS and each thread has 256
-//   registers for its planes: twice the sources per batch on mid-size graphs.
-template <bool WIDE> struct BfsShape {
-    static constexpr int kThreads = WIDE ? kBfsThreadsWide : kBfsThreads;
-};
-
-template <int BW, int NW, int P, bool WIDE>
-__global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev *__restrict__ graphs,
-                                                                  const BfsJob *__restrict__ jobs)
+// Level 1 pushed from the sources: source b of the batch (node s0 + b) is
+// offered to each of its out-neighbours, nxt[u] |= bit b. kT / BW threads
+// share a source and stride over its CSR row, four independent loads in
+// flight each. (A second pushed level, over the neighbours' rows, serialises
+// on the rows of high-degree neighbours and measured slower than a pull.)
+template <int BW, int kT>
+__device__ __forceinline__ void push_level1(const GraphDev &G, int s0, int nb,
+                                            typename BfsWord<BW>::T *nxt)
 {
     using W = BfsWord<BW>;
     using T = typename W::T;
-    constexpr int kT = BfsShape<WIDE>::kThreads;
+    constexpr int kTps = kT / BW;           // threads per source (>= 8)
+    const int b = (int)threadIdx.x / kTps;
+    const int part = (int)threadIdx.x % kTps;
+    if (b >= nb) return;
+    const int s = s0 + b;
+    const int32_t *__restrict__ col = G.col;
+    const int e1 = G.row_ptr[s + 1];
+    for (int e = G.row_ptr[s] + part; e < e1; e += 4 * kTps) {
+        int u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = (e + k * kTps < e1) ? col[e + k * kTps] : -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (u[k] >= 0)
+                __hip_atomic_fetch_or(&nxt[u[k] / W::kPer], (T)((T)1 << ((u[k] % W::kPer) * BW + b)),
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Workgroup shapes (kBfsNarrow, kBfsWide, kBfsWide1024):
+//   narrow   1024 threads, three fields (pull from `front`);
+//   wide      512 threads, two fields (pull from `seen`, which is also
+//             exact: a source that reached c before the previous level has
+//             already reached r), so twice the words fit the LDS and each
+//             thread has 256 registers for its planes: twice the sources per
+//             batch on mid-size graphs;
+//   wide1024 1024 threads, two fields: up to 16 words per thread fit 128
+//             registers, so a batch that needs the two-field layout (and
+//             fits 16 words) runs with four wavefronts per SIMD, not two.
+// Pulling from `seen` delivers bits that `front` would not (sources that
+// reached c long ago), so for one batch width the three-field shape issues
+// fewer atomics; the planner prefers it whenever the batch fits.
+template <int SHAPE> struct BfsShape {
+    static constexpr int kThreads = (SHAPE == kBfsWide) ? kBfsThreadsWide : kBfsThreads;
+    static constexpr bool kTwoFields = SHAPE != kBfsNarrow;
+};
+
+template <int BW, int NW, int P, int SHAPE>
+__global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDev *__restrict__ graphs,
+                                                                   const BfsJob *__restrict__ jobs)
+{
+    constexpr bool WIDE = BfsShape<SHAPE>::kTwoFields;
+    using W = BfsWord<BW>;
+    using T = typename W::T;
+    constexpr int kT = BfsShape<SHAPE>::kThreads;
     constexpr int NWW = (BW == 64) ? NW / 2 : NW;   // words of type T per thread
     constexpr int kLdsWords = NWW * kT;
     constexpr int kLevels = (P >= 7) ? kMaxDist : ((1 << P) - 1);  // largest encodable level
@@ -158,19 +201,26 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
     int last = 0;
     int overflow = 0;
     for (int level = 1;; ++level) {
-        // A. pull over every edge, 8 consecutive edges per thread. Quad index
-        //    nquads is the all-zero padding quad: loads clamp to it instead of
-        //    branching, so the next 8 edges stay in flight.
-        int q = 2 * tid;
-        u32x4 ca = quads[min(q, nquads)];
-        u32x4 cb = quads[min(q + 1, nquads)];
-        for (; q < nquads; q += 2 * kT) {
-            const int qn = q + 2 * kT;
-            const u32x4 na = quads[min(qn, nquads)];
-            const u32x4 nb4 = quads[min(qn + 1, nquads)];
-            pull_oct<BW>(ca, cb, front, nxt);
-            ca = na;
-            cb = nb4;
+        if (level == 1) {
+            // A'. level 1 is pushed from the sources along their CSR rows
+            //     (out-edges): a few hundred edges where a pull would scan
+            //     the whole edge list.
+            push_level1<BW, kT>(G, s0, nb, nxt);
+        } else {
+            // A. pull over every edge, 8 consecutive edges per thread. Quad
+            //    index nquads is the all-zero padding quad: loads clamp to it
+            //    instead of branching, so the next 8 edges stay in flight.
+            int q = 2 * tid;
+            u32x4 ca = quads[min(q, nquads)];
+            u32x4 cb = quads[min(q + 1, nquads)];
+            for (; q < nquads; q += 2 * kT) {
+                const int qn = q + 2 * kT;
+                const u32x4 na = quads[min(qn, nquads)];
+                const u32x4 nb4 = quads[min(qn + 1, nquads)];
+                pull_oct<BW>(ca, cb, front, nxt);
+                ca = na;
+                cb = nb4;
+            }
         }
         __syncthreads();
         // B. move the new bits of owned words into front / seen / planes.
@@ -244,10 +294,10 @@ __global__ __launch_bounds__(BfsShape<WIDE>::kThreads) void k_bfs(const GraphDev
     }
 }
 
-template <int BW, int NW, int P, bool WIDE>
+template <int BW, int NW, int P, int SHAPE>
 hipError_t launch_bfs_t(const GraphDev *graphs, const BfsJob *jobs, int n_jobs, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_bfs<BW, NW, P, WIDE>), dim3(n_jobs), dim3(BfsShape<WIDE>::kThreads), 0,
+    hipLaunchKernelGGL((k_bfs<BW, NW, P, SHAPE>), dim3(n_jobs), dim3(BfsShape<SHAPE>::kThreads), 0,
                        stream, graphs, jobs);
     return hipGetLastError();
 }
@@ -257,14 +307,14 @@ hipError_t launch_bfs_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int 
                         hipStream_t stream)
 {
     switch (nw) {
-    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1, P, false>(graphs, jobs, n_jobs, stream);
+    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
             return hipErrorInvalidValue;
-    case 2: return launch_bfs_t<BW, 2, P, false>(graphs, jobs, n_jobs, stream);
-    case 4: return launch_bfs_t<BW, 4, P, false>(graphs, jobs, n_jobs, stream);
-    case 6: return launch_bfs_t<BW, 6, P, false>(graphs, jobs, n_jobs, stream);
-    case 8: return launch_bfs_t<BW, 8, P, false>(graphs, jobs, n_jobs, stream);
-    case 10: return launch_bfs_t<BW, 10, P, false>(graphs, jobs, n_jobs, stream);
-    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P, false>(graphs, jobs, n_jobs, stream);
+    case 2: return launch_bfs_t<BW, 2, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_t<BW, 4, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
+    case 6: return launch_bfs_t<BW, 6, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_t<BW, 8, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
+    case 10: return launch_bfs_t<BW, 10, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
+    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
              return hipErrorInvalidValue;  // 7 planes x 12 words exceed the registers
     default: return hipErrorInvalidValue;
     }
@@ -279,13 +329,34 @@ hipError_t launch_bfs_wide_p(int nw, const GraphDev *graphs, const BfsJob *jobs,
         return hipErrorInvalidValue;
     } else {
         switch (nw) {
-        case 16: return launch_bfs_t<BW, 16, P, true>(graphs, jobs, n_jobs, stream);
-        case 24: return launch_bfs_t<BW, 24, P, true>(graphs, jobs, n_jobs, stream);
-        case 32: return launch_bfs_t<BW, 32, P, true>(graphs, jobs, n_jobs, stream);
-        case 38: if constexpr (P == 4) return launch_bfs_t<BW, 38, P, true>(graphs, jobs, n_jobs, stream);
+        case 16: return launch_bfs_t<BW, 16, P, kBfsWide>(graphs, jobs, n_jobs, stream);
+        case 24: return launch_bfs_t<BW, 24, P, kBfsWide>(graphs, jobs, n_jobs, stream);
+        case 32: return launch_bfs_t<BW, 32, P, kBfsWide>(graphs, jobs, n_jobs, stream);
+        case 38: if constexpr (P == 4) return launch_bfs_t<BW, 38, P, kBfsWide>(graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;  // 5 planes x 38 words exceed the registers
         case 39: if constexpr (P == 4 && BW != 64)
-                     return launch_bfs_t<BW, 39, P, true>(graphs, jobs, n_jobs, stream);
+                     return launch_bfs_t<BW, 39, P, kBfsWide>(graphs, jobs, n_jobs, stream);
+                 return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+// Two-field, 1024-thread shapes (planes 4 or 5): 16 words with 4 planes and
+// 14 with 5 (batches of 32 or 64 sources only) are the most that fit 128
+// registers without spills.
+template <int BW, int P>
+hipError_t launch_bfs_wide1024_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                                 hipStream_t stream)
+{
+    if constexpr (P >= 7 || BW < 8) {
+        return hipErrorInvalidValue;
+    } else {
+        switch (nw) {
+        case 14: if constexpr (P == 4 || BW >= 32)
+                     return launch_bfs_t<BW, 14, P, kBfsWide1024>(graphs, jobs, n_jobs, stream);
+                 return hipErrorInvalidValue;
+        case 16: if constexpr (P == 4) return launch_bfs_t<BW, 16, P, kBfsWide1024>(graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
         }
@@ -293,16 +364,24 @@ hipError_t launch_bfs_wide_p(int nw, const GraphDev *graphs, const BfsJob *jobs,
 }
 
 template <int BW>
-hipError_t launch_bfs_bw(int nw, int planes, bool wide, const GraphDev *graphs, const BfsJob *jobs,
+hipError_t launch_bfs_bw(int nw, int planes, int shape, const GraphDev *graphs, const BfsJob *jobs,
                          int n_jobs, hipStream_t stream)
 {
-    if (wide) {
+    if (shape == kBfsWide) {
         switch (planes) {
         case 4: return launch_bfs_wide_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
         case 5: return launch_bfs_wide_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);
         default: return hipErrorInvalidValue;
         }
     }
+    if (shape == kBfsWide1024) {
+        switch (planes) {
+        case 4: return launch_bfs_wide1024_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
+        case 5: return launch_bfs_wide1024_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (shape != kBfsNarrow) return hipErrorInvalidValue;
     switch (planes) {
     case 4: return launch_bfs_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
     case 5: return launch_bfs_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);

@@ -2,6 +2,6 @@
 #include "qc_bfs.h"
 
 namespace qc {
-template hipError_t launch_bfs_bw<32>(int, int, bool, const GraphDev *, const BfsJob *, int,
+template hipError_t launch_bfs_bw<32>(int, int, int, const GraphDev *, const BfsJob *, int,
                                          hipStream_t);
 }  // namespace qc

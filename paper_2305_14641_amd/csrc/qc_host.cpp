@@ -126,23 +126,42 @@ int planes_for(int32_t dmax)
     return 7;
 }
 
-BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, bool wide)
+BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape)
 {
     static const int kNarrow[] = {1, 2, 4, 6, 8, 10, 12};
     static const int kWide[] = {16, 24, 32, 38, 39};
+    static const int kWide1024[] = {14, 16};
     const int planes = planes_for(dmax);
-    BfsPlan none = {0, 0, planes, 0, wide};
-    if (wide && planes >= 7) return none;
-    const int threads = wide ? kBfsThreadsWide : kBfsThreads;
-    // registers (no spills): three-field shape 10 words per thread with 7
-    // planes, 12 with 4-5; two-field shape 39 words with 4 planes, 32 with 5
-    const int max_nw = wide ? (planes <= 4 ? 39 : 32) : (planes >= 7 ? 10 : 12);
+    const bool two = shape != kBfsNarrow;
+    BfsPlan none = {0, 0, planes, 0, shape};
+    if (two && planes >= 7) return none;
+    const int threads = (shape == kBfsWide) ? kBfsThreadsWide : kBfsThreads;
+    // words per thread that fit the registers without spills: three-field
+    // shape 10 with 7 planes, 12 with 4-5; two-field 512-thread 39 with 4
+    // planes, 32 with 5; two-field 1024-thread 16 with 4, 14 with 5 (and
+    // then only for batches of 32 or 64 sources)
+    int max_nw;
+    const int *opts;
+    int nopts;
+    if (shape == kBfsNarrow) {
+        max_nw = planes >= 7 ? 10 : 12;
+        opts = kNarrow;
+        nopts = 7;
+    } else if (shape == kBfsWide) {
+        max_nw = planes <= 4 ? 39 : 32;
+        opts = kWide;
+        nopts = 5;
+    } else {
+        max_nw = planes <= 4 ? 16 : 14;
+        opts = kWide1024;
+        nopts = 2;
+    }
     for (int bw : {64, 32, 16, 8, 4}) {
-        if (wide && bw < 8) continue;
+        if (two && bw < 8) continue;
+        // 5 planes of a two-field 1024-thread batch narrower than 32 spill
+        if (shape == kBfsWide1024 && planes == 5 && bw < 32) continue;
         const int64_t words = ((int64_t)n * bw + 31) / 32;  // 32-bit words of one bit field
         const int64_t need = (words + threads - 1) / threads;
-        const int *opts = wide ? kWide : kNarrow;
-        const int nopts = wide ? 5 : 7;
         for (int k = 0; k < nopts; ++k) {
             const int nw = opts[k];
             if (nw > max_nw) break;
@@ -153,7 +172,7 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, bool wide)
                 p.nw = nw;
                 p.planes = planes;
                 p.n_batches = (int)((n + bw - 1) / bw);
-                p.wide = wide;
+                p.shape = shape;
                 return p;
             }
         }
@@ -163,9 +182,14 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, bool wide)
 
 BfsPlan plan_bfs(int32_t n, int32_t dmax)
 {
-    const BfsPlan narrow = plan_bfs_shape(n, dmax, false);
-    const BfsPlan wide = plan_bfs_shape(n, dmax, true);
-    return (wide.bw > narrow.bw) ? wide : narrow;
+    // the widest batch wins; at equal width, more threads per workgroup, and
+    // three fields (fewer atomics) before two
+    BfsPlan best = plan_bfs_shape(n, dmax, kBfsNarrow);
+    for (int shape : {kBfsWide1024, kBfsWide}) {
+        const BfsPlan p = plan_bfs_shape(n, dmax, shape);
+        if (p.bw > best.bw) best = p;
+    }
+    return best;
 }
 
 static void split_f32(double x, float &hi, float &lo)

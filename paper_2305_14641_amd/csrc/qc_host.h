@@ -33,15 +33,16 @@ int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::v
 
 // BFS launch shape for a graph of n nodes whose largest finite distance is
 // dmax (or -1 while unknown): `planes` distance bit-planes (enough for dmax,
-// 7 when unknown), and the widest batch of sources whose three LDS bit
-// fields and register planes fit one 1024-thread workgroup, with nw 32-bit
-// words per thread per field.
-// `wide` selects the two-field 512-thread shape (only with 4-5 planes), used
-// when it allows a wider batch than the three-field shape.
-struct BfsPlan { int bw; int nw; int planes; int n_batches; bool wide; };
+// 7 when unknown), and the widest batch of sources whose LDS bit fields and
+// register planes fit one workgroup, with nw 32-bit words per thread per
+// field. `shape` (kBfsNarrow, kBfsWide, kBfsWide1024): the three-field
+// 1024-thread shape is used whenever it fits the widest batch; otherwise the
+// two-field 1024-thread one, then the two-field 512-thread one (both only
+// with 4-5 planes).
+struct BfsPlan { int bw; int nw; int planes; int n_batches; int shape; };
 BfsPlan plan_bfs(int32_t n, int32_t dmax);
-// The three-field or two-field plan alone (bw = 0 when n does not fit).
-BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, bool wide);
+// The plan of one shape alone (bw = 0 when n does not fit).
+BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape);
 int planes_for(int32_t dmax);
 
 // Histogram row length for a largest finite distance dmax.

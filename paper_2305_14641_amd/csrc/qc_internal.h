@@ -12,10 +12,13 @@ namespace qc {
 constexpr int kMaxDist = 126;
 // Largest supported node count: edges are packed as (row << 16 | col).
 constexpr int kMaxNodes = 65536;
-// Threads per workgroup of the multi-source BFS: the three-field shape and
-// the two-field ("wide") shape.
+// Threads per workgroup of the multi-source BFS: the three-field shape (and
+// the 1024-thread two-field one) and the 512-thread two-field ("wide") shape.
 constexpr int kBfsThreads = 1024;
 constexpr int kBfsThreadsWide = 512;
+// BFS workgroup shapes: three fields x 1024 threads, two fields x 512
+// threads, two fields x 1024 threads.
+enum { kBfsNarrow = 0, kBfsWide = 1, kBfsWide1024 = 2 };
 // 32-bit words of each LDS bit field one BFS thread owns at most (the three
 // fields of 13 x 1024 words fill 156 KB of the 160 KB LDS).
 constexpr int kBfsMaxWordsPerThread = 13;
@@ -77,12 +80,12 @@ hipError_t launch_set_desc(GraphDev *dst, const GraphDev &src, hipStream_t strea
 // Multi-source BFS over `n_jobs` (graph, source-batch) jobs; every graph of the
 // launch must share the batch width `bw`, words-per-thread `nw` and the
 // number of distance bit-planes `planes` (4, 5 or 7; levels < 2^planes).
-// `wide` selects the two-field 512-thread shape.
-hipError_t launch_bfs(int bw, int nw, int planes, bool wide, const GraphDev *graphs,
+// `shape` is kBfsNarrow, kBfsWide or kBfsWide1024.
+hipError_t launch_bfs(int bw, int nw, int planes, int shape, const GraphDev *graphs,
                       const BfsJob *jobs, int n_jobs, hipStream_t stream);
 // One batch width (qc_bfs_<bw>.hip).
 template <int BW>
-hipError_t launch_bfs_bw(int nw, int planes, bool wide, const GraphDev *graphs, const BfsJob *jobs,
+hipError_t launch_bfs_bw(int nw, int planes, int shape, const GraphDev *graphs, const BfsJob *jobs,
                          int n_jobs, hipStream_t stream);
 
 // Histograms of the resident distance rows (one job = hist_rows_per_job(K)

@@ -10,16 +10,16 @@
 
 namespace qc {
 
-hipError_t launch_bfs(int bw, int nw, int planes, bool wide, const GraphDev *graphs,
+hipError_t launch_bfs(int bw, int nw, int planes, int shape, const GraphDev *graphs,
                       const BfsJob *jobs, int n_jobs, hipStream_t stream)
 {
     if (n_jobs <= 0) return hipSuccess;
     switch (bw) {
-    case 4: return launch_bfs_bw<4>(nw, planes, wide, graphs, jobs, n_jobs, stream);
-    case 8: return launch_bfs_bw<8>(nw, planes, wide, graphs, jobs, n_jobs, stream);
-    case 16: return launch_bfs_bw<16>(nw, planes, wide, graphs, jobs, n_jobs, stream);
-    case 32: return launch_bfs_bw<32>(nw, planes, wide, graphs, jobs, n_jobs, stream);
-    case 64: return launch_bfs_bw<64>(nw, planes, wide, graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_bw<4>(nw, planes, shape, graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_bw<8>(nw, planes, shape, graphs, jobs, n_jobs, stream);
+    case 16: return launch_bfs_bw<16>(nw, planes, shape, graphs, jobs, n_jobs, stream);
+    case 32: return launch_bfs_bw<32>(nw, planes, shape, graphs, jobs, n_jobs, stream);
+    case 64: return launch_bfs_bw<64>(nw, planes, shape, graphs, jobs, n_jobs, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -133,11 +133,13 @@ def test_config3_full(torch_cuda):
 
 @pytest.mark.parametrize("n,deg,seed", [
     (3000, 5.0, 21),     # batch width 64
-    (9000, 4.0, 22),     # 32, then 64 (two-field shape) once dmax is known
-    (15000, 4.0, 26),    # 16, then 32 (two-field shape)
+    (9000, 4.0, 22),     # 32, then 64 (two fields, 512 threads) once dmax is known
+    (15000, 4.0, 26),    # 16, then 32 (two fields, 1024 threads, 16 words, 4 planes)
+    (18000, 4.0, 27),    # 16, then 32 (two fields, 512 threads)
     (20001, 3.0, 23),    # 16
-    (40000, 3.0, 24),    # 8, then 16 (two-field shape)
+    (40000, 3.0, 24),    # 8, then 16 (two fields)
     (50003, 3.0, 25),    # 4, then 8
+    (13000, 0.0, 7),     # sparse SBM, largest distance 20: 32 (two fields, 1024 threads, 5 planes)
 ])
 def test_batch_width_classes_sampled(torch_cuda, n, deg, seed):
     """Every BFS launch shape, ragged last batch: the first run (7 planes)
@@ -146,7 +148,10 @@ def test_batch_width_classes_sampled(torch_cuda, n, deg, seed):
     without the matrix), labels bit-exact."""
     from paper_2305_14641_amd import qc
     torch = torch_cuda
-    g = gg.dcsbm(n, [0.5, 0.3, 0.2], deg, seed=seed)
+    if deg > 0:
+        g = gg.dcsbm(n, [0.5, 0.3, 0.2], deg, seed=seed)
+    else:
+        g = gg.sbm(n, 1, 5e-5, 5e-5, seed=seed)
     print(f"[gpu] width class n={n} nnz={g.nnz}", flush=True)
     G = qc.Graph.from_graph(g)
     dist = torch.empty((n, n), dtype=torch.int8, device="cuda")
