@@ -4,7 +4,9 @@
 #include <string.h>
 
 #include <atomic>
+#include <algorithm>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -184,6 +186,7 @@ void destroy(qc_graph g, bool sync)
     if (sync) (void)hipDeviceSynchronize();
     gfree(g, g->d_row_ptr);
     gfree(g, g->d_col);
+    gfree(g, g->d_order);
     gfree(g, g->d_edges);
     gfree(g, g->d_dist_owned);
     gfree(g, g->d_hist);
@@ -278,6 +281,15 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     g->n_components = count_components(n, rp, col, &g->comp_size);
 
     const std::vector<uint32_t> edges = pack_in_edges(n, rp, col, directed);
+    // The descent gives one thread to each node, in this order: nodes sorted
+    // by decreasing degree within windows of kOrderWindow consecutive nodes,
+    // so a wavefront's neighbour loops have similar trip counts while the
+    // scattered loads and stores of a window's jobs stay within a few KB.
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    for (int32_t i0 = 0; i0 < n; i0 += kOrderWindow)
+        std::stable_sort(order.begin() + i0, order.begin() + std::min(n, i0 + kOrderWindow),
+                         [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
     std::vector<NodeJob> njobs;
     for (int i = 0; i < n; i += kNodesPerJob) njobs.push_back(NodeJob{0, i, 0});
     g->n_node_jobs = (int)njobs.size();
@@ -285,11 +297,13 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     qc_status st_ = QC_OK;
     auto fail = [&](qc_status s) { destroy(g, region == nullptr); return s; };
     if ((st_ = galloc(g, &g->d_row_ptr, rp.size())) || (st_ = galloc(g, &g->d_col, col.size())) ||
+        (st_ = galloc(g, &g->d_order, order.size())) ||
         (st_ = galloc(g, &g->d_edges, edges.size())) || (st_ = galloc(g, &g->d_status, 2)) ||
         (st_ = galloc(g, &g->d_recheck, 1)) || (st_ = galloc(g, &g->d_desc, 1)) ||
         (st_ = galloc(g, &g->d_node_jobs, njobs.size())))
         return fail(st_);
     if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
+        (st_ = upload(g->d_order, order)) ||
         (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
         (st_ = set_plan(g, plan_bfs(n, -1))))
         return fail(st_);

@@ -115,6 +115,45 @@ std::vector<J> xcd_order(const std::vector<std::vector<J>> &per_graph, const std
     return out;
 }
 
+// Descent jobs pinned to XCDs: every graph's jobs go to one XCD (largest
+// graphs first, each to the least loaded XCD), and the eight lists are padded
+// to one length with no-op jobs (first node past the graph's end) before they
+// are interleaved. With a multiple of 8 jobs per sigma row of the grid, job k
+// runs on XCD k % 8 for every sigma, so an XCD's L2 only ever holds the V
+// planes and neighbour lists of its own graphs. Returns an empty list when
+// the graphs cannot be balanced this way (too few, or one too large).
+std::vector<NodeJob> xcd_pinned_node_jobs(const std::vector<qc_graph> &graphs)
+{
+    constexpr int kXcd = 8;
+    const int ng = (int)graphs.size();
+    std::vector<double> cost(ng);
+    double total = 0.0, largest = 0.0;
+    for (int i = 0; i < ng; ++i) {
+        cost[i] = (double)graphs[i]->n + (double)graphs[i]->nnz;
+        total += cost[i];
+        largest = std::max(largest, cost[i]);
+    }
+    if (ng < 2 * kXcd || largest > total / kXcd) return {};
+    std::vector<int> order(ng);
+    for (int i = 0; i < ng; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<std::vector<NodeJob>> lanes(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (int gi : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int r = 0; r < graphs[gi]->n; r += kNodesPerJob) lanes[x].push_back(NodeJob{gi, r, 0});
+        load[x] += cost[gi];
+    }
+    size_t longest = 0;
+    for (auto &l : lanes) longest = std::max(longest, l.size());
+    std::vector<NodeJob> out;
+    out.reserve(longest * kXcd);
+    for (size_t r = 0; r < longest; ++r)
+        for (int x = 0; x < kXcd; ++x)
+            out.push_back(r < lanes[x].size() ? lanes[x][r] : NodeJob{0, graphs[0]->n, 0});
+    return out;
+}
+
 qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st)
 {
     const int S = (int)b->sigmas.size();
@@ -249,9 +288,12 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         b->hist.push_back(h);
         b->pot.push_back(p);
     }
-    std::vector<NodeJob> gj, jj;
+    std::vector<qc_graph> gv(graphs, graphs + n_graphs);
+    std::vector<NodeJob> gj = xcd_pinned_node_jobs(gv), jj;
+    const bool pinned = !gj.empty();
     for (int gi = 0; gi < n_graphs; ++gi) {
-        for (int r = 0; r < graphs[gi]->n; r += kNodesPerJob) gj.push_back(NodeJob{gi, r, 0});
+        if (!pinned)
+            for (int r = 0; r < graphs[gi]->n; r += kNodesPerJob) gj.push_back(NodeJob{gi, r, 0});
         jj.push_back(NodeJob{gi, 0, b->offsets[gi]});
     }
     b->n_ggd_jobs = (int)gj.size();

@@ -30,6 +30,7 @@ struct qc_graph_s {
     // device CSR
     int32_t *d_row_ptr = nullptr;
     int32_t *d_col = nullptr;
+    int32_t *d_order = nullptr;       // descent thread order (see create_graph)
     uint32_t *d_edges = nullptr;
 
     // distances and histograms
@@ -76,6 +77,7 @@ struct qc_graph_s {
         d.nnz = nnz;
         d.row_ptr = d_row_ptr;
         d.col = d_col;
+        d.order = d_order;
         d.edges = d_edges;
         d.dist = d_dist;
         d.hist = d_hist;

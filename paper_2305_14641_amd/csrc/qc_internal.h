@@ -39,6 +39,7 @@ struct GraphDev {
     int64_t nnz;
     const int32_t *row_ptr;   // [n+1]
     const int32_t *col;       // [nnz]
+    const int32_t *order;     // [n] nodes by decreasing degree within windows of kOrderWindow
     const uint32_t *edges;    // [nnz] packed (row << 16) | col, rows ascending
     int8_t *dist;             // [n*n] row-major
     int32_t *hist;            // [n*K]
@@ -66,6 +67,12 @@ struct NodeJob { int32_t g; int32_t i0; int64_t out_off; };  // graph, first nod
 inline int hist_rows_per_job(int K) { return 32; }
 // Nodes per job of the potential and descent kernels.
 constexpr int kNodesPerJob = 256;
+// Window (in nodes, a multiple of kNodesPerJob) within which the descent's
+// thread order sorts nodes by degree.
+#ifndef QC_ORDER_WINDOW
+#define QC_ORDER_WINDOW 4096
+#endif
+constexpr int kOrderWindow = QC_ORDER_WINDOW;
 
 // Relative FP32 gap under which a descent comparison is re-decided in FP64.
 // It exceeds twice the worst FP32 error of V for both FP64ACC (about 2^-24)

@@ -408,9 +408,12 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
     const int s = sigma_base + (int)blockIdx.y;
-    const int i = job.i0 + (int)threadIdx.x;
+    const int t = job.i0 + (int)threadIdx.x;
     bool rechecked = false;
-    if (i < n && s < G.n_sigmas) {
+    if (t < n && s < G.n_sigmas) {
+        // within the job, threads take its nodes by decreasing degree, so the
+        // neighbour loops of one wavefront have similar trip counts
+        const int i = G.order[t];
         const float *__restrict__ V = G.v + (int64_t)s * n;
         const int32_t *__restrict__ col = G.col;
         const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
