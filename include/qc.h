@@ -106,6 +106,26 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
                           const int32_t *col_idx, uint32_t flags, void *stream,
                           qc_graph *out);
 
+/*
+ * A graph handle whose distances are shortest-path lengths under positive
+ * integer edge weights (Section 3.1: a path's length is the sum of its
+ * edges' weights), for the same histogram, potential and descent path.
+ *   weights  host, uint8[nnz], 1..126, one per CSR entry; for an undirected
+ *            graph both entries of an edge must carry the same weight
+ *   flags    0 or QC_GRAPH_DIRECTED (the CSR must be canonical: no
+ *            QC_GRAPH_CANONICALIZE, since the weights follow its entries)
+ * Internally an edge of weight w is walked as w unit steps, through w - 1
+ * extra nodes, so n + sum over edges of (w - 1) must not exceed 65536
+ * (else QC_E_INVAL), and qc_distances reports QC_E_OVERFLOW when any of
+ * those steps lies farther than 126 from a source (so distances up to 126
+ * minus half the heaviest weight are always representable). The descent uses
+ * the graph's own edges. Other arguments and errors as qc_graph_create;
+ * QC_E_NOT_SYMMETRIC also when the two weights of an undirected edge differ.
+ */
+qc_status qc_graph_create_weighted(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_idx, const uint8_t *weights, uint32_t flags,
+                                   void *stream, qc_graph *out);
+
 /* Release a handle and all device memory it owns (waits for its work). */
 qc_status qc_graph_destroy(qc_graph g);
 

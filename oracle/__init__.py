@@ -74,6 +74,8 @@ def lib():
         L.qco_potential_literal.restype = None
         L.qco_potential_dense.argtypes = [I, I, P, D, P, P]
         L.qco_potential_dense.restype = None
+        L.qco_dijkstra_rows.argtypes = [I, P, P, P, I, P, P, P]
+        L.qco_dijkstra_rows.restype = I
         L.qco_num_threads.argtypes = []
         L.qco_num_threads.restype = I
         _lib = L
@@ -112,6 +114,24 @@ def bfs_rows(n, row_ptr, col, sources) -> tuple:
 def distances(n, row_ptr, col) -> tuple:
     """Full N x N hop-distance matrix and its largest finite entry."""
     return bfs_rows(n, row_ptr, col, np.arange(n, dtype=np.int32))
+
+
+def weighted_rows(n, row_ptr, col, weight, sources) -> tuple:
+    """Shortest-path lengths with positive integer edge weights (one per
+    CSR entry, 1..255) from the given sources: int8 rows, -1 unreachable."""
+    rp, c = _csr(row_ptr, col)
+    w = np.ascontiguousarray(weight, dtype=np.uint8)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    out = np.empty((src.shape[0], n), dtype=np.int8)
+    dmax = np.zeros(1, dtype=np.int32)
+    st = lib().qco_dijkstra_rows(n, _p(rp), _p(c), _p(w), src.shape[0], _p(src), _p(out), _p(dmax))
+    if st != 0:
+        raise OracleError(f"dijkstra status {st} (distance above {MAX_DIST} or zero weight)")
+    return out, int(dmax[0])
+
+
+def weighted_distances(n, row_ptr, col, weight) -> tuple:
+    return weighted_rows(n, row_ptr, col, weight, np.arange(n, dtype=np.int32))
 
 
 def hist_rows(dist_rows: np.ndarray, K: int) -> np.ndarray:

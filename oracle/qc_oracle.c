@@ -98,6 +98,89 @@ int qco_bfs_rows(int n, const int32_t *row_ptr, const int32_t *col,
     return status;
 }
 
+/* Shortest-path lengths from s along CSR rows with positive integer edge
+ * weights w[e] (Section 3.1: a path's length is the sum of its edges'
+ * weights), by Dijkstra's algorithm with a bucket queue (Dial's variant):
+ * bucket d lists the nodes whose tentative distance was lowered to d; the
+ * buckets are drained in increasing d, and a node becomes final the first
+ * time it is drained at its current distance. Every push takes a fresh list
+ * entry from `pool` (node, next), at most one per edge plus the source.
+ * Returns the largest finite distance, or -1 if one exceeds 126. */
+static int dijkstra_one(int n, const int32_t *row_ptr, const int32_t *col, const uint8_t *w,
+                        int s, int8_t *row, int32_t *dist, int32_t *pool_node,
+                        int32_t *pool_next, int32_t *bucket_head)
+{
+    for (int v = 0; v < n; ++v) {
+        dist[v] = INT32_MAX;
+        row[v] = -1;
+    }
+    const int nb = QCO_MAX_DIST + 257;     /* tentative distances stay below 126 + 256 */
+    for (int d = 0; d < nb; ++d) bucket_head[d] = -1;
+    int used = 0;
+    dist[s] = 0;
+    pool_node[used] = s;
+    pool_next[used] = -1;
+    bucket_head[0] = used++;
+    int ecc = 0;
+    for (int d = 0; d < nb; ++d) {
+        for (int it = bucket_head[d]; it >= 0; it = pool_next[it]) {
+            int u = pool_node[it];
+            if (dist[u] != d || row[u] >= 0) continue;   /* stale or already final */
+            if (d > QCO_MAX_DIST) return -1;
+            row[u] = (int8_t)d;
+            if (d > ecc) ecc = d;
+            for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                int v = col[e];
+                int nd = d + (int)w[e];
+                if (row[v] < 0 && nd < dist[v]) {
+                    dist[v] = nd;
+                    pool_node[used] = v;
+                    pool_next[used] = bucket_head[nd];
+                    bucket_head[nd] = used++;
+                }
+            }
+        }
+    }
+    return ecc;
+}
+
+/* Weighted all-pairs distances for the listed sources (weights 1..255). */
+int qco_dijkstra_rows(int n, const int32_t *row_ptr, const int32_t *col, const uint8_t *w,
+                      int nsrc, const int32_t *srcs, int8_t *dist, int32_t *dmax_out)
+{
+    if (n <= 0 || nsrc < 0) return QCO_E_ARG;
+    const int32_t m = row_ptr[n];
+    for (int32_t e = 0; e < m; ++e)
+        if (w[e] == 0) return QCO_E_ARG;
+    int status = QCO_OK;
+    int dmax = 0;
+#pragma omp parallel
+    {
+        int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *pn = (int32_t *)malloc(sizeof(int32_t) * ((size_t)m + 1));
+        int32_t *px = (int32_t *)malloc(sizeof(int32_t) * ((size_t)m + 1));
+        int32_t *head = (int32_t *)malloc(sizeof(int32_t) * (size_t)(QCO_MAX_DIST + 257));
+        int local_max = 0, local_bad = 0;
+#pragma omp for schedule(dynamic, 8)
+        for (int r = 0; r < nsrc; ++r) {
+            int ecc = dijkstra_one(n, row_ptr, col, w, srcs[r], dist + (size_t)r * n, d, pn, px, head);
+            if (ecc < 0) local_bad = 1;
+            else if (ecc > local_max) local_max = ecc;
+        }
+#pragma omp critical
+        {
+            if (local_bad) status = QCO_E_OVERFLOW;
+            if (local_max > dmax) dmax = local_max;
+        }
+        free(d);
+        free(pn);
+        free(px);
+        free(head);
+    }
+    if (dmax_out) *dmax_out = dmax;
+    return status;
+}
+
 /* Histogram of each listed distance row: hist[r*K + k] = #{v : row_r[v] == k}.
  * Unreachable entries (-1) are not counted. Distances >= K are an error. */
 int qco_hist_rows(int n, int nrows, const int8_t *dist, int K, int32_t *hist)

@@ -63,9 +63,11 @@ uint32_t batch_target(qc_graph g, int s0, int bw)
     return (uint32_t)t;
 }
 
-qc_status set_plan(qc_graph g, const BfsPlan &p)
+qc_status set_plan(qc_graph g, const BfsPlan &plan)
 {
-    if (p.bw <= 0) return QC_E_INVAL;
+    if (plan.bw <= 0) return QC_E_INVAL;
+    BfsPlan p = plan;
+    p.n_batches = (g->n + p.bw - 1) / p.bw;   // sources are the graph's own nodes
     if (g->d_bfs_jobs && p.bw == g->plan.bw) {
         g->plan = p;
         return QC_OK;
@@ -101,19 +103,24 @@ qc_status run_distances(qc_graph g, hipStream_t st)
     QC_TRY(push_desc(g, st));
     {
         StageTimer t(QC_STAGE_BFS, st);
-        QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->plan.planes, g->plan.shape, g->d_desc,
+        QC_HIP(launch_bfs(g->plan.bw, g->plan.nw, g->plan.planes,
+                          g->plan.shape | (g->weighted ? kBfsWeighted : 0), g->d_desc,
                           g->d_bfs_jobs, g->plan.n_batches, st));
     }
-    if (g->dmax < 0) {
+    const bool first = g->dmax < 0;
+    if (first) {
         int32_t status[2];
         QC_HIP(hipMemcpyAsync(status, g->d_status, sizeof status, hipMemcpyDeviceToHost, st));
         QC_HIP(hipStreamSynchronize(st));
         if (status[1]) return QC_E_OVERFLOW;
         if (status[1] & 2) return QC_E_DEVICE;  // cannot happen with 7 planes
+        // the largest level the search reached; with weighted edges it can
+        // be that of a node inside an edge, above the graph's own dmax
+        g->dmax_bfs = status[0];
         g->dmax = status[0];
         g->K = bins_for(g->dmax);
         // later runs need only enough planes for dmax: maybe a wider batch
-        QC_TRY(set_plan(g, plan_bfs(g->n, g->dmax)));
+        QC_TRY(set_plan(g, plan_bfs(g->n_bfs, g->dmax_bfs)));
         gfree(g, g->d_hist);
         QC_TRY(galloc(g, &g->d_hist, (size_t)g->n * g->K));
         QC_TRY(ensure_hist_jobs(g));
@@ -122,6 +129,18 @@ qc_status run_distances(qc_graph g, hipStream_t st)
     {
         StageTimer t(QC_STAGE_HIST, st);
         QC_HIP(launch_hist(g->K, g->d_desc, g->d_hist_jobs, g->n_hist_jobs, st));
+    }
+    if (first && g->weighted) {
+        // the graph's own largest finite distance: the last non-empty bin
+        std::vector<int32_t> h((size_t)g->n * g->K);
+        QC_HIP(hipMemcpyAsync(h.data(), g->d_hist, h.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+        QC_HIP(hipStreamSynchronize(st));
+        int32_t dm = 0;
+        for (size_t i = 0; i < h.size(); ++i)
+            if (h[i] && (int32_t)(i % g->K) > dm) dm = (int32_t)(i % g->K);
+        g->dmax = dm;
+        QC_TRY(push_desc(g, st));
     }
     g->have_dist = true;
     return QC_OK;
@@ -187,6 +206,8 @@ void destroy(qc_graph g, bool sync)
     gfree(g, g->d_row_ptr);
     gfree(g, g->d_col);
     gfree(g, g->d_order);
+    gfree(g, g->d_bfs_row_ptr);
+    gfree(g, g->d_bfs_col);
     gfree(g, g->d_edges);
     gfree(g, g->d_dist_owned);
     gfree(g, g->d_hist);
@@ -253,20 +274,35 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
     return create_graph(n, nnz, row_ptr, col_idx, flags, as_stream(stream), nullptr, 0, out);
 }
 
+qc_status qc_graph_create_weighted(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_idx, const uint8_t *weights, uint32_t flags,
+                                   void *stream, qc_graph *out)
+{
+    if (!weights && nnz > 0) return QC_E_INVAL;
+    static const uint8_t kNone = 1;
+    return create_graph(n, nnz, row_ptr, col_idx, flags, as_stream(stream), nullptr, 0, out,
+                        weights ? weights : &kNone);
+}
+
 }  // extern "C"
 
 namespace qc {
 
 qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                        uint32_t flags, hipStream_t st, char *region, size_t region_bytes,
-                       qc_graph *out)
+                       qc_graph *out, const uint8_t *weights)
 {
     if (!out) return QC_E_INVAL;
     if (flags & ~(uint32_t)(QC_GRAPH_CANONICALIZE | QC_GRAPH_DIRECTED)) return QC_E_INVAL;
+    // weights follow the caller's CSR entries, so that CSR must be canonical
+    if (weights && (flags & QC_GRAPH_CANONICALIZE)) return QC_E_INVAL;
     const bool directed = (flags & QC_GRAPH_DIRECTED) != 0;
     std::vector<int32_t> rp, col;
     QC_TRY(validate_csr(n, nnz, row_ptr, col_idx, (flags & QC_GRAPH_CANONICALIZE) != 0, rp, col,
                         directed));
+    int32_t n_bfs = n;
+    std::vector<int32_t> brp, bcol;
+    if (weights) QC_TRY(subdivide_weighted(n, rp, col, weights, directed, n_bfs, brp, bcol));
     int dev = 0;
     QC_TRY(check_device(&dev));
 
@@ -277,10 +313,22 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     g->n = n;
     g->nnz = (int64_t)col.size();
     // (weakly) connected components: a source reaches at most its component,
-    // exactly all of it when the graph is undirected (the BFS's stop target)
-    g->n_components = count_components(n, rp, col, &g->comp_size);
+    // exactly all of it when the graph is undirected (the BFS's stop target).
+    // With weights they are taken in the graph the BFS walks, whose extra
+    // nodes the search counts too (and whose components are the graph's).
+    if (weights) {
+        std::vector<int32_t> size_all;
+        g->n_components = count_components(n_bfs, brp, bcol, &size_all);
+        g->comp_size.assign(size_all.begin(), size_all.begin() + n);
+    } else {
+        g->n_components = count_components(n, rp, col, &g->comp_size);
+    }
 
-    const std::vector<uint32_t> edges = pack_in_edges(n, rp, col, directed);
+    g->n_bfs = n_bfs;
+    g->nnz_bfs = weights ? (int64_t)bcol.size() : g->nnz;
+    g->weighted = weights != nullptr;
+    const std::vector<uint32_t> edges =
+        weights ? pack_in_edges(n_bfs, brp, bcol, directed) : pack_in_edges(n, rp, col, directed);
     // The descent gives one thread to each node, in this order: nodes sorted
     // by decreasing degree within windows of kOrderWindow consecutive nodes,
     // so a wavefront's neighbour loops have similar trip counts while the
@@ -298,14 +346,17 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     auto fail = [&](qc_status s) { destroy(g, region == nullptr); return s; };
     if ((st_ = galloc(g, &g->d_row_ptr, rp.size())) || (st_ = galloc(g, &g->d_col, col.size())) ||
         (st_ = galloc(g, &g->d_order, order.size())) ||
+        (weights && ((st_ = galloc(g, &g->d_bfs_row_ptr, brp.size())) ||
+                     (st_ = galloc(g, &g->d_bfs_col, bcol.size())))) ||
         (st_ = galloc(g, &g->d_edges, edges.size())) || (st_ = galloc(g, &g->d_status, 2)) ||
         (st_ = galloc(g, &g->d_recheck, 1)) || (st_ = galloc(g, &g->d_desc, 1)) ||
         (st_ = galloc(g, &g->d_node_jobs, njobs.size())))
         return fail(st_);
     if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
         (st_ = upload(g->d_order, order)) ||
+        (weights && ((st_ = upload(g->d_bfs_row_ptr, brp)) || (st_ = upload(g->d_bfs_col, bcol)))) ||
         (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
-        (st_ = set_plan(g, plan_bfs(n, -1))))
+        (st_ = set_plan(g, plan_bfs(n_bfs, -1))))
         return fail(st_);
     if ((st_ = from_hip(launch_fill_u64(g->d_recheck, 1, st))) || (st_ = push_desc(g, st)))
         return fail(st_);

@@ -245,7 +245,9 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by_class;
     for (int i = 0; i < n_graphs; ++i) {
         const BfsPlan &p = graphs[i]->plan;
-        by_class[std::make_tuple(p.bw, p.nw, p.planes, p.shape)].push_back(i);
+        by_class[std::make_tuple(p.bw, p.nw, p.planes,
+                                 p.shape | (graphs[i]->weighted ? kBfsWeighted : 0))]
+            .push_back(i);
     }
     for (auto &kv : by_class) {
         std::vector<std::vector<BfsJob>> per;

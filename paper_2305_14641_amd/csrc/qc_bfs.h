@@ -101,7 +101,7 @@ __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
 // share a source and stride over its CSR row, four independent loads in
 // flight each. (A second pushed level, over the neighbours' rows, serialises
 // on the rows of high-degree neighbours and measured slower than a pull.)
-template <int BW, int kT>
+template <int BW, int kT, bool WEIGHTED>
 __device__ __forceinline__ void push_level1(const GraphDev &G, int s0, int nb,
                                             typename BfsWord<BW>::T *nxt)
 {
@@ -112,9 +112,10 @@ __device__ __forceinline__ void push_level1(const GraphDev &G, int s0, int nb,
     const int part = (int)threadIdx.x % kTps;
     if (b >= nb) return;
     const int s = s0 + b;
-    const int32_t *__restrict__ col = G.col;
-    const int e1 = G.row_ptr[s + 1];
-    for (int e = G.row_ptr[s] + part; e < e1; e += 4 * kTps) {
+    const int32_t *__restrict__ rp = WEIGHTED ? G.bfs_row_ptr : G.row_ptr;
+    const int32_t *__restrict__ col = WEIGHTED ? G.bfs_col : G.col;
+    const int e1 = rp[s + 1];
+    for (int e = rp[s] + part; e < e1; e += 4 * kTps) {
         int u[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) u[k] = (e + k * kTps < e1) ? col[e + k * kTps] : -1;
@@ -144,7 +145,10 @@ template <int SHAPE> struct BfsShape {
     static constexpr bool kTwoFields = SHAPE != kBfsNarrow;
 };
 
-template <int BW, int NW, int P, int SHAPE>
+// WEIGHTED: the graph's edges carry integer weights and the search walks the
+// subdivided graph (G.n_bfs nodes, G.nnz_bfs edges, the first G.n being the
+// graph's own nodes); otherwise the graph itself.
+template <int BW, int NW, int P, int SHAPE, bool WEIGHTED>
 __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDev *__restrict__ graphs,
                                                                    const BfsJob *__restrict__ jobs)
 {
@@ -167,9 +171,12 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     const int n = G.n;
     const int s0 = job.s0;
     const int nb = min(BW, n - s0);
-    const int nwords = (n + W::kPer - 1) / W::kPer;
+    // with weights the BFS walks n_bfs nodes (n plus the nodes that subdivide
+    // edges, which count as reached pairs and levels like any node); only
+    // the first n are sources and get distances written
+    const int nwords = ((WEIGHTED ? G.n_bfs : n) + W::kPer - 1) / W::kPer;
     const int tid = threadIdx.x;
-    const int nquads = (int)((G.nnz + 3) >> 2);
+    const int nquads = (int)(((WEIGHTED ? G.nnz_bfs : G.nnz) + 3) >> 2);
     const global_u4 quads = (global_u4)G.edges;
 
     T plane[NWW][P];
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             // A'. level 1 is pushed from the sources along their CSR rows
             //     (out-edges): a few hundred edges where a pull would scan
             //     the whole edge list.
-            push_level1<BW, kT>(G, s0, nb, nxt);
+            push_level1<BW, kT, WEIGHTED>(G, s0, nb, nxt);
         } else {
             // A. pull over every edge, 8 consecutive edges per thread. Quad
             //    index nquads is the all-zero padding quad: loads clamp to it
@@ -262,10 +269,12 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     // Only the loop over words is unrolled (so the planes keep static register
     // indices); the loop over the word's dwords shifts by a variable amount.
     int8_t *__restrict__ out = G.dist;
+    // words of the graph's own nodes (the first n)
+    const int own_words = WEIGHTED ? (n + W::kPer - 1) / W::kPer : nwords;
 #pragma unroll
     for (int j = 0; j < NWW; ++j) {
         const int w = j * kT + tid;
-        if (w < nwords) {
+        if (w < own_words) {
             const T sw = seen[w];
             T lp[P];
 #pragma unroll
@@ -295,26 +304,31 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
 }
 
 template <int BW, int NW, int P, int SHAPE>
-hipError_t launch_bfs_t(const GraphDev *graphs, const BfsJob *jobs, int n_jobs, hipStream_t stream)
+hipError_t launch_bfs_t(bool weighted, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
+                        hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_bfs<BW, NW, P, SHAPE>), dim3(n_jobs), dim3(BfsShape<SHAPE>::kThreads), 0,
-                       stream, graphs, jobs);
+    if (weighted)
+        hipLaunchKernelGGL((k_bfs<BW, NW, P, SHAPE, true>), dim3(n_jobs),
+                           dim3(BfsShape<SHAPE>::kThreads), 0, stream, graphs, jobs);
+    else
+        hipLaunchKernelGGL((k_bfs<BW, NW, P, SHAPE, false>), dim3(n_jobs),
+                           dim3(BfsShape<SHAPE>::kThreads), 0, stream, graphs, jobs);
     return hipGetLastError();
 }
 
 template <int BW, int P>
-hipError_t launch_bfs_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
-                        hipStream_t stream)
+hipError_t launch_bfs_p(int nw, bool weighted, const GraphDev *graphs, const BfsJob *jobs,
+                        int n_jobs, hipStream_t stream)
 {
     switch (nw) {
-    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
+    case 1: if constexpr (BW != 64) return launch_bfs_t<BW, 1, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
             return hipErrorInvalidValue;
-    case 2: return launch_bfs_t<BW, 2, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
-    case 4: return launch_bfs_t<BW, 4, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
-    case 6: return launch_bfs_t<BW, 6, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
-    case 8: return launch_bfs_t<BW, 8, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
-    case 10: return launch_bfs_t<BW, 10, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
-    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P, kBfsNarrow>(graphs, jobs, n_jobs, stream);
+    case 2: return launch_bfs_t<BW, 2, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_t<BW, 4, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
+    case 6: return launch_bfs_t<BW, 6, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
+    case 8: return launch_bfs_t<BW, 8, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
+    case 10: return launch_bfs_t<BW, 10, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
+    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
              return hipErrorInvalidValue;  // 7 planes x 12 words exceed the registers
     default: return hipErrorInvalidValue;
     }
@@ -322,20 +336,20 @@ hipError_t launch_bfs_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int 
 
 // Two-field, 512-thread shapes (planes 4 or 5 only).
 template <int BW, int P>
-hipError_t launch_bfs_wide_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
-                             hipStream_t stream)
+hipError_t launch_bfs_wide_p(int nw, bool weighted, const GraphDev *graphs, const BfsJob *jobs,
+                             int n_jobs, hipStream_t stream)
 {
     if constexpr (P >= 7 || BW < 8) {
         return hipErrorInvalidValue;
     } else {
         switch (nw) {
-        case 16: return launch_bfs_t<BW, 16, P, kBfsWide>(graphs, jobs, n_jobs, stream);
-        case 24: return launch_bfs_t<BW, 24, P, kBfsWide>(graphs, jobs, n_jobs, stream);
-        case 32: return launch_bfs_t<BW, 32, P, kBfsWide>(graphs, jobs, n_jobs, stream);
-        case 38: if constexpr (P == 4) return launch_bfs_t<BW, 38, P, kBfsWide>(graphs, jobs, n_jobs, stream);
+        case 16: return launch_bfs_t<BW, 16, P, kBfsWide>(weighted, graphs, jobs, n_jobs, stream);
+        case 24: return launch_bfs_t<BW, 24, P, kBfsWide>(weighted, graphs, jobs, n_jobs, stream);
+        case 32: return launch_bfs_t<BW, 32, P, kBfsWide>(weighted, graphs, jobs, n_jobs, stream);
+        case 38: if constexpr (P == 4) return launch_bfs_t<BW, 38, P, kBfsWide>(weighted, graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;  // 5 planes x 38 words exceed the registers
         case 39: if constexpr (P == 4 && BW != 64)
-                     return launch_bfs_t<BW, 39, P, kBfsWide>(graphs, jobs, n_jobs, stream);
+                     return launch_bfs_t<BW, 39, P, kBfsWide>(weighted, graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
         }
@@ -346,17 +360,17 @@ hipError_t launch_bfs_wide_p(int nw, const GraphDev *graphs, const BfsJob *jobs,
 // 14 with 5 (batches of 32 or 64 sources only) are the most that fit 128
 // registers without spills.
 template <int BW, int P>
-hipError_t launch_bfs_wide1024_p(int nw, const GraphDev *graphs, const BfsJob *jobs, int n_jobs,
-                                 hipStream_t stream)
+hipError_t launch_bfs_wide1024_p(int nw, bool weighted, const GraphDev *graphs,
+                                 const BfsJob *jobs, int n_jobs, hipStream_t stream)
 {
     if constexpr (P >= 7 || BW < 8) {
         return hipErrorInvalidValue;
     } else {
         switch (nw) {
         case 14: if constexpr (P == 4 || BW >= 32)
-                     return launch_bfs_t<BW, 14, P, kBfsWide1024>(graphs, jobs, n_jobs, stream);
+                     return launch_bfs_t<BW, 14, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;
-        case 16: if constexpr (P == 4) return launch_bfs_t<BW, 16, P, kBfsWide1024>(graphs, jobs, n_jobs, stream);
+        case 16: if constexpr (P == 4) return launch_bfs_t<BW, 16, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
         }
@@ -367,25 +381,27 @@ template <int BW>
 hipError_t launch_bfs_bw(int nw, int planes, int shape, const GraphDev *graphs, const BfsJob *jobs,
                          int n_jobs, hipStream_t stream)
 {
+    const bool weighted = (shape & kBfsWeighted) != 0;
+    shape &= ~kBfsWeighted;
     if (shape == kBfsWide) {
         switch (planes) {
-        case 4: return launch_bfs_wide_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
-        case 5: return launch_bfs_wide_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);
+        case 4: return launch_bfs_wide_p<BW, 4>(nw, weighted, graphs, jobs, n_jobs, stream);
+        case 5: return launch_bfs_wide_p<BW, 5>(nw, weighted, graphs, jobs, n_jobs, stream);
         default: return hipErrorInvalidValue;
         }
     }
     if (shape == kBfsWide1024) {
         switch (planes) {
-        case 4: return launch_bfs_wide1024_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
-        case 5: return launch_bfs_wide1024_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);
+        case 4: return launch_bfs_wide1024_p<BW, 4>(nw, weighted, graphs, jobs, n_jobs, stream);
+        case 5: return launch_bfs_wide1024_p<BW, 5>(nw, weighted, graphs, jobs, n_jobs, stream);
         default: return hipErrorInvalidValue;
         }
     }
     if (shape != kBfsNarrow) return hipErrorInvalidValue;
     switch (planes) {
-    case 4: return launch_bfs_p<BW, 4>(nw, graphs, jobs, n_jobs, stream);
-    case 5: return launch_bfs_p<BW, 5>(nw, graphs, jobs, n_jobs, stream);
-    case 7: return launch_bfs_p<BW, 7>(nw, graphs, jobs, n_jobs, stream);
+    case 4: return launch_bfs_p<BW, 4>(nw, weighted, graphs, jobs, n_jobs, stream);
+    case 5: return launch_bfs_p<BW, 5>(nw, weighted, graphs, jobs, n_jobs, stream);
+    case 7: return launch_bfs_p<BW, 7>(nw, weighted, graphs, jobs, n_jobs, stream);
     default: return hipErrorInvalidValue;
     }
 }

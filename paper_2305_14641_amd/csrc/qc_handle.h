@@ -31,6 +31,11 @@ struct qc_graph_s {
     int32_t *d_row_ptr = nullptr;
     int32_t *d_col = nullptr;
     int32_t *d_order = nullptr;       // descent thread order (see create_graph)
+    int32_t n_bfs = 0;                // nodes of the graph the BFS walks
+    int64_t nnz_bfs = 0;              // and its edges
+    int32_t *d_bfs_row_ptr = nullptr; // its CSR when edges are weighted (else null)
+    int32_t *d_bfs_col = nullptr;
+    bool weighted = false;
     uint32_t *d_edges = nullptr;
 
     // distances and histograms
@@ -39,6 +44,7 @@ struct qc_graph_s {
     int32_t *d_hist = nullptr;
     int K = 0;
     int32_t dmax = -1;
+    int32_t dmax_bfs = -1;            // largest level of the search (>= dmax when weighted)
     bool have_dist = false;
 
     // potentials
@@ -78,6 +84,10 @@ struct qc_graph_s {
         d.row_ptr = d_row_ptr;
         d.col = d_col;
         d.order = d_order;
+        d.n_bfs = n_bfs;
+        d.nnz_bfs = nnz_bfs;
+        d.bfs_row_ptr = d_bfs_row_ptr ? d_bfs_row_ptr : d_row_ptr;
+        d.bfs_col = d_bfs_row_ptr ? d_bfs_col : d_col;
         d.edges = d_edges;
         d.dist = d_dist;
         d.hist = d_hist;
@@ -175,8 +185,9 @@ qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStr
 // live in an arena region are released after their own stream has drained).
 void destroy(qc_graph g, bool sync = true);
 // qc_graph_create with an optional arena region for every device buffer.
+// `weights` (host, one per CSR entry, or null): integer edge weights 1..126.
 qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                        uint32_t flags, hipStream_t stream, char *region, size_t region_bytes,
-                       qc_graph *out);
+                       qc_graph *out, const uint8_t *weights = nullptr);
 
 }  // namespace qc

@@ -87,6 +87,57 @@ std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
     return edges;
 }
 
+qc_status subdivide_weighted(int32_t n, const std::vector<int32_t> &rp,
+                             const std::vector<int32_t> &col, const uint8_t *w, bool directed,
+                             int32_t &n_out, std::vector<int32_t> &rp_out,
+                             std::vector<int32_t> &col_out)
+{
+    if (!w && !col.empty()) return QC_E_INVAL;
+    int64_t total = n;
+    for (int32_t u = 0; u < n; ++u) {
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            const int32_t v = col[e];
+            if (w[e] < 1 || w[e] > kMaxDist) return QC_E_INVAL;
+            if (!directed) {
+                // the reverse entry exists (canonical CSR); it must agree
+                const int32_t *b = col.data() + rp[v], *f = col.data() + rp[v + 1];
+                const int32_t *it = std::lower_bound(b, f, u);
+                if (it == f || *it != u || w[it - col.data()] != w[e]) return QC_E_NOT_SYMMETRIC;
+                if (v < u) continue;
+            }
+            total += w[e] - 1;
+        }
+    }
+    if (total > kMaxNodes) return QC_E_INVAL;
+    n_out = (int32_t)total;
+    std::vector<std::vector<int32_t>> adj(n_out);
+    int32_t next = n;
+    auto link = [&](int32_t a, int32_t b) {
+        adj[a].push_back(b);
+        if (!directed) adj[b].push_back(a);
+    };
+    for (int32_t u = 0; u < n; ++u) {
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            const int32_t v = col[e];
+            if (!directed && v < u) continue;
+            int32_t prev = u;
+            for (int k = 1; k < w[e]; ++k) {   // w - 1 new nodes along the edge
+                link(prev, next);
+                prev = next++;
+            }
+            link(prev, v);
+        }
+    }
+    rp_out.assign(n_out + 1, 0);
+    col_out.clear();
+    for (int32_t v = 0; v < n_out; ++v) {
+        std::sort(adj[v].begin(), adj[v].end());
+        col_out.insert(col_out.end(), adj[v].begin(), adj[v].end());
+        rp_out[v + 1] = (int32_t)col_out.size();
+    }
+    return QC_OK;
+}
+
 static int32_t uf_find(std::vector<int32_t> &p, int32_t x)
 {
     while (p[x] != x) {

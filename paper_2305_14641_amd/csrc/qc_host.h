@@ -31,6 +31,18 @@ std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
 int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
                          std::vector<int32_t> *comp_size = nullptr);
 
+// Integer edge weights (Section 3.1: a path's length is the sum of its edges'
+// weights): an edge of weight w >= 2 becomes a path of w unit edges through
+// w - 1 new nodes numbered from n on, so unit-edge hop distances between the
+// original nodes are the weighted shortest-path lengths. `w` holds one weight
+// (1..126) per CSR entry of the canonical CSR (rp, col). Returns QC_E_INVAL
+// for a weight outside 1..126 or more than kMaxNodes nodes in all, and
+// QC_E_NOT_SYMMETRIC when the two entries of an undirected edge differ.
+qc_status subdivide_weighted(int32_t n, const std::vector<int32_t> &rp,
+                             const std::vector<int32_t> &col, const uint8_t *w, bool directed,
+                             int32_t &n_out, std::vector<int32_t> &rp_out,
+                             std::vector<int32_t> &col_out);
+
 // BFS launch shape for a graph of n nodes whose largest finite distance is
 // dmax (or -1 while unknown): `planes` distance bit-planes (enough for dmax,
 // 7 when unknown), and the widest batch of sources whose LDS bit fields and

@@ -19,6 +19,8 @@ constexpr int kBfsThreadsWide = 512;
 // BFS workgroup shapes: three fields x 1024 threads, two fields x 512
 // threads, two fields x 1024 threads.
 enum { kBfsNarrow = 0, kBfsWide = 1, kBfsWide1024 = 2 };
+// Added to a shape at launch: the graph carries integer edge weights.
+constexpr int kBfsWeighted = 16;
 // 32-bit words of each LDS bit field one BFS thread owns at most (the three
 // fields of 13 x 1024 words fill 156 KB of the 160 KB LDS).
 constexpr int kBfsMaxWordsPerThread = 13;
@@ -39,8 +41,16 @@ struct GraphDev {
     int64_t nnz;
     const int32_t *row_ptr;   // [n+1]
     const int32_t *col;       // [nnz]
+    // The graph the BFS walks: the same CSR, or (integer edge weights) the
+    // graph with every edge of weight w subdivided into w unit edges; its
+    // first n nodes are the graph's nodes.
+    int32_t n_bfs;
+    int32_t pad_bfs;
+    int64_t nnz_bfs;              // its edges (= nnz without weights)
+    const int32_t *bfs_row_ptr;   // [n_bfs+1]
+    const int32_t *bfs_col;
     const int32_t *order;     // [n] nodes by decreasing degree within windows of kOrderWindow
-    const uint32_t *edges;    // [nnz] packed (row << 16) | col, rows ascending
+    const uint32_t *edges;    // packed in-edges (row << 16) | col of the BFS graph, rows ascending
     int8_t *dist;             // [n*n] row-major
     int32_t *hist;            // [n*K]
     float *psi;               // [n_sigmas*n] resident
@@ -87,7 +97,8 @@ hipError_t launch_set_desc(GraphDev *dst, const GraphDev &src, hipStream_t strea
 // Multi-source BFS over `n_jobs` (graph, source-batch) jobs; every graph of the
 // launch must share the batch width `bw`, words-per-thread `nw` and the
 // number of distance bit-planes `planes` (4, 5 or 7; levels < 2^planes).
-// `shape` is kBfsNarrow, kBfsWide or kBfsWide1024.
+// `shape` is kBfsNarrow, kBfsWide or kBfsWide1024, plus kBfsWeighted for a
+// graph with integer edge weights.
 hipError_t launch_bfs(int bw, int nw, int planes, int shape, const GraphDev *graphs,
                       const BfsJob *jobs, int n_jobs, hipStream_t stream);
 // One batch width (qc_bfs_<bw>.hip).

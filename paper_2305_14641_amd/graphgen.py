@@ -225,6 +225,21 @@ def dcsbm_directed(n: int, block_fracs, mean_out_degree: float, seed: int, mu: f
                  name=f"dcsbm_directed(n={n},blocks={nb},outdeg={mean_out_degree:g},seed={seed})")
 
 
+def edge_weights(g: Graph, max_weight: int, seed: int, directed: bool = False) -> np.ndarray:
+    """Seeded integer weights 1..max_weight, one per CSR entry (uint8). For an
+    undirected graph both directions of an edge get the same weight."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    cols = g.col.astype(np.int64)
+    if directed:
+        return rng.integers(1, max_weight + 1, g.nnz).astype(np.uint8)
+    lo, hi = np.minimum(rows, cols), np.maximum(rows, cols)
+    key = lo * g.n + hi
+    uniq, inv = np.unique(key, return_inverse=True)
+    w = rng.integers(1, max_weight + 1, uniq.shape[0]).astype(np.uint8)
+    return w[inv]
+
+
 def random_digraph(n: int, p: float, seed: int) -> Graph:
     """Directed Erdos-Renyi graph: each ordered pair an arc with probability p."""
     rng = np.random.default_rng(seed)

@@ -36,7 +36,8 @@ GRAPH_DIRECTED = 2
 
 # Every symbol include/qc.h declares (checked by the tests).
 EXPORTED = [
-    "qc_status_str", "qc_device_count", "qc_graph_create", "qc_graph_destroy",
+    "qc_status_str", "qc_device_count", "qc_graph_create", "qc_graph_create_weighted",
+    "qc_graph_destroy",
     "qc_graph_info", "qc_distances", "qc_get_histograms", "qc_potential",
     "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync", "qc_timing_enable",
     "qc_timing_read", "qc_potential_dense",
@@ -98,6 +99,7 @@ def lib():
         L.qc_status_str.restype = ctypes.c_char_p
         L.qc_device_count.argtypes = [P]
         L.qc_graph_create.argtypes = [I32, I64, P, P, U32, P, P]
+        L.qc_graph_create_weighted.argtypes = [I32, I64, P, P, P, U32, P, P]
         L.qc_graph_destroy.argtypes = [P]
         L.qc_graph_info.argtypes = [P, P, P, P, P]
         L.qc_distances.argtypes = [P, P, P, P]
@@ -174,17 +176,29 @@ class Graph:
     """A graph handle: CSR uploaded once, distances/potentials resident."""
 
     def __init__(self, n: int, row_ptr, col, canonicalize: bool = False, directed: bool = False,
-                 stream=None):
+                 weights=None, stream=None):
+        """CSR graph; `weights` (one integer 1..126 per CSR entry) makes the
+        distances weighted shortest-path lengths (qc_graph_create_weighted)."""
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         c = np.ascontiguousarray(col, dtype=np.int32)
         self._rp, self._col = rp, c
         h = ctypes.c_void_p()
-        st = lib().qc_graph_create(
-            int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
-            c.ctypes.data_as(ctypes.c_void_p),
-            (GRAPH_CANONICALIZE if canonicalize else 0) | (GRAPH_DIRECTED if directed else 0),
-            _stream_ptr(stream), ctypes.byref(h))
-        _check(st, "qc_graph_create")
+        flags = (GRAPH_CANONICALIZE if canonicalize else 0) | (GRAPH_DIRECTED if directed else 0)
+        if weights is None:
+            st = lib().qc_graph_create(
+                int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+                c.ctypes.data_as(ctypes.c_void_p), flags, _stream_ptr(stream), ctypes.byref(h))
+            _check(st, "qc_graph_create")
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.uint8)
+            if w.shape != c.shape:
+                raise ValueError("one weight per CSR entry")
+            self._w = w
+            st = lib().qc_graph_create_weighted(
+                int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+                c.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p), flags,
+                _stream_ptr(stream), ctypes.byref(h))
+            _check(st, "qc_graph_create_weighted")
         self._h = h
         self.n = int(n)
         self.sigmas = None

@@ -158,3 +158,41 @@ def test_directed_flag_validation_on_host():
     assert create(3, [0, 2, 2, 2], [1, 1], flags=D) == qc.QC_E_NOT_SYMMETRIC  # duplicate arc
     assert create(3, [0, 3, 3, 3], [2, 1, 1], flags=D | qc.GRAPH_CANONICALIZE) == ok
     assert create(3, [0, 1, 2, 2], [1, 2], flags=4) == qc.QC_E_INVAL           # unknown flag
+
+
+def test_weighted_graph_validation_on_host():
+    """qc_graph_create_weighted checks weights before touching a device."""
+    L = qc.lib()
+
+    def create_w(n, rp, col, w, flags=0):
+        h = ctypes.c_void_p()
+        rp = np.ascontiguousarray(rp, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        w = np.ascontiguousarray(w, dtype=np.uint8)
+        st = L.qc_graph_create_weighted(n, col.shape[0], rp.ctypes.data_as(ctypes.c_void_p),
+                                        col.ctypes.data_as(ctypes.c_void_p) if col.size else None,
+                                        w.ctypes.data_as(ctypes.c_void_p) if w.size else None,
+                                        flags, None, ctypes.byref(h))
+        if st == qc.QC_OK:
+            L.qc_graph_destroy(h)
+        return st
+
+    ok = qc.QC_OK if qc.device_count() > 0 else qc.QC_E_DEVICE
+    path = (3, [0, 1, 3, 4], [1, 0, 2, 1])              # 0-1-2
+    assert create_w(*path, [2, 2, 5, 5]) == ok
+    assert create_w(*path, [2, 3, 5, 5]) == qc.QC_E_NOT_SYMMETRIC   # the two entries differ
+    assert create_w(*path, [0, 0, 5, 5]) == qc.QC_E_INVAL           # weight 0
+    assert create_w(*path, [127, 127, 5, 5]) == qc.QC_E_INVAL       # above 126
+    assert create_w(*path, [2, 2, 5, 5], flags=qc.GRAPH_CANONICALIZE) == qc.QC_E_INVAL
+    assert create_w(3, [0, 1, 2, 2], [1, 2], [9, 4], flags=qc.GRAPH_DIRECTED) == ok
+    # a star of 600 nodes whose 599 edges weigh 126 has 600 + 599 * 125 = 75,475
+    # nodes once subdivided: too many; with weight 100, 59,901 nodes fit
+    n = 600
+    rows = np.concatenate([np.zeros(n - 1, dtype=np.int32), np.arange(1, n, dtype=np.int32)])
+    cols = np.concatenate([np.arange(1, n, dtype=np.int32), np.zeros(n - 1, dtype=np.int32)])
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    assert create_w(n, rp, cols, np.full(cols.shape[0], 126, dtype=np.uint8)) == qc.QC_E_INVAL
+    assert create_w(n, rp, cols, np.full(cols.shape[0], 100, dtype=np.uint8)) == ok

@@ -187,3 +187,47 @@ def test_directed_generator_is_canonical_and_seeded():
     # genuinely directed: most arcs have no reverse arc
     fwd = set(zip(rows.tolist(), g.col.tolist()))
     assert sum((b, a) in fwd for a, b in fwd) < 0.2 * len(fwd)
+
+
+# --- integer edge weights: shortest-path lengths (Dijkstra with buckets) -----
+
+WEIGHTED = [(gg.random_graph(30, 0.12, seed=s), 1 + s % 5) for s in range(4)] + [
+    (gg.config2(), 3), (gg.dcsbm_directed(300, [0.5, 0.5], 2.0, seed=8), 4)]
+
+
+@pytest.mark.parametrize("case", range(len(WEIGHTED)))
+def test_weighted_rows_match_scipy_and_networkx(case):
+    import networkx as nx
+    g, wmax = WEIGHTED[case]
+    directed = g.name.startswith("dcsbm_directed")
+    w = gg.edge_weights(g, wmax, seed=case, directed=directed)
+    d, dmax = oracle.weighted_distances(g.n, g.row_ptr, g.col, w)
+    a = sp.csr_matrix((w.astype(np.float64), g.col, g.row_ptr), shape=(g.n, g.n))
+    ref = csg.shortest_path(a, directed=directed)
+    ref = np.where(np.isinf(ref), -1, ref).astype(np.int8)
+    np.testing.assert_array_equal(d, ref)
+    assert dmax == ref.max()
+    G = nx.DiGraph() if directed else nx.Graph()
+    G.add_nodes_from(range(g.n))
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    G.add_weighted_edges_from(zip(rows.tolist(), g.col.tolist(), w.tolist()))
+    for s in range(0, g.n, max(1, g.n // 5)):
+        want = np.full(g.n, -1, dtype=np.int8)
+        for v, l in nx.single_source_dijkstra_path_length(G, s).items():
+            want[v] = l
+        np.testing.assert_array_equal(d[s], want)
+
+
+def test_unit_weights_equal_hop_distances():
+    g = gg.config1()
+    d_hop, _ = oracle.distances(g.n, g.row_ptr, g.col)
+    d_w, _ = oracle.weighted_distances(g.n, g.row_ptr, g.col, np.ones(g.nnz, dtype=np.uint8))
+    np.testing.assert_array_equal(d_hop, d_w)
+
+
+def test_weighted_overflow_and_zero_weight():
+    g = gg.path_graph(4)
+    with pytest.raises(oracle.OracleError):
+        oracle.weighted_distances(g.n, g.row_ptr, g.col, np.full(g.nnz, 50, dtype=np.uint8))
+    with pytest.raises(oracle.OracleError):
+        oracle.weighted_distances(g.n, g.row_ptr, g.col, np.zeros(g.nnz, dtype=np.uint8))
