@@ -46,6 +46,20 @@ def bfs_bytes(g) -> float:
 PROFILE = os.path.join(ROOT, "profiles", "bench_c4_kernels_and_traffic.json")
 
 
+def profiled_bfs():
+    """The k_bfs entry of the committed counter summary, or None when it is
+    missing or a kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    prof = json.load(open(PROFILE))
+    for rel, digest in prof.get("kernel_sources_sha256", {}).items():
+        path = os.path.join(ROOT, rel)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+            return None
+    return prof.get("k_bfs_tuned")
+
+
 def profiled_traffic():
     """HBM bytes per k_bfs launch measured by rocprofv3 FETCH_SIZE / WRITE_SIZE
     (scaled by a copy-kernel calibration) for the kernel sources as they are
@@ -210,6 +224,20 @@ def dense_profile(kernel: str):
         return prof["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def bfs_alu(stages):
+    """Vector-ALU view of k_bfs: VALU lane-operations per second (counted
+    wavefront instructions x 64 lanes, from the committed counter summary)
+    against the issue rate of 256 CUs x 64 lanes x 2.4 GHz."""
+    prof = profiled_bfs()
+    if not prof or not prof.get("valu_wave_instructions_per_launch"):
+        return None
+    ops = prof["valu_wave_instructions_per_launch"] * 64 / (stages["bfs"]["avg_launch_ms"] * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": "k_bfs", "achieved": ops, "peak": VALU_PEAK_TOPS,
+            "unit": "T VALU lane-ops/s", "frac": ops / VALU_PEAK_TOPS,
+            "valu_wave_instructions_per_launch": prof["valu_wave_instructions_per_launch"],
+            "lds_wave_instructions_per_launch": prof.get("lds_wave_instructions_per_launch")}
 
 
 def dense_leg(args, qc, torch) -> dict:
@@ -468,6 +496,7 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
             "algorithmic_bytes_per_launch": bytes_step / bfs_launches,
         },
+        "bfs_alu": bfs_alu(stages),
         "hist_kernel_gbs": hist_gbs,
         "plain": plain,
         "bf16_sweep": bf16,
