@@ -84,3 +84,47 @@ def test_serving_stream_full_size():
             ref_lab = oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v_c, 0))
             np.testing.assert_array_equal(labels[s], ref_lab, err_msg=f"request {r} sigma {sigma}")
     srv.close()
+
+
+def test_maximum_node_count():
+    """n = 65,536, the largest graph the library takes (edges pack two 16-bit
+    ids): sampled distance rows and columns bit-exact against the oracle;
+    every histogram checked against what the graph fixes (h[i][0] = 1,
+    h[i][1] = degree, row sum = component size); psi/V and labels against the
+    oracle's canonical form and descent on those histograms."""
+    import torch
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    from paper_2305_14641_amd import qc
+    n = 65536
+    g = gg.dcsbm(n, [0.5, 0.3, 0.2], 3.0, seed=65536)
+    print(f"[gpu] maximum node count: n={g.n} nnz={g.nnz}", flush=True)
+    G = qc.Graph.from_graph(g)
+    dist = torch.empty((n, n), dtype=torch.int8, device="cuda")
+    dmax = G.distances(dist)
+    rows = np.unique(np.concatenate([np.random.default_rng(1).choice(n, 24, replace=False),
+                                     [0, n - 1]])).astype(np.int32)
+    ref_rows, ref_dmax_rows = oracle.bfs_rows(n, g.row_ptr, g.col, rows)
+    idx = torch.as_tensor(rows.astype(np.int64), device="cuda")
+    np.testing.assert_array_equal(dist[idx].cpu().numpy(), ref_rows)
+    np.testing.assert_array_equal(dist[:, idx].cpu().numpy().T, ref_rows)   # symmetry
+    assert ref_dmax_rows <= dmax
+    del dist
+    torch.cuda.empty_cache()
+    hist = G.histograms().cpu().numpy().astype(np.int64)
+    a = csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(n, n))
+    _, comp = connected_components(a, directed=False)
+    comp_size = np.bincount(comp)[comp]
+    assert (hist[:, 0] == 1).all()
+    np.testing.assert_array_equal(hist[:, 1], np.diff(g.row_ptr))
+    np.testing.assert_array_equal(hist.sum(axis=1), comp_size)
+    assert int(np.nonzero(hist.any(axis=0))[0].max()) == dmax
+    sigma = 2.0
+    psi, v = G.potential([sigma])
+    lab = G.labels(0, qc.TIE_STRICT).cpu().numpy()
+    psi_c, v_c = oracle.potential_canonical(hist.astype(np.int32), sigma)
+    assert rel_err(psi.cpu().numpy()[0], psi_c) <= 1e-6
+    assert rel_err(v.cpu().numpy()[0], v_c) <= 1e-6
+    ref_lab = oracle.find_centers(oracle.ggd_parent(n, g.row_ptr, g.col, v_c, 0))
+    np.testing.assert_array_equal(lab, ref_lab)
+    G.close()
