@@ -27,18 +27,15 @@ hipError_t launch_bfs(int bw, int nw, int planes, int shape, const GraphDev *gra
 // ===========================================================================
 // Distance histograms h[i][k] = #{j : d(i,j) = k} from resident int8 rows.
 // One wavefront per row (RPW rows per wavefront per job). Every lane counts
-// into its own LDS column, so increments never collide; two bins share one
-// 32-bit word as 16-bit halves (a lane sees at most 1,024 bytes of a row of
-// at most 65,536 nodes, so a half cannot overflow), which halves the LDS a
-// wavefront needs and lets four workgroups share a CU. One extra bin absorbs
-// unreachable entries (-1 read as 255), keeping the per-byte work
-// branch-free. Lane k then sums bin k over the 64 columns with a rotated
-// start, free of bank conflicts.
+// into its own LDS column (bins[k][lane]), so increments never collide, with
+// one extra bin that absorbs unreachable entries (-1 read as 255), which keeps
+// the per-byte work branch-free: extract and clamp the byte, form the bin's
+// address, one no-return LDS add. Lane k then sums bin k over the 64 columns
+// with a rotated start, free of bank conflicts. (Two bins per word as 16-bit
+// halves would halve the LDS but doubles the per-byte ALU work, and the
+// registers already cap the kernel at four wavefronts per SIMD.)
 // Loads are aligned 16-byte chunks, kHistDepth per lane in flight while the
-// previous group is counted (the kernel is bound by HBM latency otherwise);
-// prefetch addresses are clamped to the row's last chunk (and the buffer's
-// last whole one), and only chunks that straddle the row's ends check bytes
-// against the row.
+// previous group is counted (the kernel is bound by HBM latency otherwise).
 // ===========================================================================
 
 #ifndef QC_HIST_DEPTH
@@ -50,8 +47,7 @@ template <int K, int WAVES, int RPW>
 __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict__ graphs,
                                                      const NodeJob *__restrict__ jobs)
 {
-    constexpr int KW = (K + 2) / 2;   // words holding bins 0..K (K = unreachable)
-    __shared__ uint32_t bins[WAVES][KW][64];
+    __shared__ uint32_t bins[WAVES][K + 1][64];
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
@@ -61,59 +57,67 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     const int64_t total = (int64_t)n * n;
     const bool vec_ok = total >= 16;
     const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
-    const u32x4 z4 = {0u, 0u, 0u, 0u};
     constexpr int64_t kStep = 64 * 16;   // bytes one wavefront covers per chunk
+    uint32_t *const col = &bins[wave][0][lane];
 
     auto count = [&](uint32_t u) {
-        const uint32_t b = min(u, (uint32_t)K);
-        __hip_atomic_fetch_add(&bins[wave][b >> 1][lane], 1u << ((b & 1u) * 16u),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(col + 64 * min(u, (uint32_t)K), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     };
 
     for (int rr = 0; rr < RPW; ++rr) {
         const int row = job.i0 + rr * WAVES + wave;
         const bool active = row < n;
 #pragma unroll
-        for (int k = 0; k < KW; ++k) bins[wave][k][lane] = 0;
-        if (active) {
+        for (int k = 0; k <= K; ++k) bins[wave][k][lane] = 0;
+        if (active && vec_ok) {
             const int64_t r0 = (int64_t)row * n;
             const int64_t r1 = r0 + n;
             const int64_t first = (r0 & ~(int64_t)15) + lane * 16;
-            // loads past the row's last chunk re-read that chunk (an L2 hit)
+            // Whole 16-byte chunks inside the row are counted in the loop;
+            // a chunk that is not (the row's first or last, cut by its ends)
+            // adds to the junk bin K instead, so the loop has no branches and
+            // the next group of loads stays in flight. Loads past the row's
+            // last chunk re-read that chunk (an L2 hit); a whole chunk inside
+            // the row is never clamped.
             const int64_t last_c = min((r1 - 1) & ~(int64_t)15, last_whole);
             u32x4 cur[kHistDepth];
 #pragma unroll
-            for (int u = 0; u < kHistDepth; ++u)
-                cur[u] = vec_ok ? *(global_u4)(base + min(first + u * kStep, last_c)) : z4;
+            for (int u = 0; u < kHistDepth; ++u) cur[u] = *(global_u4)(base + min(first + u * kStep, last_c));
             for (int64_t c = first; c < r1; c += kHistDepth * kStep) {
                 u32x4 ahead[kHistDepth];
 #pragma unroll
                 for (int u = 0; u < kHistDepth; ++u)
-                    ahead[u] = vec_ok ? *(global_u4)(base + min(c + (kHistDepth + u) * kStep, last_c))
-                                      : z4;
+                    ahead[u] = *(global_u4)(base + min(c + (kHistDepth + u) * kStep, last_c));
 #pragma unroll
                 for (int u = 0; u < kHistDepth; ++u) {
                     const int64_t cc = c + u * kStep;
-                    if (cc >= r0 && cc + 16 <= r1) {
-                        // whole chunk inside the row (and so inside the buffer)
-                        const uint32_t wv[4] = {cur[u].x, cur[u].y, cur[u].z, cur[u].w};
+                    const bool whole = (cc >= r0) && (cc + 16 <= r1);
+                    const uint32_t wv[4] = {cur[u].x, cur[u].y, cur[u].z, cur[u].w};
 #pragma unroll
-                        for (int p = 0; p < 16; ++p) count((wv[p / 4] >> (8 * (p % 4))) & 0xFFu);
-                    } else if (cc < r1) {
-                        for (int64_t f = max(cc, r0); f < cc + 16 && f < r1; ++f)
-                            count((uint32_t)(uint8_t)base[f]);
-                    }
+                    for (int p = 0; p < 16; ++p)
+                        count(whole ? (wv[p / 4] >> (8 * (p % 4))) & 0xFFu : (uint32_t)K);
                 }
 #pragma unroll
                 for (int u = 0; u < kHistDepth; ++u) cur[u] = ahead[u];
             }
+            // the row's bytes outside whole chunks: at most 15 at each end
+            const int64_t head_end = min(r1, (r0 + 15) & ~(int64_t)15);
+            const int64_t tail_begin = max(r1 & ~(int64_t)15, head_end);
+            const int64_t f = (lane < 16) ? r0 + lane : tail_begin + (lane - 16);
+            if ((lane < 16 && f < head_end) || (lane >= 16 && lane < 32 && f < r1))
+                count((uint32_t)(uint8_t)base[f]);
+        } else if (active) {
+            // a matrix of fewer than 16 bytes: byte loads
+            const int64_t r0 = (int64_t)row * n;
+            for (int64_t f = r0 + lane; f < r0 + n; f += 64) count((uint32_t)(uint8_t)base[f]);
         }
         __syncthreads();
         if (active) {
             int32_t *__restrict__ h = G.hist + (int64_t)row * G.K;
             for (int k = lane; k < K; k += 64) {
                 uint32_t sum = 0;
-                for (int l = 0; l < 64; ++l) sum += (bins[wave][k >> 1][(l + k) & 63] >> ((k & 1) * 16)) & 0xFFFFu;
+                for (int l = 0; l < 64; ++l) sum += bins[wave][k][(l + k) & 63];
                 h[k] = (int32_t)sum;
             }
             for (int k = K + lane; k < G.K; k += 64) h[k] = 0;
