@@ -397,6 +397,11 @@ __device__ __noinline__ double canonical_v(const int32_t *__restrict__ h, int km
     return inv_a * (s1 / s2);
 }
 
+#ifndef QC_GGD_UNROLL
+#define QC_GGD_UNROLL 4
+#endif
+constexpr int kGgdUnroll = QC_GGD_UNROLL;
+
 __device__ __forceinline__ double fp64_v(const GraphDev &G, int s, int node)
 {
     if (G.v64) return G.v64[(int64_t)s * G.n + node];
@@ -426,11 +431,26 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
         const float vi = V[i];
         float m1 = FLT_MAX, m2 = FLT_MAX;
         int j1 = -1;
-        for (int e = e0; e < e1; ++e) {
-            const int j = col[e];
-            const float vj = V[j];
-            if (vj < m1) { m2 = m1; m1 = vj; j1 = j; }
-            else if (vj < m2) m2 = vj;
+        // kGgdUnroll neighbours per round: their column indices load
+        // together, then their V values, so a round waits for two memory
+        // latencies instead of two per neighbour. Slots past the row's end
+        // re-read its last entry (in bounds) and take no part in the minima;
+        // the slots are scanned in edge order, so the first minimum wins as in
+        // a plain scan.
+        for (int e = e0; e < e1; e += kGgdUnroll) {
+            int j[kGgdUnroll];
+            float vj[kGgdUnroll];
+#pragma unroll
+            for (int u = 0; u < kGgdUnroll; ++u) j[u] = col[min(e + u, e1 - 1)];
+#pragma unroll
+            for (int u = 0; u < kGgdUnroll; ++u) vj[u] = V[j[u]];
+#pragma unroll
+            for (int u = 0; u < kGgdUnroll; ++u) {
+                if (e + u < e1) {
+                    if (vj[u] < m1) { m2 = m1; m1 = vj[u]; j1 = j[u]; }
+                    else if (vj[u] < m2) m2 = vj[u];
+                }
+            }
         }
         int parent = i;
         if (j1 >= 0) {
