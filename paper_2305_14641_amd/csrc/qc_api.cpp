@@ -1,6 +1,7 @@
 // C ABI of the library (include/qc.h): graph handles, resident device state,
 // and the launch sequence of each call.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -59,7 +60,7 @@ qc_status push_desc(qc_graph g, hipStream_t st)
 uint32_t batch_target(qc_graph g, int s0, int bw)
 {
     uint64_t t = 0;
-    for (int s = s0; s < s0 + bw && s < g->n; ++s) t += (uint64_t)g->comp_size[s];
+    for (int s = s0; s < s0 + bw && s < g->n; ++s) t += (uint64_t)g->comp_size[g->src_order[s]];
     return (uint32_t)t;
 }
 
@@ -206,6 +207,7 @@ void destroy(qc_graph g, bool sync)
     gfree(g, g->d_row_ptr);
     gfree(g, g->d_col);
     gfree(g, g->d_order);
+    gfree(g, g->d_src);
     gfree(g, g->d_bfs_row_ptr);
     gfree(g, g->d_bfs_col);
     gfree(g, g->d_edges);
@@ -338,6 +340,17 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     for (int32_t i0 = 0; i0 < n; i0 += kOrderWindow)
         std::stable_sort(order.begin() + i0, order.begin() + std::min(n, i0 + kOrderWindow),
                          [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    // BFS sources by estimated eccentricity (undirected graphs; a directed
+    // graph keeps its node order). QC_SOURCE_ORDER=identity keeps the node
+    // order for every graph (a switch for measurements and tests).
+    const char *so = getenv("QC_SOURCE_ORDER");
+    if (!directed && !(so && strcmp(so, "identity") == 0)) {
+        g->src_order = weights ? source_order(n_bfs, brp, bcol, n, kSourceSweeps)
+                               : source_order(n, rp, col, n, kSourceSweeps);
+    } else {
+        g->src_order.resize(n);
+        std::iota(g->src_order.begin(), g->src_order.end(), 0);
+    }
     std::vector<NodeJob> njobs;
     for (int i = 0; i < n; i += kNodesPerJob) njobs.push_back(NodeJob{0, i, 0});
     g->n_node_jobs = (int)njobs.size();
@@ -346,6 +359,7 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     auto fail = [&](qc_status s) { destroy(g, region == nullptr); return s; };
     if ((st_ = galloc(g, &g->d_row_ptr, rp.size())) || (st_ = galloc(g, &g->d_col, col.size())) ||
         (st_ = galloc(g, &g->d_order, order.size())) ||
+        (st_ = galloc(g, &g->d_src, g->src_order.size())) ||
         (weights && ((st_ = galloc(g, &g->d_bfs_row_ptr, brp.size())) ||
                      (st_ = galloc(g, &g->d_bfs_col, bcol.size())))) ||
         (st_ = galloc(g, &g->d_edges, edges.size())) || (st_ = galloc(g, &g->d_status, 2)) ||
@@ -353,7 +367,7 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
         (st_ = galloc(g, &g->d_node_jobs, njobs.size())))
         return fail(st_);
     if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
-        (st_ = upload(g->d_order, order)) ||
+        (st_ = upload(g->d_order, order)) || (st_ = upload(g->d_src, g->src_order)) ||
         (weights && ((st_ = upload(g->d_bfs_row_ptr, brp)) || (st_ = upload(g->d_bfs_col, bcol)))) ||
         (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
         (st_ = set_plan(g, plan_bfs(n_bfs, -1))))

@@ -1,8 +1,9 @@
 // Multi-source BFS kernel template (instantiated per batch width by
 // qc_bfs_<bw>.hip).
 //
-// One workgroup owns a batch of BW consecutive sources s0..s0+BW-1 and runs
-// the level-synchronous search of all of them at once. LDS holds three bit
+// One workgroup owns a batch of BW sources, entries s0..s0+BW-1 of the
+// graph's source order, and runs the level-synchronous search of all of them
+// at once. LDS holds three bit
 // fields per node: `seen` (the batch sources that have reached the node),
 // `front` (those that reached it at the previous level) and `nxt` (those
 // reaching it at the current level). A level is:
@@ -19,10 +20,10 @@
 // level (plane p holds bit p of every pair's distance; P = 7 covers every
 // distance up to 126, fewer planes suffice once the graph's largest distance
 // is known). Each batch therefore writes its BW output rows exactly once, at
-// the end. Bit b at node v means that source s0+b has reached v, so the
-// pair's distance is entry (s0+b, v) of the row-major matrix (the edge list
-// holds in-edges, so for a directed graph this is the distance from the
-// source): rows s0..s0+BW-1 are this workgroup's.
+// the end. Bit b at node v means that the batch's source b has reached v, so the
+// pair's distance is entry (src[s0+b], v) of the row-major matrix (the edge
+// list holds in-edges, so for a directed graph this is the distance from the
+// source): those BW rows are this workgroup's.
 //
 // The edge list (packed (row << 16) | col, rows ascending, padded with no-op
 // (0, 0) entries to a multiple of 4) is streamed every level with 16-byte
@@ -44,6 +45,31 @@ template <> struct BfsWord<64> {
     static constexpr int kBits = 64;
     static constexpr int kPer = 1;
 };
+
+// A copy of x the compiler cannot see through: indices derived from it are
+// recomputed where they are used instead of being held in registers for the
+// whole search (the registers go to the distance planes).
+__device__ __forceinline__ int opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Sum of v over the 64 lanes of the wavefront, returned to every lane: an
+// inclusive scan within each row of 16 lanes (DPP row shifts by 1, 2, 4, 8;
+// lanes shifted in from outside the row add 0), then row 15's total is
+// broadcast into rows 1 and 3 and lane 31's into rows 2 and 3, so lane 63
+// holds the total.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 
 // 4-bit mask -> 4 bytes of 0x01 / 0x00 (bit i selects byte i).
 __device__ __forceinline__ uint32_t spread4(uint32_t m4)
@@ -96,13 +122,13 @@ __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
     }
 }
 
-// Level 1 pushed from the sources: source b of the batch (node s0 + b) is
+// Level 1 pushed from the sources: source b of the batch (node srcs[b]) is
 // offered to each of its out-neighbours, nxt[u] |= bit b. kT / BW threads
 // share a source and stride over its CSR row, four independent loads in
 // flight each. (A second pushed level, over the neighbours' rows, serialises
 // on the rows of high-degree neighbours and measured slower than a pull.)
 template <int BW, int kT, bool WEIGHTED>
-__device__ __forceinline__ void push_level1(const GraphDev &G, int s0, int nb,
+__device__ __forceinline__ void push_level1(const GraphDev &G, const int32_t *srcs, int nb,
                                             typename BfsWord<BW>::T *nxt)
 {
     using W = BfsWord<BW>;
@@ -111,7 +137,7 @@ __device__ __forceinline__ void push_level1(const GraphDev &G, int s0, int nb,
     const int b = (int)threadIdx.x / kTps;
     const int part = (int)threadIdx.x % kTps;
     if (b >= nb) return;
-    const int s = s0 + b;
+    const int s = srcs[b];
     const int32_t *__restrict__ rp = WEIGHTED ? G.bfs_row_ptr : G.row_ptr;
     const int32_t *__restrict__ col = WEIGHTED ? G.bfs_col : G.col;
     const int e1 = rp[s + 1];
@@ -164,6 +190,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     __shared__ T nxt[kLdsWords];
     __shared__ T front_store[WIDE ? 1 : kLdsWords];
     __shared__ uint32_t found_pairs;
+    __shared__ int32_t srcs[BW];          // the batch's sources
     T *const front = WIDE ? seen : front_store;
 
     const BfsJob job = jobs[blockIdx.x];
@@ -189,19 +216,21 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
 #pragma unroll
     for (int j = 0; j < NWW; ++j) {
         const int w = j * kT + tid;
-        T bits = 0;
-        if (w < nwords) {
-#pragma unroll
-            for (int q = 0; q < W::kPer; ++q) {
-                const int b = w * W::kPer + q - s0;
-                if (b >= 0 && b < nb) bits |= (T)1 << (q * BW + b);
-            }
-        }
-        seen[w] = bits;
-        if constexpr (!WIDE) front[w] = bits;
+        seen[w] = 0;
+        if constexpr (!WIDE) front[w] = 0;
         nxt[w] = 0;
     }
+    if (tid < nb) srcs[tid] = G.src[s0 + tid];
     if (tid == 0) found_pairs = (uint32_t)nb;   // level 0: every source itself
+    __syncthreads();
+    if (tid < nb) {
+        const int v = srcs[tid];
+        const T bit = (T)1 << ((v % W::kPer) * BW + tid);
+        __hip_atomic_fetch_or(&seen[v / W::kPer], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if constexpr (!WIDE)
+            __hip_atomic_fetch_or(&front[v / W::kPer], bit, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
     __syncthreads();
     uint32_t found_before = (uint32_t)nb;
 
@@ -212,12 +241,12 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             // A'. level 1 is pushed from the sources along their CSR rows
             //     (out-edges): a few hundred edges where a pull would scan
             //     the whole edge list.
-            push_level1<BW, kT, WEIGHTED>(G, s0, nb, nxt);
+            push_level1<BW, kT, WEIGHTED>(G, srcs, nb, nxt);
         } else {
             // A. pull over every edge, 8 consecutive edges per thread. Quad
             //    index nquads is the all-zero padding quad: loads clamp to it
             //    instead of branching, so the next 8 edges stay in flight.
-            int q = 2 * tid;
+            int q = 2 * opaque(tid);
             u32x4 ca = quads[min(q, nquads)];
             u32x4 cb = quads[min(q + 1, nquads)];
             for (; q < nquads; q += 2 * kT) {
@@ -232,9 +261,10 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
         __syncthreads();
         // B. move the new bits of owned words into front / seen / planes.
         uint32_t cnt = 0;
+        const int tb = opaque(tid);
 #pragma unroll
         for (int j = 0; j < NWW; ++j) {
-            const int w = j * kT + tid;
+            const int w = j * kT + tb;
             if (w < nwords) {
                 const T raw = nxt[w];
                 const T sw = seen[w];
@@ -249,7 +279,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             }
         }
         // one LDS atomic per wavefront with the wavefront's count of new pairs
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        cnt = wave_sum(cnt);
         if ((tid & 63) == 0 && cnt) atomicAdd(&found_pairs, cnt);
         __syncthreads();
         const uint32_t found = found_pairs;
@@ -265,15 +295,16 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     }
 
     // Decode the planes of every owned word into distance bytes and write
-    // rows s0..s0+nb-1, columns = owned nodes. Unreached pairs get -1 (0xFF).
+    // rows srcs[0..nb-1], columns = owned nodes. Unreached pairs get -1 (0xFF).
     // Only the loop over words is unrolled (so the planes keep static register
     // indices); the loop over the word's dwords shifts by a variable amount.
     int8_t *__restrict__ out = G.dist;
     // words of the graph's own nodes (the first n)
     const int own_words = WEIGHTED ? (n + W::kPer - 1) / W::kPer : nwords;
+    const int td = opaque(tid);
 #pragma unroll
     for (int j = 0; j < NWW; ++j) {
-        const int w = j * kT + tid;
+        const int w = j * kT + td;
         if (w < own_words) {
             const T sw = seen[w];
             T lp[P];
@@ -292,7 +323,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
                     const int b = i % BW;          // source within the batch
                     const int v = w * W::kPer + qn;
                     if (v < n && b < nb)
-                        out[(int64_t)(s0 + b) * n + v] = (int8_t)((d >> (8 * k)) & 0xFFu);
+                        out[(int64_t)srcs[b] * n + v] = (int8_t)((d >> (8 * k)) & 0xFFu);
                 }
             }
         }
@@ -328,8 +359,8 @@ hipError_t launch_bfs_p(int nw, bool weighted, const GraphDev *graphs, const Bfs
     case 6: return launch_bfs_t<BW, 6, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
     case 8: return launch_bfs_t<BW, 8, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
     case 10: return launch_bfs_t<BW, 10, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
-    case 12: if constexpr (P < 7) return launch_bfs_t<BW, 12, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
-             return hipErrorInvalidValue;  // 7 planes x 12 words exceed the registers
+    case 12: if constexpr (P < 7 || BW < 64) return launch_bfs_t<BW, 12, P, kBfsNarrow>(weighted, graphs, jobs, n_jobs, stream);
+             return hipErrorInvalidValue;  // 7 planes x 12 64-bit halves exceed the registers
     default: return hipErrorInvalidValue;
     }
 }
@@ -356,9 +387,10 @@ hipError_t launch_bfs_wide_p(int nw, bool weighted, const GraphDev *graphs, cons
     }
 }
 
-// Two-field, 1024-thread shapes (planes 4 or 5): 16 words with 4 planes and
-// 14 with 5 (batches of 32 or 64 sources only) are the most that fit 128
-// registers without spills.
+// Two-field, 1024-thread shapes (planes 4 or 5): 19 words with 4 planes (18
+// for 64-bit words) and 16 with 5 (18 for batches of 32) are the most that
+// fit 128 registers without spills; 19 words of both fields also fill the
+// 160 KB of LDS.
 template <int BW, int P>
 hipError_t launch_bfs_wide1024_p(int nw, bool weighted, const GraphDev *graphs,
                                  const BfsJob *jobs, int n_jobs, hipStream_t stream)
@@ -367,10 +399,13 @@ hipError_t launch_bfs_wide1024_p(int nw, bool weighted, const GraphDev *graphs,
         return hipErrorInvalidValue;
     } else {
         switch (nw) {
-        case 14: if constexpr (P == 4 || BW >= 32)
-                     return launch_bfs_t<BW, 14, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
+        case 14: return launch_bfs_t<BW, 14, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
+        case 16: return launch_bfs_t<BW, 16, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
+        case 18: if constexpr (P == 4 || BW == 32)
+                     return launch_bfs_t<BW, 18, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;
-        case 16: if constexpr (P == 4) return launch_bfs_t<BW, 16, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
+        case 19: if constexpr (P == 4 && BW != 64)
+                     return launch_bfs_t<BW, 19, P, kBfsWide1024>(weighted, graphs, jobs, n_jobs, stream);
                  return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
         }

@@ -31,6 +31,8 @@ struct qc_graph_s {
     int32_t *d_row_ptr = nullptr;
     int32_t *d_col = nullptr;
     int32_t *d_order = nullptr;       // descent thread order (see create_graph)
+    std::vector<int32_t> src_order;   // BFS sources in batch order (host copy)
+    int32_t *d_src = nullptr;         // and on the device
     int32_t n_bfs = 0;                // nodes of the graph the BFS walks
     int64_t nnz_bfs = 0;              // and its edges
     int32_t *d_bfs_row_ptr = nullptr; // its CSR when edges are weighted (else null)
@@ -84,6 +86,7 @@ struct qc_graph_s {
         d.row_ptr = d_row_ptr;
         d.col = d_col;
         d.order = d_order;
+        d.src = d_src;
         d.n_bfs = n_bfs;
         d.nnz_bfs = nnz_bfs;
         d.bfs_row_ptr = d_bfs_row_ptr ? d_bfs_row_ptr : d_row_ptr;
@@ -175,7 +178,8 @@ qc_status check_device(int *dev_out);
 qc_status push_desc(qc_graph g, hipStream_t st);
 qc_status ensure_hist_jobs(qc_graph g);
 qc_status set_plan(qc_graph g, const BfsPlan &p);
-// Reachable (source, node) pairs of the batch of sources s0..s0+bw-1.
+// Reachable (source, node) pairs of the batch of sources at positions
+// s0..s0+bw-1 of the source order.
 uint32_t batch_target(qc_graph g, int s0, int bw);
 qc_status run_distances(qc_graph g, hipStream_t st);
 qc_status ensure_sigma_buffers(qc_graph g, int S);

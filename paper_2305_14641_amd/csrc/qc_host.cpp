@@ -170,6 +170,73 @@ int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::v
     return comps;
 }
 
+std::vector<int32_t> source_order(int32_t n, const std::vector<int32_t> &rp,
+                                  const std::vector<int32_t> &col, int32_t n_src, int sweeps)
+{
+    auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
+    // component labels (BFS) and each component's first seed
+    std::vector<int32_t> comp(n, -1), queue(n), dist(n), seed;
+    for (int32_t v = 0; v < n; ++v) {
+        if (comp[v] >= 0) continue;
+        const int32_t c = (int32_t)seed.size();
+        int32_t head = 0, tail = 0, best = v;
+        queue[tail++] = v;
+        comp[v] = c;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            if (deg(u) > deg(best) || (deg(u) == deg(best) && u < best)) best = u;
+            for (int32_t e = rp[u]; e < rp[u + 1]; ++e)
+                if (comp[col[e]] < 0) {
+                    comp[col[e]] = c;
+                    queue[tail++] = col[e];
+                }
+        }
+        seed.push_back(best);
+    }
+    const size_t n_comp = seed.size();
+    std::vector<int32_t> lo(n, 0), hi(n, INT32_MAX), ecc(n_comp), far(n_comp);
+    for (int s = 0; s < sweeps; ++s) {
+        // one multi-source BFS: each node is reached from its own component's seed
+        std::fill(dist.begin(), dist.end(), -1);
+        int32_t head = 0, tail = 0;
+        for (int32_t x : seed) {
+            dist[x] = 0;
+            queue[tail++] = x;
+        }
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            for (int32_t e = rp[u]; e < rp[u + 1]; ++e)
+                if (dist[col[e]] < 0) {
+                    dist[col[e]] = dist[u] + 1;
+                    queue[tail++] = col[e];
+                }
+        }
+        for (size_t c = 0; c < n_comp; ++c) {
+            ecc[c] = 0;
+            far[c] = seed[c];
+        }
+        for (int32_t i = 0; i < tail; ++i) {   // BFS order: the first node at the largest distance
+            const int32_t u = queue[i], c = comp[u];
+            if (dist[u] > ecc[c]) {
+                ecc[c] = dist[u];
+                far[c] = u;
+            }
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t d = dist[v], e = ecc[comp[v]];
+            lo[v] = std::max(lo[v], std::max(d, e - d));
+            hi[v] = std::min(hi[v], e + d);
+        }
+        seed = far;
+    }
+    std::vector<int32_t> order(n_src);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return lo[a] != lo[b] ? lo[a] < lo[b] : hi[a] < hi[b];
+    });
+    return order;
+}
+
 int planes_for(int32_t dmax)
 {
     if (dmax >= 0 && dmax <= 15) return 4;
@@ -181,21 +248,21 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape)
 {
     static const int kNarrow[] = {1, 2, 4, 6, 8, 10, 12};
     static const int kWide[] = {16, 24, 32, 38, 39};
-    static const int kWide1024[] = {14, 16};
+    static const int kWide1024[] = {14, 16, 18, 19};
     const int planes = planes_for(dmax);
     const bool two = shape != kBfsNarrow;
     BfsPlan none = {0, 0, planes, 0, shape};
     if (two && planes >= 7) return none;
     const int threads = (shape == kBfsWide) ? kBfsThreadsWide : kBfsThreads;
     // words per thread that fit the registers without spills: three-field
-    // shape 10 with 7 planes, 12 with 4-5; two-field 512-thread 39 with 4
-    // planes, 32 with 5; two-field 1024-thread 16 with 4, 14 with 5 (and
-    // then only for batches of 32 or 64 sources)
+    // shape 12 (10 with 7 planes and 64-source batches); two-field 512-thread
+    // 39 with 4 planes, 32 with 5; two-field 1024-thread 19 with 4, 16 with 5
+    // (18 for batches of 32)
     int max_nw;
     const int *opts;
     int nopts;
     if (shape == kBfsNarrow) {
-        max_nw = planes >= 7 ? 10 : 12;
+        max_nw = 12;
         opts = kNarrow;
         nopts = 7;
     } else if (shape == kBfsWide) {
@@ -203,20 +270,20 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape)
         opts = kWide;
         nopts = 5;
     } else {
-        max_nw = planes <= 4 ? 16 : 14;
+        max_nw = planes <= 4 ? 19 : 18;
         opts = kWide1024;
-        nopts = 2;
+        nopts = 4;
     }
     for (int bw : {64, 32, 16, 8, 4}) {
         if (two && bw < 8) continue;
-        // 5 planes of a two-field 1024-thread batch narrower than 32 spill
-        if (shape == kBfsWide1024 && planes == 5 && bw < 32) continue;
         const int64_t words = ((int64_t)n * bw + 31) / 32;  // 32-bit words of one bit field
         const int64_t need = (words + threads - 1) / threads;
         for (int k = 0; k < nopts; ++k) {
             const int nw = opts[k];
             if (nw > max_nw) break;
             if (bw == 64 && (nw % 2)) continue;
+            if (bw == 64 && shape == kBfsNarrow && planes >= 7 && nw > 10) continue;
+            if (shape == kBfsWide1024 && planes == 5 && nw > 16 && bw != 32) continue;
             if (nw >= need) {
                 BfsPlan p;
                 p.bw = bw;

@@ -31,6 +31,18 @@ std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
 int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
                          std::vector<int32_t> *comp_size = nullptr);
 
+// The order in which the BFS takes its sources (batch k holds entries
+// k*bw .. k*bw+bw-1). A batch searches until its farthest-reaching source is
+// done, so sources with similar eccentricities go together: nodes sorted by
+// a lower bound on their eccentricity, then by an upper bound. Both bounds
+// come from `sweeps` BFS sweeps over every component of the undirected graph
+// (rp, col) of n nodes: from its highest-degree node, then each time from the
+// node the previous sweep reached last; for a sweep from c with eccentricity
+// e(c), every node v of the component has max(d(v,c), e(c) - d(v,c)) <= e(v)
+// <= e(c) + d(v,c). The order lists the first n_src nodes (the sources).
+std::vector<int32_t> source_order(int32_t n, const std::vector<int32_t> &rp,
+                                  const std::vector<int32_t> &col, int32_t n_src, int sweeps);
+
 // Integer edge weights (Section 3.1: a path's length is the sum of its edges'
 // weights): an edge of weight w >= 2 becomes a path of w unit edges through
 // w - 1 new nodes numbered from n on, so unit-edge hop distances between the

@@ -50,6 +50,7 @@ struct GraphDev {
     const int32_t *bfs_row_ptr;   // [n_bfs+1]
     const int32_t *bfs_col;
     const int32_t *order;     // [n] nodes by decreasing degree within windows of kOrderWindow
+    const int32_t *src;       // [n] BFS sources in batch order (a permutation of 0..n-1)
     const uint32_t *edges;    // packed in-edges (row << 16) | col of the BFS graph, rows ascending
     int8_t *dist;             // [n*n] row-major
     int32_t *hist;            // [n*K]
@@ -83,6 +84,8 @@ constexpr int kNodesPerJob = 256;
 #define QC_ORDER_WINDOW 4096
 #endif
 constexpr int kOrderWindow = QC_ORDER_WINDOW;
+// BFS sweeps per component behind the eccentricity bounds of the source order
+constexpr int kSourceSweeps = 4;
 
 // Relative FP32 gap under which a descent comparison is re-decided in FP64.
 // It exceeds twice the worst FP32 error of V for both FP64ACC (about 2^-24)

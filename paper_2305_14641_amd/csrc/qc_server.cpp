@@ -223,6 +223,7 @@ int64_t qc_request_footprint(int32_t n, int64_t nnz, int32_t n_sigmas)
     add(4 * (N + 1));                 // row_ptr
     add(4 * nnz);                     // col
     add(4 * N);                       // descent thread order
+    add(4 * N);                       // BFS source order
     add(4 * quads);                   // packed edges
     add(8);                           // status
     add(8);                           // recheck counter

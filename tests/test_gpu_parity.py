@@ -133,13 +133,17 @@ def test_config3_full(torch_cuda):
 
 @pytest.mark.parametrize("n,deg,seed", [
     (3000, 5.0, 21),     # batch width 64
-    (9000, 4.0, 22),     # 32, then 64 (two fields, 512 threads) once dmax is known
+    (9000, 4.0, 22),     # 32, then 64 (two fields, 1024 threads, 18 words) once dmax is known
+    (12000, 4.0, 31),    # 32 (three fields, 12 words, 7 planes), then 32 with 4 planes
     (15000, 4.0, 26),    # 16, then 32 (two fields, 1024 threads, 16 words, 4 planes)
-    (18000, 4.0, 27),    # 16, then 32 (two fields, 512 threads)
+    (18000, 4.0, 27),    # 16, then 32 (two fields, 1024 threads, 18 words)
+    (19000, 4.0, 28),    # 16, then 32 (two fields, 1024 threads, 19 words: all of the LDS)
+    (19800, 4.5, 29),    # 16, then 32 (two fields, 512 threads, 39 words)
     (20001, 3.0, 23),    # 16
     (40000, 3.0, 24),    # 8, then 16 (two fields)
-    (50003, 3.0, 25),    # 4, then 8
+    (50003, 3.0, 25),    # 4, then 8 (two fields, 1024 threads, 14 words, 5 planes)
     (13000, 0.0, 7),     # sparse SBM, largest distance 20: 32 (two fields, 1024 threads, 5 planes)
+    (17000, 0.0, 8),     # sparse SBM, largest distance 19: 16, then 32 (1024 threads, 18 words, 5 planes)
 ])
 def test_batch_width_classes_sampled(torch_cuda, n, deg, seed):
     """Every BFS launch shape, ragged last batch: the first run (7 planes)
@@ -232,6 +236,28 @@ def test_deterministic_and_repeatable(torch_cuda):
     d2 = torch.empty((g.n, g.n), dtype=torch.int8, device="cuda")
     G.distances(d2)
     np.testing.assert_array_equal(d2.cpu().numpy(), a["dist"])
+
+
+@pytest.mark.parametrize("g", [gg.config1(), gg.random_graph(700, 0.004, 9),
+                               gg.disjoint_union(gg.path_graph(90), gg.empty_graph(5),
+                                                 gg.complete_graph(40))],
+                         ids=lambda g: g.name)
+def test_source_order_changes_nothing(torch_cuda, monkeypatch, g):
+    """The BFS takes its sources in an order estimated from eccentricity
+    bounds (batches of sources that end their searches together); the node
+    order (QC_SOURCE_ORDER=identity) must give the same bytes everywhere."""
+    torch = torch_cuda
+    print(f"[gpu] source order {g.name} n={g.n}", flush=True)
+    a = run_gpu(torch, g, [0.7, 2.0])
+    monkeypatch.setenv("QC_SOURCE_ORDER", "identity")
+    b = run_gpu(torch, g, [0.7, 2.0])
+    np.testing.assert_array_equal(a["dist"], b["dist"])
+    assert a["dmax"] == b["dmax"]
+    np.testing.assert_array_equal(a["hist"], b["hist"])
+    assert a["v"].tobytes() == b["v"].tobytes()
+    for k in a["labels"]:
+        np.testing.assert_array_equal(a["labels"][k], b["labels"][k])
+    check_against_oracle(g, [0.7, 2.0], b, ties=(0,), pairsum=False)
 
 
 def test_recheck_counts_exact_ties(torch_cuda):
