@@ -85,7 +85,7 @@ qc_status qc_device_count(int32_t *count_out);
  * Algorithm 1's input, stored sparsely).
  *   n        number of nodes, 1 <= n <= 65536
  *   nnz      number of stored entries (2 x undirected edges, or the directed
- *            edges), 0 <= nnz < 2^31
+ *            edges), 0 <= nnz < 2^29
  *   row_ptr  host, int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
  *   col_idx  host, int32[nnz], neighbours of node i in row_ptr[i]..row_ptr[i+1]-1
  *   flags    0: the CSR must already be canonical (each row strictly
@@ -115,8 +115,9 @@ qc_status qc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
  *   flags    0 or QC_GRAPH_DIRECTED (the CSR must be canonical: no
  *            QC_GRAPH_CANONICALIZE, since the weights follow its entries)
  * Internally an edge of weight w is walked as w unit steps, through w - 1
- * extra nodes, so n + sum over edges of (w - 1) must not exceed 65536
- * (else QC_E_INVAL), and qc_distances reports QC_E_OVERFLOW when any of
+ * extra nodes, so n + sum over edges of (w - 1) must not exceed 65536 and
+ * the entries of the subdivided graph must stay below 2^29 (else
+ * QC_E_INVAL), and qc_distances reports QC_E_OVERFLOW when any of
  * those steps lies farther than 126 from a source (so distances up to 126
  * minus half the heaviest weight are always representable). The descent uses
  * the graph's own edges. Other arguments and errors as qc_graph_create;

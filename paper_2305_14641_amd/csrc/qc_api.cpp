@@ -73,9 +73,13 @@ qc_status set_plan(qc_graph g, const BfsPlan &plan)
         g->plan = p;
         return QC_OK;
     }
+    // last batch first: the source order puts the farthest-reaching sources
+    // (the longest searches) at the end
     std::vector<BfsJob> jobs(p.n_batches);
-    for (int b = 0; b < p.n_batches; ++b)
-        jobs[b] = BfsJob{0, b * p.bw, batch_target(g, b * p.bw, p.bw), 0u};
+    for (int b = 0; b < p.n_batches; ++b) {
+        const int s0 = (p.n_batches - 1 - b) * p.bw;
+        jobs[b] = BfsJob{0, s0, batch_target(g, s0, p.bw), 0u};
+    }
     gfree(g, g->d_bfs_jobs);
     QC_TRY(galloc(g, &g->d_bfs_jobs, jobs.size()));
     QC_TRY(upload(g->d_bfs_jobs, jobs));
@@ -304,7 +308,10 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
                         directed));
     int32_t n_bfs = n;
     std::vector<int32_t> brp, bcol;
-    if (weights) QC_TRY(subdivide_weighted(n, rp, col, weights, directed, n_bfs, brp, bcol));
+    if (weights) {
+        QC_TRY(subdivide_weighted(n, rp, col, weights, directed, n_bfs, brp, bcol));
+        if ((int64_t)bcol.size() >= kMaxEdges) return QC_E_INVAL;
+    }
     int dev = 0;
     QC_TRY(check_device(&dev));
 

@@ -254,8 +254,10 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         std::vector<double> cost;
         for (int gi : kv.second) {
             qc_graph g = graphs[gi];
+            // last batch first: the source order puts the farthest-reaching
+            // sources (the longest searches) at the end
             std::vector<BfsJob> js;
-            for (int bidx = 0; bidx < g->plan.n_batches; ++bidx)
+            for (int bidx = g->plan.n_batches - 1; bidx >= 0; --bidx)
                 js.push_back(BfsJob{gi, bidx * g->plan.bw,
                                     batch_target(g, bidx * g->plan.bw, g->plan.bw), 0u});
             per.push_back(js);

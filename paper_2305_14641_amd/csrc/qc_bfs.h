@@ -27,8 +27,8 @@
 //
 // The edge list (packed (row << 16) | col, rows ascending, padded with no-op
 // (0, 0) entries to a multiple of 4) is streamed every level with 16-byte
-// global loads; every thread takes 8 consecutive edges (the next 8 in
-// flight), issues their 8 front gathers together, then 8 atomics.
+// buffer loads; every thread takes 8 consecutive edges (the next 8 in
+// flight), issues their 8 front gathers together, then up to 8 atomics.
 #pragma once
 
 #include "qc_internal.h"
@@ -94,6 +94,8 @@ __device__ __forceinline__ typename BfsWord<BW>::T field_of(const typename BfsWo
 // of one row is formed with selects (no branches), and only the last edge of
 // a run with something to deliver issues a no-return LDS atomic into nxt[r].
 // Bits r has already seen are harmless: the word's owner masks with seen.
+// brk[k] (edge k ends a run) serves both as "edge k is a run's last" and as
+// "edge k + 1 starts a new run".
 template <int BW>
 __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
                                          const typename BfsWord<BW>::T *src,
@@ -105,21 +107,26 @@ __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
     T x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = field_of<BW>(src, (int)(e[k] & 0xFFFFu));
-    T acc = 0;
+    bool brk[8];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) brk[k] = (e[k] >> 16) != (e[k + 1] >> 16);
+    brk[7] = true;
+    T acc = x[0];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint32_t r = e[k] >> 16;
-        if (k == 0) {
-            acc = x[0];
-        } else {
-            acc = (r == (e[(k + 7) & 7] >> 16)) ? (acc | x[k]) : x[k];
-        }
-        bool last = true;
-        if (k < 7) last = (e[(k + 1) & 7] >> 16) != r;
-        if (last && acc)
+        if (k > 0) acc = brk[k - 1] ? x[k] : (acc | x[k]);
+        if (brk[k] && acc)
             __hip_atomic_fetch_or(&nxt[r / W::kPer], (T)(acc << ((r % W::kPer) * BW)),
                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+}
+
+// 16 bytes of the packed edge list at byte offset `off`; offsets at or past
+// the end read as zeros (the buffer's range check), i.e. no-op edges (0, 0).
+__device__ __forceinline__ u32x4 edge_quad(__amdgpu_buffer_rsrc_t rsrc, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0);
 }
 
 // Level 1 pushed from the sources: source b of the batch (node srcs[b]) is
@@ -186,12 +193,15 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     constexpr int kLdsWords = NWW * kT;
     constexpr int kLevels = (P >= 7) ? kMaxDist : ((1 << P) - 1);  // largest encodable level
 
-    __shared__ T seen[kLdsWords];
-    __shared__ T nxt[kLdsWords];
-    __shared__ T front_store[WIDE ? 1 : kLdsWords];
+    // The fields share one LDS array, the field the pull gathers from first
+    // (LDS address 0, so a gather's address is the column's word offset):
+    // two fields [seen | nxt], three fields [front | nxt | seen].
+    __shared__ T fields[(WIDE ? 2 : 3) * kLdsWords];
     __shared__ uint32_t found_pairs;
     __shared__ int32_t srcs[BW];          // the batch's sources
-    T *const front = WIDE ? seen : front_store;
+    T *const front = fields;
+    T *const nxt = fields + kLdsWords;
+    T *const seen = WIDE ? fields : fields + 2 * kLdsWords;
 
     const BfsJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
@@ -203,8 +213,9 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     // the first n are sources and get distances written
     const int nwords = ((WEIGHTED ? G.n_bfs : n) + W::kPer - 1) / W::kPer;
     const int tid = threadIdx.x;
-    const int nquads = (int)(((WEIGHTED ? G.nnz_bfs : G.nnz) + 3) >> 2);
-    const global_u4 quads = (global_u4)G.edges;
+    const uint32_t quad_bytes = (uint32_t)(((WEIGHTED ? G.nnz_bfs : G.nnz) + 3) >> 2) * 16u;
+    const __amdgpu_buffer_rsrc_t edges =
+        __builtin_amdgcn_make_buffer_rsrc((void *)G.edges, 0, (int)quad_bytes, kBufferWord3);
 
     T plane[NWW][P];
 #pragma unroll
@@ -243,19 +254,36 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             //     the whole edge list.
             push_level1<BW, kT, WEIGHTED>(G, srcs, nb, nxt);
         } else {
-            // A. pull over every edge, 8 consecutive edges per thread. Quad
-            //    index nquads is the all-zero padding quad: loads clamp to it
-            //    instead of branching, so the next 8 edges stay in flight.
-            int q = 2 * opaque(tid);
-            u32x4 ca = quads[min(q, nquads)];
-            u32x4 cb = quads[min(q + 1, nquads)];
-            for (; q < nquads; q += 2 * kT) {
-                const int qn = q + 2 * kT;
-                const u32x4 na = quads[min(qn, nquads)];
-                const u32x4 nb4 = quads[min(qn + 1, nquads)];
-                pull_oct<BW>(ca, cb, front, nxt);
-                ca = na;
-                cb = nb4;
+            // A. pull over every edge, 8 consecutive edges (two quads) per
+            //    thread, the next 8 in flight. Loads past the end read no-op
+            //    edges, so they need no bounds check.
+            //    Unrolled twice where the registers allow, so the two sets of
+            //    quads alternate roles instead of being copied.
+            constexpr uint32_t kStep = 2u * kT * 16u;   // bytes per round of the workgroup
+            constexpr bool kAlternate = !(kT == 1024 && NWW * P > 80);
+            uint32_t off = (uint32_t)opaque(tid) * 32u;
+            u32x4 a0 = edge_quad(edges, off);
+            u32x4 b0 = edge_quad(edges, off + 16u);
+            if constexpr (kAlternate) {
+                while (off < quad_bytes) {
+                    const u32x4 a1 = edge_quad(edges, off + kStep);
+                    const u32x4 b1 = edge_quad(edges, off + kStep + 16u);
+                    pull_oct<BW>(a0, b0, front, nxt);
+                    off += kStep;
+                    if (off >= quad_bytes) break;
+                    a0 = edge_quad(edges, off + kStep);
+                    b0 = edge_quad(edges, off + kStep + 16u);
+                    pull_oct<BW>(a1, b1, front, nxt);
+                    off += kStep;
+                }
+            } else {
+                for (; off < quad_bytes; off += kStep) {
+                    const u32x4 a1 = edge_quad(edges, off + kStep);
+                    const u32x4 b1 = edge_quad(edges, off + kStep + 16u);
+                    pull_oct<BW>(a0, b0, front, nxt);
+                    a0 = a1;
+                    b0 = b1;
+                }
             }
         }
         __syncthreads();

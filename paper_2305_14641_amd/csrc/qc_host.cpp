@@ -16,7 +16,7 @@ qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
                        std::vector<int32_t> &col_out, bool directed)
 {
     if (n < 1 || n > kMaxNodes) return QC_E_INVAL;
-    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return QC_E_INVAL;
+    if (nnz < 0 || nnz >= kMaxEdges) return QC_E_INVAL;
     if (!row_ptr) return QC_E_INVAL;
     if (nnz > 0 && !col) return QC_E_INVAL;
     if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz) return QC_E_INVAL;

@@ -12,6 +12,10 @@ namespace qc {
 constexpr int kMaxDist = 126;
 // Largest supported node count: edges are packed as (row << 16 | col).
 constexpr int kMaxNodes = 65536;
+// Edge entries must stay below this (also after subdividing weighted edges):
+// the packed edge list the BFS streams then spans less than 2 GB, within the
+// 32-bit byte offsets of its buffer loads.
+constexpr int64_t kMaxEdges = (int64_t)1 << 29;
 // Threads per workgroup of the multi-source BFS: the three-field shape (and
 // the 1024-thread two-field one) and the 512-thread two-field ("wide") shape.
 constexpr int kBfsThreads = 1024;
@@ -29,6 +33,9 @@ constexpr int kBfsMaxWordsPerThread = 13;
 // address-space pointer (keeps loads off the flat path).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) u32x4 *global_u4;
+// Word 3 of a buffer resource for raw (untyped, unswizzled) loads on gfx9-family
+// GPUs: 32-bit data format, range checked against the byte count in word 2.
+constexpr int kBufferWord3 = 0x00020000;
 
 // Device-visible description of one graph and its resident buffers.
 // Kernels receive an array of these plus a job table, so one launch can

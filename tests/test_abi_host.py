@@ -71,6 +71,18 @@ def test_invalid_csr_rejected_on_host(case, want):
     assert create(n, rp, col) == want
 
 
+def test_edge_count_limit_checked_first():
+    """nnz must stay below 2^29; the count is checked before the arrays are read."""
+    L = qc.lib()
+    h = ctypes.c_void_p()
+    rp = np.array([0, 1, 2], np.int32)
+    col = np.array([1, 0], np.int32)
+    for nnz in (1 << 29, (1 << 31) - 1, -1):
+        assert L.qc_graph_create(2, nnz, rp.ctypes.data_as(ctypes.c_void_p),
+                                 col.ctypes.data_as(ctypes.c_void_p), 0, None,
+                                 ctypes.byref(h)) == qc.QC_E_INVAL, nnz
+
+
 def test_null_pointers_rejected():
     L = qc.lib()
     h = ctypes.c_void_p()
