@@ -64,11 +64,35 @@ uint32_t batch_target(qc_graph g, int s0, int bw)
     return (uint32_t)t;
 }
 
+// LDS banks the order of the packed edges is chosen for (QC_EDGE_BANKS=0
+// keeps rows-ascending order; a switch for measurements and tests).
+static int edge_banks()
+{
+    const char *s = getenv("QC_EDGE_BANKS");
+    if (!s) return 32;
+    const int b = atoi(s);
+    return (b == 0 || b == 16 || b == 32 || b == 64) ? b : 32;
+}
+
+// Upload the packed edges in the order that spreads the pull's gathers over
+// the LDS banks for batches of `bw` sources.
+static qc_status order_edges(qc_graph g, int bw)
+{
+    std::vector<uint32_t> e = g->edges_host;
+    const int banks = edge_banks();
+    if (banks > 0)
+        spread_gather_banks(e, g->nnz_bfs, bw >= 32 ? 1 : 32 / bw, bw == 64 ? banks / 2 : banks);
+    QC_TRY(upload(g->d_edges, e));
+    g->edges_bw = bw;
+    return QC_OK;
+}
+
 qc_status set_plan(qc_graph g, const BfsPlan &plan)
 {
     if (plan.bw <= 0) return QC_E_INVAL;
     BfsPlan p = plan;
     p.n_batches = (g->n + p.bw - 1) / p.bw;   // sources are the graph's own nodes
+    if (p.bw != g->edges_bw) QC_TRY(order_edges(g, p.bw));
     if (g->d_bfs_jobs && p.bw == g->plan.bw) {
         g->plan = p;
         return QC_OK;
@@ -336,8 +360,9 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     g->n_bfs = n_bfs;
     g->nnz_bfs = weights ? (int64_t)bcol.size() : g->nnz;
     g->weighted = weights != nullptr;
-    const std::vector<uint32_t> edges =
+    g->edges_host =
         weights ? pack_in_edges(n_bfs, brp, bcol, directed) : pack_in_edges(n, rp, col, directed);
+    const std::vector<uint32_t> &edges = g->edges_host;
     // The descent gives one thread to each node, in this order: nodes sorted
     // by decreasing degree within windows of kOrderWindow consecutive nodes,
     // so a wavefront's neighbour loops have similar trip counts while the
@@ -376,7 +401,7 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
         (st_ = upload(g->d_order, order)) || (st_ = upload(g->d_src, g->src_order)) ||
         (weights && ((st_ = upload(g->d_bfs_row_ptr, brp)) || (st_ = upload(g->d_bfs_col, bcol)))) ||
-        (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
+        (st_ = upload(g->d_node_jobs, njobs)) ||   // set_plan uploads the edges
         (st_ = set_plan(g, plan_bfs(n_bfs, -1))))
         return fail(st_);
     if ((st_ = from_hip(launch_fill_u64(g->d_recheck, 1, st))) || (st_ = push_desc(g, st)))

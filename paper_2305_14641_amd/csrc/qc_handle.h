@@ -39,6 +39,8 @@ struct qc_graph_s {
     int32_t *d_bfs_col = nullptr;
     bool weighted = false;
     uint32_t *d_edges = nullptr;
+    std::vector<uint32_t> edges_host; // packed edges, rows ascending (host copy)
+    int edges_bw = 0;                 // batch width d_edges' order was chosen for
 
     // distances and histograms
     int8_t *d_dist_owned = nullptr;   // library-owned matrix (n*n, 16-byte padded)

@@ -26,6 +26,19 @@ qc_status validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
 std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
                                     const std::vector<int32_t> &col, bool directed);
 
+// Reorders the packed edges inside each group of 8 (one thread's share of a
+// pull round) so that the gathers of one LDS pass (the same slot of `banks`
+// consecutive groups, one group per lane) fall into distinct banks where
+// possible: a greedy choice per slot and lane of the edge whose field word
+// shares its bank with the fewest words already chosen (a word already chosen
+// costs nothing: lanes reading one word are served together). The edges of
+// one row stay contiguous within a group, so the pull's run merging (one
+// atomic per run) is unchanged; any order of the edges gives the same search.
+// `nodes_per_word` nodes share a field word (32 / batch width, at least 1);
+// 64-bit words (batches of 64) span two 4-byte banks, so pass banks = 16.
+void spread_gather_banks(std::vector<uint32_t> &edges, int64_t nnz, int nodes_per_word,
+                         int banks);
+
 // Number of connected components (union-find over the canonical CSR); if
 // comp_size is given it receives, for every node, the size of its component.
 int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,

@@ -240,16 +240,22 @@ def test_deterministic_and_repeatable(torch_cuda):
 
 @pytest.mark.parametrize("g", [gg.config1(), gg.random_graph(700, 0.004, 9),
                                gg.disjoint_union(gg.path_graph(90), gg.empty_graph(5),
-                                                 gg.complete_graph(40))],
+                                                 gg.complete_graph(40)),
+                               gg.dcsbm(5000, [0.5, 0.3, 0.2], 5.0, seed=41)],
                          ids=lambda g: g.name)
-def test_source_order_changes_nothing(torch_cuda, monkeypatch, g):
+@pytest.mark.parametrize("env", [{"QC_SOURCE_ORDER": "identity"}, {"QC_EDGE_BANKS": "0"},
+                                 {"QC_EDGE_BANKS": "64"}], ids=lambda e: ",".join(e.values()))
+def test_search_order_changes_nothing(torch_cuda, monkeypatch, g, env):
     """The BFS takes its sources in an order estimated from eccentricity
-    bounds (batches of sources that end their searches together); the node
-    order (QC_SOURCE_ORDER=identity) must give the same bytes everywhere."""
+    bounds, and the edges of each pull group in an order that spreads the
+    gathers over the LDS banks; the node order (QC_SOURCE_ORDER=identity),
+    the plain rows-ascending edge order (QC_EDGE_BANKS=0) or another bank
+    count must give the same bytes everywhere."""
     torch = torch_cuda
-    print(f"[gpu] source order {g.name} n={g.n}", flush=True)
+    print(f"[gpu] search order {g.name} n={g.n} {env}", flush=True)
     a = run_gpu(torch, g, [0.7, 2.0])
-    monkeypatch.setenv("QC_SOURCE_ORDER", "identity")
+    for k, val in env.items():
+        monkeypatch.setenv(k, val)
     b = run_gpu(torch, g, [0.7, 2.0])
     np.testing.assert_array_equal(a["dist"], b["dist"])
     assert a["dmax"] == b["dmax"]
