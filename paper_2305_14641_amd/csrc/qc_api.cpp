@@ -235,6 +235,9 @@ void destroy(qc_graph g, bool sync)
     gfree(g, g->d_row_ptr);
     gfree(g, g->d_col);
     gfree(g, g->d_order);
+    gfree(g, g->d_sell_col);
+    gfree(g, g->d_sell_off);
+    gfree(g, g->d_sell_deg);
     gfree(g, g->d_src);
     gfree(g, g->d_bfs_row_ptr);
     gfree(g, g->d_bfs_col);
@@ -372,6 +375,23 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     for (int32_t i0 = 0; i0 < n; i0 += kOrderWindow)
         std::stable_sort(order.begin() + i0, order.begin() + std::min(n, i0 + kOrderWindow),
                          [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    // ... and reads its node's neighbours from a sliced ELL copy of the CSR
+    // in that order: 64 nodes (one wavefront) per slice, as wide as the
+    // slice's largest degree, slot-major; unused entries hold node 0.
+    const int32_t n_slices = (n + 63) / 64;
+    std::vector<int32_t> sell_off(n_slices + 1, 0), sell_deg(n);
+    for (int32_t t = 0; t < n; ++t) sell_deg[t] = rp[order[t] + 1] - rp[order[t]];
+    for (int32_t w = 0; w < n_slices; ++w) {
+        int32_t width = 0;
+        for (int32_t t = 64 * w; t < std::min(n, 64 * w + 64); ++t) width = std::max(width, sell_deg[t]);
+        sell_off[w + 1] = sell_off[w] + 64 * width;
+    }
+    std::vector<int32_t> sell_col((size_t)sell_off[n_slices] + 64 * kGgdPad, 0);
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t i = order[t], w = t / 64, lane = t % 64;
+        for (int32_t k = 0; k < sell_deg[t]; ++k)
+            sell_col[(size_t)sell_off[w] + 64 * k + lane] = col[rp[i] + k];
+    }
     // BFS sources by estimated eccentricity (undirected graphs; a directed
     // graph keeps its node order). QC_SOURCE_ORDER=identity keeps the node
     // order for every graph (a switch for measurements and tests).
@@ -391,6 +411,9 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     auto fail = [&](qc_status s) { destroy(g, region == nullptr); return s; };
     if ((st_ = galloc(g, &g->d_row_ptr, rp.size())) || (st_ = galloc(g, &g->d_col, col.size())) ||
         (st_ = galloc(g, &g->d_order, order.size())) ||
+        (st_ = galloc(g, &g->d_sell_col, sell_col.size())) ||
+        (st_ = galloc(g, &g->d_sell_off, sell_off.size())) ||
+        (st_ = galloc(g, &g->d_sell_deg, sell_deg.size())) ||
         (st_ = galloc(g, &g->d_src, g->src_order.size())) ||
         (weights && ((st_ = galloc(g, &g->d_bfs_row_ptr, brp.size())) ||
                      (st_ = galloc(g, &g->d_bfs_col, bcol.size())))) ||
@@ -400,6 +423,8 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
         return fail(st_);
     if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
         (st_ = upload(g->d_order, order)) || (st_ = upload(g->d_src, g->src_order)) ||
+        (st_ = upload(g->d_sell_col, sell_col)) || (st_ = upload(g->d_sell_off, sell_off)) ||
+        (st_ = upload(g->d_sell_deg, sell_deg)) ||
         (weights && ((st_ = upload(g->d_bfs_row_ptr, brp)) || (st_ = upload(g->d_bfs_col, bcol)))) ||
         (st_ = upload(g->d_node_jobs, njobs)) ||   // set_plan uploads the edges
         (st_ = set_plan(g, plan_bfs(n_bfs, -1))))

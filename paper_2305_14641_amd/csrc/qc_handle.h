@@ -31,6 +31,9 @@ struct qc_graph_s {
     int32_t *d_row_ptr = nullptr;
     int32_t *d_col = nullptr;
     int32_t *d_order = nullptr;       // descent thread order (see create_graph)
+    int32_t *d_sell_col = nullptr;    // descent neighbour lists, sliced ELL (see GraphDev)
+    int32_t *d_sell_off = nullptr;
+    int32_t *d_sell_deg = nullptr;
     std::vector<int32_t> src_order;   // BFS sources in batch order (host copy)
     int32_t *d_src = nullptr;         // and on the device
     int32_t n_bfs = 0;                // nodes of the graph the BFS walks
@@ -88,6 +91,9 @@ struct qc_graph_s {
         d.row_ptr = d_row_ptr;
         d.col = d_col;
         d.order = d_order;
+        d.sell_col = d_sell_col;
+        d.sell_off = d_sell_off;
+        d.sell_deg = d_sell_deg;
         d.src = d_src;
         d.n_bfs = n_bfs;
         d.nnz_bfs = nnz_bfs;

@@ -57,6 +57,13 @@ struct GraphDev {
     const int32_t *bfs_row_ptr;   // [n_bfs+1]
     const int32_t *bfs_col;
     const int32_t *order;     // [n] nodes by decreasing degree within windows of kOrderWindow
+    // The descent's neighbour lists in sliced ELL layout: slice w holds the
+    // nodes order[64w .. 64w+63], slot-major (entry k of the slice's lane l
+    // at sell_col[sell_off[w] + 64k + l]), so the lanes of a wavefront read
+    // the k-th neighbours of their nodes from one contiguous 256-byte row.
+    const int32_t *sell_col;  // [sell_off[n_slices] + 64 * kGgdPad]
+    const int32_t *sell_off;  // [n_slices + 1]
+    const int32_t *sell_deg;  // [n] degree of node order[t]
     const int32_t *src;       // [n] BFS sources in batch order (a permutation of 0..n-1)
     const uint32_t *edges;    // packed in-edges (row << 16) | col of the BFS graph, rows ascending
     int8_t *dist;             // [n*n] row-major
@@ -91,6 +98,14 @@ constexpr int kNodesPerJob = 256;
 #define QC_ORDER_WINDOW 4096
 #endif
 constexpr int kOrderWindow = QC_ORDER_WINDOW;
+// Neighbours one descent thread loads per round (the sliced neighbour lists
+// carry this many padding rows after the last slice).
+constexpr int kGgdPad = 4;
+// Sigmas one descent thread decides (when the launch covers that many).
+#ifndef QC_GGD_SIGMAS
+#define QC_GGD_SIGMAS 4
+#endif
+constexpr int kGgdSigmas = QC_GGD_SIGMAS;
 // BFS sweeps per component behind the eccentricity bounds of the source order
 constexpr int kSourceSweeps = 4;
 

@@ -397,11 +397,6 @@ __device__ __noinline__ double canonical_v(const int32_t *__restrict__ h, int km
     return inv_a * (s1 / s2);
 }
 
-#ifndef QC_GGD_UNROLL
-#define QC_GGD_UNROLL 4
-#endif
-constexpr int kGgdUnroll = QC_GGD_UNROLL;
-
 __device__ __forceinline__ double fp64_v(const GraphDev &G, int s, int node)
 {
     if (G.v64) return G.v64[(int64_t)s * G.n + node];
@@ -409,88 +404,137 @@ __device__ __forceinline__ double fp64_v(const GraphDev &G, int s, int node)
                        G.inv_a[s]);
 }
 
-__global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev *__restrict__ graphs,
-                                                    const NodeJob *__restrict__ jobs, int sigma_base)
+// The FP64 decision for node i at sigma s: among the neighbours whose FP32 V
+// lies within the bound of the lowest one (m1), the lowest canonical FP64 V,
+// compared with the node's own.
+__device__ __noinline__ int fp64_decide(int tie_mode, const GraphDev &G, int s, int i, float m1)
 {
-    // blockIdx.y is the sigma: the blocks in flight share one sigma, so the
+    const float *__restrict__ V = G.v + (int64_t)s * G.n;
+    const int32_t *__restrict__ col = G.col;
+    const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
+    const double vi64 = fp64_v(G, s, i);
+    double bv = DBL_MAX;
+    int best = -1;
+    for (int e = e0; e < e1; ++e) {
+        const int j = col[e];
+        const float vj = V[j];
+        if (vj - m1 <= kTieTau * vj) {
+            const double d = fp64_v(G, s, j);
+            if (d < bv) {
+                bv = d;
+                best = j;
+            }
+        }
+    }
+    if (tie_mode == 0) return (bv < vi64) ? best : i;
+    return (bv < vi64 || (bv == vi64 && best < i)) ? best : i;
+}
+
+// One thread per node and KS consecutive sigmas: the node's order slot,
+// degree and neighbour indices are loaded once and the V values of all KS
+// sigmas are gathered together, so one chain of dependent loads serves KS
+// decisions (the kernel is bound by memory latency, not by bandwidth).
+template <int KS>
+__global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev *__restrict__ graphs,
+                                                    const NodeJob *__restrict__ jobs, int sigma_base,
+                                                    int sigma_end)
+{
+    // blockIdx.y selects the sigmas: the blocks in flight share them, so the
     // gathered V values (one FP32 plane per sigma, a few MB for a whole
     // batch) stay in L2 while the neighbour lists stream past.
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
-    const int s = sigma_base + (int)blockIdx.y;
+    const int s0 = sigma_base + (int)blockIdx.y * KS;
+    const int s_end = min(sigma_end, G.n_sigmas);
     const int t = job.i0 + (int)threadIdx.x;
-    bool rechecked = false;
-    if (t < n && s < G.n_sigmas) {
+    bool rechecked[KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) rechecked[q] = false;
+    if (t < n && s0 < s_end) {
         // within the job, threads take its nodes by decreasing degree, so the
         // neighbour loops of one wavefront have similar trip counts
         const int i = G.order[t];
-        const float *__restrict__ V = G.v + (int64_t)s * n;
-        const int32_t *__restrict__ col = G.col;
-        const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
-        const float vi = V[i];
-        float m1 = FLT_MAX, m2 = FLT_MAX;
-        int j1 = -1;
-        // kGgdUnroll neighbours per round: their column indices load
-        // together, then their V values, so a round waits for two memory
-        // latencies instead of two per neighbour. Slots past the row's end
-        // re-read its last entry (in bounds) and take no part in the minima;
-        // the slots are scanned in edge order, so the first minimum wins as in
-        // a plain scan.
-        for (int e = e0; e < e1; e += kGgdUnroll) {
-            int j[kGgdUnroll];
-            float vj[kGgdUnroll];
+        const float *V[KS];
+        float vi[KS], m1[KS], m2[KS];
+        int j1[KS];
 #pragma unroll
-            for (int u = 0; u < kGgdUnroll; ++u) j[u] = col[min(e + u, e1 - 1)];
-#pragma unroll
-            for (int u = 0; u < kGgdUnroll; ++u) vj[u] = V[j[u]];
-#pragma unroll
-            for (int u = 0; u < kGgdUnroll; ++u) {
-                if (e + u < e1) {
-                    if (vj[u] < m1) { m2 = m1; m1 = vj[u]; j1 = j[u]; }
-                    else if (vj[u] < m2) m2 = vj[u];
-                }
-            }
+        for (int q = 0; q < KS; ++q) {
+            // sigmas past the end repeat the last one (loads stay in bounds)
+            V[q] = G.v + (int64_t)min(s0 + q, s_end - 1) * n;
+            vi[q] = V[q][i];
+            m1[q] = m2[q] = FLT_MAX;
+            j1[q] = -1;
         }
-        int parent = i;
-        if (j1 >= 0) {
-            const float tau = kTieTau;
-            bool ambiguous = (m2 - m1 <= tau * m2);
-            const float hi = fmaxf(m1, vi), lo = fminf(m1, vi);
-            if (hi - lo <= tau * hi) ambiguous = true;
-            if (!ambiguous) {
-                parent = (m1 < vi) ? j1 : i;
-            } else {
-                const double vi64 = fp64_v(G, s, i);
-                double bv = DBL_MAX;
-                int best = -1;
-                for (int e = e0; e < e1; ++e) {
-                    const int j = col[e];
-                    const float vj = V[j];
-                    if (vj - m1 <= tau * vj) {
-                        const double d = fp64_v(G, s, j);
-                        if (d < bv) { bv = d; best = j; }
+        // The node's neighbours from the sliced lists (t & 63 is the lane:
+        // jobs start at multiples of 256 nodes), kGgdPad per round: their
+        // indices load together (coalesced across the wavefront), then their
+        // V values, so a round waits for two memory latencies. Slots past
+        // the node's degree read other entries of the same lists or the
+        // padding (valid node ids) and take no part in the minima; the slots
+        // are scanned in CSR order, so the first minimum wins as in a plain
+        // scan.
+        const int deg = G.sell_deg[t];
+        const int32_t *__restrict__ sc = G.sell_col + G.sell_off[t >> 6] + (t & 63);
+        for (int k = 0; k < deg; k += kGgdPad) {
+            int j[kGgdPad];
+            float vj[KS][kGgdPad];
+#pragma unroll
+            for (int u = 0; u < kGgdPad; ++u) j[u] = sc[64 * (k + u)];
+#pragma unroll
+            for (int q = 0; q < KS; ++q)
+#pragma unroll
+                for (int u = 0; u < kGgdPad; ++u) vj[q][u] = V[q][j[u]];
+#pragma unroll
+            for (int u = 0; u < kGgdPad; ++u) {
+                if (k + u < deg) {
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        if (vj[q][u] < m1[q]) { m2[q] = m1[q]; m1[q] = vj[q][u]; j1[q] = j[u]; }
+                        else if (vj[q][u] < m2[q]) m2[q] = vj[q][u];
                     }
                 }
-                if (tie_mode == 0) parent = (bv < vi64) ? best : i;
-                else parent = (bv < vi64 || (bv == vi64 && best < i)) ? best : i;
-                rechecked = true;
             }
         }
-        G.parent[(int64_t)s * n + i] = parent;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const int s = s0 + q;
+            if (s >= s_end) break;
+            int parent = i;
+            if (j1[q] >= 0) {
+                const float tau = kTieTau;
+                bool ambiguous = (m2[q] - m1[q] <= tau * m2[q]);
+                const float hi = fmaxf(m1[q], vi[q]), lo = fminf(m1[q], vi[q]);
+                if (hi - lo <= tau * hi) ambiguous = true;
+                if (!ambiguous) {
+                    parent = (m1[q] < vi[q]) ? j1[q] : i;
+                } else {
+                    parent = fp64_decide(tie_mode, G, s, i, m1[q]);
+                    rechecked[q] = true;
+                }
+            }
+            G.parent[(int64_t)s * n + i] = parent;
+        }
     }
     // one counter update per wavefront
-    const unsigned long long m = __ballot(rechecked);
-    if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1))
-        atomicAdd(G.recheck, (unsigned long long)__popcll(m));
+    unsigned int total = 0;
+#pragma unroll
+    for (int q = 0; q < KS; ++q) total += (unsigned)__popcll(__ballot(rechecked[q]));
+    if (total && __lane_id() == 0) atomicAdd(G.recheck, (unsigned long long)total);
 }
 
 hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob *jobs,
                              int n_jobs, int sigma_base, int n_sig, hipStream_t stream)
 {
     if (n_jobs <= 0 || n_sig <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ggd_parent, dim3(n_jobs, n_sig), dim3(256), 0, stream, tie_mode, graphs,
-                       jobs, sigma_base);
+    const int end = sigma_base + n_sig;
+    if (n_sig >= kGgdSigmas) {
+        hipLaunchKernelGGL(k_ggd_parent<kGgdSigmas>, dim3(n_jobs, (n_sig + kGgdSigmas - 1) / kGgdSigmas),
+                           dim3(256), 0, stream, tie_mode, graphs, jobs, sigma_base, end);
+    } else {
+        hipLaunchKernelGGL(k_ggd_parent<1>, dim3(n_jobs, n_sig), dim3(256), 0, stream, tie_mode,
+                           graphs, jobs, sigma_base, end);
+    }
     return hipGetLastError();
 }
 

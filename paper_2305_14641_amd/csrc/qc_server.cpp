@@ -213,7 +213,7 @@ extern "C" {
 
 int64_t qc_request_footprint(int32_t n, int64_t nnz, int32_t n_sigmas)
 {
-    if (n < 1 || n > kMaxNodes || nnz < 0 || nnz >= ((int64_t)1 << 31) || n_sigmas < 1 ||
+    if (n < 1 || n > kMaxNodes || nnz < 0 || nnz >= kMaxEdges || n_sigmas < 1 ||
         n_sigmas > 1024)
         return -1;
     const int64_t N = n, S = n_sigmas, K = 128;  // histogram bins: the largest row length
@@ -223,6 +223,13 @@ int64_t qc_request_footprint(int32_t n, int64_t nnz, int32_t n_sigmas)
     add(4 * (N + 1));                 // row_ptr
     add(4 * nnz);                     // col
     add(4 * N);                       // descent thread order
+    add(4 * N + 4 * (N / 64 + 2));    // sliced neighbour lists: degrees, slice offsets
+    {
+        // and entries: within a window of degree-sorted nodes the padding
+        // adds up to at most 63 times the window's largest degree
+        const int64_t windows = (N + kOrderWindow - 1) / kOrderWindow;
+        add(4 * (nnz + 63 * std::min<int64_t>(nnz, windows * (N - 1)) + 64 * kGgdPad));
+    }
     add(4 * N);                       // BFS source order
     add(4 * quads);                   // packed edges
     add(8);                           // status
