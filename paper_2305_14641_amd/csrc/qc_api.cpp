@@ -523,7 +523,8 @@ qc_status qc_ggd_labels(qc_graph g, int32_t sigma_index, uint32_t tie_mode, int3
     }
     {
         StageTimer t(QC_STAGE_JUMP, st);
-        QC_HIP(launch_pointer_jump(g->d_desc, g->d_node_jobs, 1, sigma_index, 1, labels_out, 0, st));
+        QC_HIP(launch_pointer_jump(g->d_desc, g->d_node_jobs, 1, sigma_index, 1, labels_out, 0,
+                                   g->n, st));
     }
     return QC_OK;
 }

@@ -178,8 +178,10 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
     }
     {
         StageTimer t(QC_STAGE_JUMP, st);
+        int max_n = 0;
+        for (qc_graph g : b->graphs) max_n = std::max(max_n, (int)g->n);
         QC_HIP(launch_pointer_jump(b->d_descs, b->d_jump_jobs, (int)b->graphs.size(), 0, S,
-                                   labels_out, total, st));
+                                   labels_out, total, max_n, st));
     }
     return QC_OK;
 }

@@ -147,10 +147,12 @@ hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob
                              int n_jobs, int sigma_base, int n_sig, hipStream_t stream);
 
 // Pointer jumping, one workgroup per (graph job, sigma); labels of sigma
-// sigma_base + y go to labels_base + y*labels_ld + job.out_off.
+// sigma_base + y go to labels_base + y*labels_ld + job.out_off. max_n: the
+// largest node count among the jobs' graphs (up to 40,704 the rounds run in
+// LDS).
 hipError_t launch_pointer_jump(const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
                                int sigma_base, int n_sig, int32_t *labels_base,
-                               int64_t labels_ld, hipStream_t stream);
+                               int64_t labels_ld, int max_n, hipStream_t stream);
 
 // Stage timing (qc_timing.cpp): Timer brackets one launch when enabled.
 class StageTimer {

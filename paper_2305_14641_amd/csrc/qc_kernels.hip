@@ -574,13 +574,54 @@ __global__ __launch_bounds__(1024) void k_jump(const GraphDev *__restrict__ grap
     }
 }
 
+// The same rounds on a copy of the parents in LDS (graphs of up to CAP
+// nodes): one coalesced read of the parents, the jumps at LDS latency, one
+// coalesced write of the labels.
+template <int CAP>
+__global__ __launch_bounds__(1024) void k_jump_lds(const GraphDev *__restrict__ graphs,
+                                                   const NodeJob *__restrict__ jobs, int sigma_base,
+                                                   int32_t *labels_base, int64_t labels_ld)
+{
+    __shared__ int32_t lab[CAP];
+    const NodeJob job = jobs[blockIdx.x];
+    const GraphDev &G = graphs[job.g];
+    const int n = G.n;
+    const int s = sigma_base + (int)blockIdx.y;
+    if (s >= G.n_sigmas || n > CAP) return;
+    const int32_t *__restrict__ par = G.parent + (int64_t)s * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = par[i];
+    __syncthreads();
+    for (int round = 0; round < 64; ++round) {
+        int changed = 0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int p = __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int q = __hip_atomic_load(&lab[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (q != p) {
+                __hip_atomic_store(&lab[i], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    int32_t *out = labels_base + (int64_t)blockIdx.y * labels_ld + job.out_off;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = lab[i];
+}
+
 hipError_t launch_pointer_jump(const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
                                int sigma_base, int n_sig, int32_t *labels_base,
-                               int64_t labels_ld, hipStream_t stream)
+                               int64_t labels_ld, int max_n, hipStream_t stream)
 {
     if (n_jobs <= 0 || n_sig <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_jump, dim3(n_jobs, n_sig), dim3(1024), 0, stream, graphs, jobs,
-                       sigma_base, labels_base, labels_ld);
+    const dim3 grid(n_jobs, n_sig), block(1024);
+    if (max_n <= 20480)   // 80 KB of LDS: two workgroups per CU
+        hipLaunchKernelGGL(k_jump_lds<20480>, grid, block, 0, stream, graphs, jobs, sigma_base,
+                           labels_base, labels_ld);
+    else if (max_n <= 40704)
+        hipLaunchKernelGGL(k_jump_lds<40704>, grid, block, 0, stream, graphs, jobs, sigma_base,
+                           labels_base, labels_ld);
+    else
+        hipLaunchKernelGGL(k_jump, grid, block, 0, stream, graphs, jobs, sigma_base, labels_base,
+                           labels_ld);
     return hipGetLastError();
 }
 
