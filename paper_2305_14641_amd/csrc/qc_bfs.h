@@ -14,7 +14,8 @@
 //      them along their CSR rows instead);
 //   B. word-owner update: every thread owns whole 32-bit words of the fields;
 //      the new pairs are nxt & ~seen; it moves them into front and seen and
-//      records the level in the distance bit-planes.
+//      records the level in the distance bit-planes (nxt keeps accumulating:
+//      bits of earlier levels are in seen already).
 //
 // Distances live in registers for the whole search, as P bit-planes of the
 // level (plane p holds bit p of every pair's distance; P = 7 covers every
@@ -288,6 +289,9 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
         }
         __syncthreads();
         // B. move the new bits of owned words into front / seen / planes.
+        //    nxt is not cleared: it accumulates over the levels, and what an
+        //    earlier level delivered is already in seen, so nxt & ~seen is
+        //    still exactly this level's new pairs.
         uint32_t cnt = 0;
         const int tb = opaque(tid);
 #pragma unroll
@@ -297,7 +301,6 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
                 const T raw = nxt[w];
                 const T sw = seen[w];
                 const T y = raw & ~sw;        // newly reached (node, source) pairs
-                nxt[w] = 0;
                 if constexpr (!WIDE) front[w] = y;
                 if (y) seen[w] = sw | y;
                 cnt += (uint32_t)__popcll((unsigned long long)y);
