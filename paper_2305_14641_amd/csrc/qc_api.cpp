@@ -92,7 +92,11 @@ qc_status set_plan(qc_graph g, const BfsPlan &plan)
     if (plan.bw <= 0) return QC_E_INVAL;
     BfsPlan p = plan;
     p.n_batches = (g->n + p.bw - 1) / p.bw;   // sources are the graph's own nodes
-    if (p.bw != g->edges_bw) QC_TRY(order_edges(g, p.bw));
+    // the bank-aware order costs host time per edge that only repeated
+    // searches repay: it is chosen once the largest distance (and so the
+    // final batch width) is known, and never for serving requests, which
+    // search once
+    if (g->dmax >= 0 && !g->bump_base && p.bw != g->edges_bw) QC_TRY(order_edges(g, p.bw));
     if (g->d_bfs_jobs && p.bw == g->plan.bw) {
         g->plan = p;
         return QC_OK;
@@ -426,7 +430,7 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
         (st_ = upload(g->d_sell_col, sell_col)) || (st_ = upload(g->d_sell_off, sell_off)) ||
         (st_ = upload(g->d_sell_deg, sell_deg)) ||
         (weights && ((st_ = upload(g->d_bfs_row_ptr, brp)) || (st_ = upload(g->d_bfs_col, bcol)))) ||
-        (st_ = upload(g->d_node_jobs, njobs)) ||   // set_plan uploads the edges
+        (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
         (st_ = set_plan(g, plan_bfs(n_bfs, -1))))
         return fail(st_);
     if ((st_ = from_hip(launch_fill_u64(g->d_recheck, 1, st))) || (st_ = push_desc(g, st)))

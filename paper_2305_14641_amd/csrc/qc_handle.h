@@ -43,7 +43,7 @@ struct qc_graph_s {
     bool weighted = false;
     uint32_t *d_edges = nullptr;
     std::vector<uint32_t> edges_host; // packed edges, rows ascending (host copy)
-    int edges_bw = 0;                 // batch width d_edges' order was chosen for
+    int edges_bw = 0;                 // batch width d_edges' order was chosen for (0: rows ascending)
 
     // distances and histograms
     int8_t *d_dist_owned = nullptr;   // library-owned matrix (n*n, 16-byte padded)

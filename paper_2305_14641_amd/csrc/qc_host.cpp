@@ -87,61 +87,92 @@ std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
     return edges;
 }
 
+namespace {
+
+// One greedy pass over a window of `nl` groups, lanes visited in `order`;
+// returns the pass's cost (sum over the 8 slots of the busiest bank's count).
+int spread_window(const uint32_t (*in)[8], int nl, const int *order, int nodes_per_word, int banks,
+                  uint32_t (*out)[8])
+{
+    bool used[64][8] = {};
+    int32_t cur[64];
+    for (int l = 0; l < nl; ++l) cur[l] = -1;
+    int cost_total = 0;
+    for (int k = 0; k < 8; ++k) {
+        int occ[64] = {};
+        uint32_t bank_words[64][8];
+        int busiest = 0;
+        for (int li = 0; li < nl; ++li) {
+            const int l = order[li];
+            // an open run (its row has edges left) must be continued
+            bool open = false;
+            for (int j = 0; j < 8; ++j)
+                if (!used[l][j] && (int32_t)(in[l][j] >> 16) == cur[l]) open = true;
+            int best = -1, best_cost = 1 << 30;
+            uint32_t best_word = 0;
+            for (int j = 0; j < 8; ++j) {
+                if (used[l][j]) continue;
+                if (open && (int32_t)(in[l][j] >> 16) != cur[l]) continue;
+                const uint32_t word = (in[l][j] & 0xFFFFu) / (uint32_t)nodes_per_word;
+                const int b = (int)(word % (uint32_t)banks);
+                int cost = occ[b] + 1;
+                for (int q = 0; q < occ[b] && q < 8; ++q)
+                    if (bank_words[b][q] == word) cost = 0;   // same word: broadcast
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best = j;
+                    best_word = word;
+                }
+            }
+            used[l][best] = true;
+            out[l][k] = in[l][best];
+            cur[l] = (int32_t)(in[l][best] >> 16);
+            if (best_cost > 0) {
+                const int b = (int)(best_word % (uint32_t)banks);
+                if (occ[b] < 8) bank_words[b][occ[b]] = best_word;
+                ++occ[b];
+                busiest = std::max(busiest, occ[b]);
+            }
+        }
+        cost_total += busiest;
+    }
+    return cost_total;
+}
+
+}  // namespace
+
 void spread_gather_banks(std::vector<uint32_t> &edges, int64_t nnz, int nodes_per_word,
                          int banks)
 {
     if (banks <= 0 || banks > 64) return;
     const int lanes = banks;
     const int64_t groups = nnz / 8;   // groups made of real edges only
-    uint32_t in[64][8], out[64][8];
-    bool used[64][8];
-    int32_t cur[64];
-    int occ[64];
-    uint32_t bank_words[64][8];
+    uint32_t in[64][8], out[64][8], best_out[64][8];
+    int order[64];
+    uint64_t rng = 0x9E3779B97F4A7C15ull;   // fixed seed: the order is deterministic
     for (int64_t g0 = 0; g0 < groups; g0 += lanes) {
         const int nl = (int)std::min<int64_t>(lanes, groups - g0);
-        for (int l = 0; l < nl; ++l) {
-            for (int j = 0; j < 8; ++j) {
-                in[l][j] = edges[(g0 + l) * 8 + j];
-                used[l][j] = false;
-            }
-            cur[l] = -1;
-        }
-        for (int k = 0; k < 8; ++k) {
-            for (int b = 0; b < banks; ++b) occ[b] = 0;
-            for (int l = 0; l < nl; ++l) {
-                // an open run (its row has edges left) must be continued
-                bool open = false;
-                for (int j = 0; j < 8; ++j)
-                    if (!used[l][j] && (int32_t)(in[l][j] >> 16) == cur[l]) open = true;
-                int best = -1, best_cost = 1 << 30;
-                uint32_t best_word = 0;
-                for (int j = 0; j < 8; ++j) {
-                    if (used[l][j]) continue;
-                    if (open && (int32_t)(in[l][j] >> 16) != cur[l]) continue;
-                    const uint32_t word = (in[l][j] & 0xFFFFu) / (uint32_t)nodes_per_word;
-                    const int b = (int)(word % (uint32_t)banks);
-                    int cost = occ[b] + 1;
-                    for (int q = 0; q < occ[b] && q < 8; ++q)
-                        if (bank_words[b][q] == word) cost = 0;   // same word: broadcast
-                    if (cost < best_cost) {
-                        best_cost = cost;
-                        best = j;
-                        best_word = word;
-                    }
+        for (int l = 0; l < nl; ++l)
+            for (int j = 0; j < 8; ++j) in[l][j] = edges[(g0 + l) * 8 + j];
+        // the greedy in lane order, then in kSpreadTries - 1 shuffled lane
+        // orders; the cheapest result is kept
+        int best_cost = 1 << 30;
+        for (int t = 0; t < kSpreadTries; ++t) {
+            for (int l = 0; l < nl; ++l) order[l] = l;
+            if (t > 0)
+                for (int l = nl - 1; l > 0; --l) {   // Fisher-Yates with a 64-bit LCG
+                    rng = rng * 6364136223846793005ull + 1442695040888963407ull;
+                    std::swap(order[l], order[(int)((rng >> 33) % (uint64_t)(l + 1))]);
                 }
-                used[l][best] = true;
-                out[l][k] = in[l][best];
-                cur[l] = (int32_t)(in[l][best] >> 16);
-                if (best_cost > 0) {
-                    const int b = (int)(best_word % (uint32_t)banks);
-                    if (occ[b] < 8) bank_words[b][occ[b]] = best_word;
-                    ++occ[b];
-                }
+            const int c = spread_window(in, nl, order, nodes_per_word, banks, out);
+            if (c < best_cost) {
+                best_cost = c;
+                for (int l = 0; l < nl; ++l)
+                    for (int j = 0; j < 8; ++j) best_out[l][j] = out[l][j];
             }
         }
         for (int l = 0; l < nl; ++l)
-            for (int j = 0; j < 8; ++j) edges[(g0 + l) * 8 + j] = out[l][j];
+            for (int j = 0; j < 8; ++j) edges[(g0 + l) * 8 + j] = best_out[l][j];
     }
 }
 

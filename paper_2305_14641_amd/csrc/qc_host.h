@@ -31,11 +31,15 @@ std::vector<uint32_t> pack_in_edges(int32_t n, const std::vector<int32_t> &rp,
 // consecutive groups, one group per lane) fall into distinct banks where
 // possible: a greedy choice per slot and lane of the edge whose field word
 // shares its bank with the fewest words already chosen (a word already chosen
-// costs nothing: lanes reading one word are served together). The edges of
+// costs nothing: lanes reading one word are served together), repeated for
+// kSpreadTries lane orders (the first the natural one, the others shuffled by
+// a fixed-seed generator), keeping the order whose slots' busiest banks add
+// up to the least. The edges of
 // one row stay contiguous within a group, so the pull's run merging (one
 // atomic per run) is unchanged; any order of the edges gives the same search.
 // `nodes_per_word` nodes share a field word (32 / batch width, at least 1);
 // 64-bit words (batches of 64) span two 4-byte banks, so pass banks = 16.
+constexpr int kSpreadTries = 8;
 void spread_gather_banks(std::vector<uint32_t> &edges, int64_t nnz, int nodes_per_word,
                          int banks);
 

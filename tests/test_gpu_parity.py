@@ -34,11 +34,12 @@ def rel_err(got, want):
     return float(err.max()) if err.size else 0.0
 
 
-def run_gpu(torch, g, sigmas, ties=(0, 1), precision=0, want_dist=True):
+def run_gpu(torch, g, sigmas, ties=(0, 1), precision=0, want_dist=True, repeat=1):
     from paper_2305_14641_amd import qc
     G = qc.Graph.from_graph(g)
     dist = torch.empty((g.n, g.n), dtype=torch.int8, device="cuda") if want_dist else None
-    dmax = G.distances(dist)
+    for _ in range(repeat):   # later runs: the final batch width and edge order
+        dmax = G.distances(dist)
     hist = G.histograms()
     psi, v = G.potential(sigmas, precision=precision)
     labels = {}
@@ -253,10 +254,10 @@ def test_search_order_changes_nothing(torch_cuda, monkeypatch, g, env):
     count must give the same bytes everywhere."""
     torch = torch_cuda
     print(f"[gpu] search order {g.name} n={g.n} {env}", flush=True)
-    a = run_gpu(torch, g, [0.7, 2.0])
+    a = run_gpu(torch, g, [0.7, 2.0], repeat=2)
     for k, val in env.items():
         monkeypatch.setenv(k, val)
-    b = run_gpu(torch, g, [0.7, 2.0])
+    b = run_gpu(torch, g, [0.7, 2.0], repeat=2)
     np.testing.assert_array_equal(a["dist"], b["dist"])
     assert a["dmax"] == b["dmax"]
     np.testing.assert_array_equal(a["hist"], b["hist"])
