@@ -397,10 +397,11 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
             sell_col[(size_t)sell_off[w] + 64 * k + lane] = col[rp[i] + k];
     }
     // BFS sources by estimated eccentricity (undirected graphs; a directed
-    // graph keeps its node order). QC_SOURCE_ORDER=identity keeps the node
-    // order for every graph (a switch for measurements and tests).
+    // graph keeps its node order, and so does a serving request: its one
+    // search would not repay the host sweeps). QC_SOURCE_ORDER=identity keeps
+    // the node order for every graph (a switch for measurements and tests).
     const char *so = getenv("QC_SOURCE_ORDER");
-    if (!directed && !(so && strcmp(so, "identity") == 0)) {
+    if (!directed && !region && !(so && strcmp(so, "identity") == 0)) {
         g->src_order = weights ? source_order(n_bfs, brp, bcol, n, kSourceSweeps)
                                : source_order(n, rp, col, n, kSourceSweeps);
     } else {
