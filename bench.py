@@ -312,6 +312,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the planner's BFS launch shapes (no timing at set-up)")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the fully connected (dense float distance) leg")
     ap.add_argument("--dense-n", type=int, default=20000)
@@ -355,7 +357,15 @@ def main():
     log(f"generated {len(graphs)} graphs in {time.perf_counter() - t0:.1f}s")
 
     handles = [qc.Graph.from_graph(g) for g in graphs]
-    batch = qc.Batch(handles, sigmas, tie_mode=qc.TIE_STRICT, hipgraph=True)
+    for G in handles:
+        G.distances()       # learns dmax: the planner's final choice
+    planned = [G.bfs_plan() for G in handles]
+    t0 = time.perf_counter()
+    batch = qc.Batch(handles, sigmas, tie_mode=qc.TIE_STRICT, hipgraph=True,
+                     autotune=not args.no_autotune)
+    tuned = [G.bfs_plan() for G in handles]
+    log(f"batch set-up {time.perf_counter() - t0:.2f}s; autotuner changed the BFS plan of "
+        f"{sum(a != b for a, b in zip(planned, tuned))} of {len(handles)} graphs")
     psi, v, lab = batch.outputs()
     pair_terms = float(sum(float(g.n) ** 2 for g in graphs)) * S
     log(f"planned batch: total nodes {batch.total}, pair-terms/step {pair_terms:.3e}")

@@ -130,6 +130,14 @@ qc_status qc_graph_create_weighted(int32_t n, int64_t nnz, const int32_t *row_pt
 /* Release a handle and all device memory it owns (waits for its work). */
 qc_status qc_graph_destroy(qc_graph g);
 
+/* The handle's current multi-source BFS launch plan (Algorithm 1's distances
+ * are computed in batches of `batch` sources): batch width, 32-bit words per
+ * thread and bit-field, distance bit-planes, workgroup shape (0: three
+ * fields x 1024 threads, 1: two fields x 512 threads, 2: two fields x 1024
+ * threads). Any output pointer may be NULL. Host only. */
+qc_status qc_graph_bfs_plan(qc_graph g, int32_t *batch, int32_t *words, int32_t *planes,
+                            int32_t *shape);
+
 /* Sizes of a handle: any output pointer may be NULL. dmax is -1 until the
  * first qc_distances / qc_potential has run. n_components counts connected
  * components (weakly connected ones for a directed graph). */

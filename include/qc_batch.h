@@ -20,7 +20,8 @@ typedef struct qc_batch_s *qc_batch;
 
 enum {
     QC_BATCH_HIPGRAPH = 1u, /* capture the launch sequence once, replay it afterwards */
-    QC_BATCH_FP32C = 2u     /* potentials in compensated FP32 instead of FP64 accumulation */
+    QC_BATCH_FP32C = 2u,    /* potentials in compensated FP32 instead of FP64 accumulation */
+    QC_BATCH_AUTOTUNE = 4u  /* time the candidate BFS launch shapes of every graph, keep the fastest */
 };
 
 /*
@@ -35,7 +36,11 @@ enum {
  *   sigmas     host, double[n_sigmas], each finite and > 0 (1..1024 values),
  *              shared by every graph
  *   tie_mode   QC_TIE_STRICT or QC_TIE_MERGE
- *   flags      any of QC_BATCH_HIPGRAPH, QC_BATCH_FP32C
+ *   flags      any of QC_BATCH_HIPGRAPH, QC_BATCH_FP32C, QC_BATCH_AUTOTUNE
+ *              (AUTOTUNE: at set-up every graph's search runs once per
+ *              candidate launch shape, timed with events on `stream`; the
+ *              fastest becomes the graph's plan, for this batch and for the
+ *              graph's own later calls. The outputs do not depend on it.)
  *   stream     stream for any set-up work (graphs whose largest distance is
  *              not yet known run their distances once here, synchronously)
  *   out        host, receives the batch handle

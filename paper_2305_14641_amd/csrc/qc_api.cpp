@@ -87,7 +87,14 @@ static qc_status order_edges(qc_graph g, int bw)
     return QC_OK;
 }
 
-qc_status set_plan(qc_graph g, const BfsPlan &plan)
+qc_status plain_edges(qc_graph g)
+{
+    QC_TRY(upload(g->d_edges, g->edges_host));
+    g->edges_bw = 0;
+    return QC_OK;
+}
+
+qc_status set_plan(qc_graph g, const BfsPlan &plan, bool reorder)
 {
     if (plan.bw <= 0) return QC_E_INVAL;
     BfsPlan p = plan;
@@ -96,7 +103,7 @@ qc_status set_plan(qc_graph g, const BfsPlan &plan)
     // searches repay: it is chosen once the largest distance (and so the
     // final batch width) is known, and never for serving requests, which
     // search once
-    if (g->dmax >= 0 && !g->bump_base && p.bw != g->edges_bw) QC_TRY(order_edges(g, p.bw));
+    if (reorder && g->dmax >= 0 && !g->bump_base && p.bw != g->edges_bw) QC_TRY(order_edges(g, p.bw));
     if (g->d_bfs_jobs && p.bw == g->plan.bw) {
         g->plan = p;
         return QC_OK;
@@ -448,6 +455,17 @@ qc_status qc_graph_destroy(qc_graph g)
 {
     if (!g) return QC_E_INVAL;
     destroy(g);
+    return QC_OK;
+}
+
+qc_status qc_graph_bfs_plan(qc_graph g, int32_t *batch, int32_t *words, int32_t *planes,
+                            int32_t *shape)
+{
+    if (!g) return QC_E_INVAL;
+    if (batch) *batch = g->plan.bw;
+    if (words) *words = g->plan.nw;
+    if (planes) *planes = g->plan.planes;
+    if (shape) *shape = g->plan.shape;
     return QC_OK;
 }
 

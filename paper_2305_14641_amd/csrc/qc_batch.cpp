@@ -154,6 +154,65 @@ std::vector<NodeJob> xcd_pinned_node_jobs(const std::vector<qc_graph> &graphs)
     return out;
 }
 
+// The autotuner: g's search under each candidate plan, the planner's choice
+// for each workgroup shape and the same shape with half the batch width,
+// one untimed and kTuneReps timed runs each (HIP events on st), all in the
+// plain edge order so that no candidate starts with an order chosen for it;
+// the fastest becomes g's plan and gets its edge order.
+constexpr int kTuneReps = 2;
+
+qc_status autotune_bfs(qc_graph g, hipStream_t st)
+{
+    std::vector<BfsPlan> cands;
+    auto add = [&](const BfsPlan &p) {
+        if (p.bw <= 0) return;
+        for (const BfsPlan &c : cands)
+            if (c.bw == p.bw && c.nw == p.nw && c.planes == p.planes && c.shape == p.shape) return;
+        cands.push_back(p);
+    };
+    add(g->plan);
+    for (int shape : {kBfsNarrow, kBfsWide1024, kBfsWide}) {
+        const BfsPlan p = plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape);
+        add(p);
+        if (p.bw > 4) add(plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape, p.bw / 2));
+    }
+    if (cands.size() < 2) return QC_OK;
+    hipEvent_t e0, e1;
+    QC_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return QC_E_DEVICE;
+    }
+    qc_status s = plain_edges(g);
+    BfsPlan best = g->plan;
+    float best_ms = 1e30f;
+    for (size_t c = 0; c < cands.size() && s == QC_OK; ++c) {
+        if ((s = set_plan(g, cands[c], false))) break;
+        const BfsPlan &p = g->plan;
+        const int shape = p.shape | (g->weighted ? kBfsWeighted : 0);
+        float total = 0.0f;
+        for (int rep = 0; rep <= kTuneReps && s == QC_OK; ++rep) {
+            hipError_t e = launch_fill_i32(g->d_status, 2, 0, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = launch_bfs(p.bw, p.nw, p.planes, shape, g->d_desc, g->d_bfs_jobs, p.n_batches, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) s = from_hip(e);
+            if (rep > 0) total += ms;
+        }
+        if (s == QC_OK && total < best_ms) {
+            best_ms = total;
+            best = p;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    QC_TRY(s);
+    return set_plan(g, best, true);
+}
+
 qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st)
 {
     const int S = (int)b->sigmas.size();
@@ -196,7 +255,7 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
 {
     if (!graphs || !out || n_graphs < 1 || n_graphs > 65536) return QC_E_INVAL;
     if (tie_mode > QC_TIE_MERGE) return QC_E_INVAL;
-    if (flags & ~(uint32_t)(QC_BATCH_HIPGRAPH | QC_BATCH_FP32C)) return QC_E_INVAL;
+    if (flags & ~(uint32_t)(QC_BATCH_HIPGRAPH | QC_BATCH_FP32C | QC_BATCH_AUTOTUNE)) return QC_E_INVAL;
     QC_TRY(validate_sigmas(sigmas, n_sigmas));
     std::set<qc_graph> seen;
     for (int i = 0; i < n_graphs; ++i) {
@@ -232,6 +291,12 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         b->offsets[i + 1] = b->offsets[i] + g->n;
     }
     if (hipStreamSynchronize(st) != hipSuccess) return fail(QC_E_DEVICE);
+    if (flags & QC_BATCH_AUTOTUNE) {
+        for (int i = 0; i < n_graphs; ++i) {
+            qc_status s = autotune_bfs(graphs[i], st);
+            if (s) return fail(s);
+        }
+    }
 
     qc_status s;
     if ((s = dalloc(&b->d_recheck, 1)) || (s = dalloc(&b->d_descs, (size_t)n_graphs))) return fail(s);

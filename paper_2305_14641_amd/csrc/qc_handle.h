@@ -185,7 +185,11 @@ inline hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 qc_status check_device(int *dev_out);
 qc_status push_desc(qc_graph g, hipStream_t st);
 qc_status ensure_hist_jobs(qc_graph g);
-qc_status set_plan(qc_graph g, const BfsPlan &p);
+// Make p g's BFS plan (job list); `reorder`: also put the edges into the
+// bank-aware order for p's batch width (when the graph qualifies).
+qc_status set_plan(qc_graph g, const BfsPlan &p, bool reorder = true);
+// Put the graph's edges back into rows-ascending order.
+qc_status plain_edges(qc_graph g);
 // Reachable (source, node) pairs of the batch of sources at positions
 // s0..s0+bw-1 of the source order.
 uint32_t batch_target(qc_graph g, int s0, int bw);

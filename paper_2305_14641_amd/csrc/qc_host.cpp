@@ -333,7 +333,7 @@ int planes_for(int32_t dmax)
     return 7;
 }
 
-BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape)
+BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw)
 {
     static const int kNarrow[] = {1, 2, 4, 6, 8, 10, 12};
     static const int kWide[] = {16, 24, 32, 38, 39};
@@ -364,7 +364,7 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape)
         nopts = 4;
     }
     for (int bw : {64, 32, 16, 8, 4}) {
-        if (two && bw < 8) continue;
+        if (bw > max_bw || (two && bw < 8)) continue;
         const int64_t words = ((int64_t)n * bw + 31) / 32;  // 32-bit words of one bit field
         const int64_t need = (words + threads - 1) / threads;
         for (int k = 0; k < nopts; ++k) {

@@ -83,7 +83,7 @@ qc_status subdivide_weighted(int32_t n, const std::vector<int32_t> &rp,
 struct BfsPlan { int bw; int nw; int planes; int n_batches; int shape; };
 BfsPlan plan_bfs(int32_t n, int32_t dmax);
 // The plan of one shape alone (bw = 0 when n does not fit).
-BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape);
+BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw = 64);
 int planes_for(int32_t dmax);
 
 // Histogram row length for a largest finite distance dmax.

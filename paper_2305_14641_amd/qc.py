@@ -38,7 +38,7 @@ GRAPH_DIRECTED = 2
 EXPORTED = [
     "qc_status_str", "qc_device_count", "qc_graph_create", "qc_graph_create_weighted",
     "qc_graph_destroy",
-    "qc_graph_info", "qc_distances", "qc_get_histograms", "qc_potential",
+    "qc_graph_info", "qc_graph_bfs_plan", "qc_distances", "qc_get_histograms", "qc_potential",
     "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync", "qc_timing_enable",
     "qc_timing_read", "qc_potential_dense",
     "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
@@ -47,6 +47,7 @@ EXPORTED = [
 
 BATCH_HIPGRAPH = 1
 BATCH_FP32C = 2
+BATCH_AUTOTUNE = 4
 
 EXPORTED += ["qc_request_footprint", "qc_server_create", "qc_server_submit", "qc_server_poll",
              "qc_server_wait", "qc_server_stats", "qc_server_destroy"]
@@ -102,6 +103,7 @@ def lib():
         L.qc_graph_create_weighted.argtypes = [I32, I64, P, P, P, U32, P, P]
         L.qc_graph_destroy.argtypes = [P]
         L.qc_graph_info.argtypes = [P, P, P, P, P]
+        L.qc_graph_bfs_plan.argtypes = [P, P, P, P, P]
         L.qc_distances.argtypes = [P, P, P, P]
         L.qc_get_histograms.argtypes = [P, P, P, P]
         L.qc_potential.argtypes = [P, P, I32, P, P, U32, P]
@@ -231,6 +233,12 @@ class Graph:
                                    ctypes.byref(dmax), ctypes.byref(comps)), "qc_graph_info")
         return dict(n=n.value, nnz=nnz.value, dmax=dmax.value, n_components=comps.value)
 
+    def bfs_plan(self) -> tuple:
+        """(batch width, words per thread, planes, workgroup shape) of the BFS."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().qc_graph_bfs_plan(self._h, *[ctypes.byref(x) for x in v]), "qc_graph_bfs_plan")
+        return tuple(x.value for x in v)
+
     def distances(self, out=None, stream=None):
         """Hop-distance matrix (int8 [n, n], -1 = unreachable) into `out`
         (a CUDA int8 tensor) or kept resident when out is None. Returns dmax."""
@@ -297,11 +305,12 @@ class Batch:
     """Many graphs x one sigma list in grouped launches (include/qc_batch.h)."""
 
     def __init__(self, graphs, sigmas, tie_mode=TIE_STRICT, hipgraph=True, fp32c=False,
-                 stream=None):
+                 autotune=False, stream=None):
         self.graphs = list(graphs)          # keeps the Graph handles alive
         arr = (ctypes.c_void_p * len(self.graphs))(*[G.handle.value for G in self.graphs])
         sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).reshape(-1))
-        flags = (BATCH_HIPGRAPH if hipgraph else 0) | (BATCH_FP32C if fp32c else 0)
+        flags = ((BATCH_HIPGRAPH if hipgraph else 0) | (BATCH_FP32C if fp32c else 0)
+                 | (BATCH_AUTOTUNE if autotune else 0))
         h = ctypes.c_void_p()
         _check(lib().qc_batch_create(arr, len(self.graphs), sig.ctypes.data_as(ctypes.c_void_p),
                                      sig.shape[0], int(tie_mode), flags, _stream_ptr(stream),

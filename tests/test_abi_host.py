@@ -98,6 +98,7 @@ def test_null_pointers_rejected():
                      ("qc_potential", [None, None, 1, None, None, 0, None]),
                      ("qc_ggd_labels", [None, 0, 0, None, None]),
                      ("qc_graph_info", [None, None, None, None, None]),
+                     ("qc_graph_bfs_plan", [None, None, None, None, None]),
                      ("qc_graph_sync", [None, None]),
                      ("qc_last_recheck_count", [None, None]),
                      ("qc_get_histograms", [None, None, None, None])]:

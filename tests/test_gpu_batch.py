@@ -78,6 +78,31 @@ def test_batch_without_hipgraph_and_fp32c(setup):
     np.testing.assert_array_equal(o2[2].cpu().numpy(), o1[2].cpu().numpy())
 
 
+def test_batch_autotune_changes_no_output(setup):
+    """QC_BATCH_AUTOTUNE times the candidate BFS launch shapes of each graph
+    and keeps the fastest; the outputs are bitwise those of the planner's
+    shapes."""
+    torch, qc, graphs, sigmas = setup
+    ha = [qc.Graph.from_graph(g) for g in graphs]
+    hb = [qc.Graph.from_graph(g) for g in graphs]
+    ba = qc.Batch(ha, sigmas, hipgraph=True, autotune=True)
+    bb = qc.Batch(hb, sigmas, hipgraph=True)
+    oa, ob = ba.outputs(), bb.outputs()
+    for _ in range(2):
+        ba.run(*oa)
+        bb.run(*ob)
+    torch.cuda.synchronize()
+    for x, y in zip(oa, ob):
+        assert x.cpu().numpy().tobytes() == y.cpu().numpy().tobytes()
+    # the tuned plan stays with the graph: its own calls agree too
+    d = torch.empty((graphs[3].n, graphs[3].n), dtype=torch.int8, device="cuda")
+    ha[3].distances(d)
+    dist, _ = oracle.distances(graphs[3].n, graphs[3].row_ptr, graphs[3].col)
+    np.testing.assert_array_equal(d.cpu().numpy(), dist)
+    ba.close()
+    bb.close()
+
+
 def test_batch_rejects_bad_arguments(setup):
     torch, qc, graphs, sigmas = setup
     G = qc.Graph.from_graph(graphs[-1])
