@@ -413,7 +413,9 @@ def main():
     bytes_step = sum(bfs_bytes(g) for g in graphs)
     achieved = (bytes_step / bfs_launches) / (stages["bfs"]["avg_launch_ms"] * 1e-3) / 1e9
     hist_bytes = sum(float(g.n) * g.n + 4.0 * g.n * 32 for g in graphs)
-    hist_gbs = hist_bytes / (stages["hist"]["ms_per_step"] * 1e-3) / 1e9
+    # (zero when every graph's search makes its histograms itself)
+    hist_ms = stages["hist"]["ms_per_step"]
+    hist_gbs = hist_bytes / (hist_ms * 1e-3) / 1e9 if hist_ms > 0 else None
     log(f"stages: " + ", ".join(f"{k}={v_['ms_per_step']:.3f}ms" for k, v_ in stages.items()))
 
     # -- plain per-graph path (one graph at a time, synchronous); its first
