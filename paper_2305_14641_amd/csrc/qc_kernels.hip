@@ -189,6 +189,8 @@ __device__ __forceinline__ double canonical_ratio(double s1, double s2, double i
     return inv_a * (s1 / s2);
 }
 
+constexpr int kPotSigmas = 4;
+
 template <int K, int PREC>
 __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ graphs,
                                                    const NodeJob *__restrict__ jobs,
@@ -206,7 +208,47 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
 #pragma unroll
     for (int k = 0; k < K; ++k) h[k] = (k < kmax) ? hrow[k] : 0;
 
-    for (int s = 0; s < G.n_sigmas; ++s) {
+    int s = 0;
+    if constexpr (PREC == 0 && K <= 32) {
+        // kPotSigmas sigmas at a time: their sums are independent chains
+        // (each in the canonical order), so the FP64 adds of one sigma wait
+        // on their predecessors while the others' issue (rows of 64 or 128
+        // bins would need more registers than there are)
+        for (; s + kPotSigmas <= G.n_sigmas; s += kPotSigmas) {
+            double a2[kPotSigmas], a1[kPotSigmas];
+#pragma unroll
+            for (int q = 0; q < kPotSigmas; ++q) a2[q] = a1[q] = 0.0;
+            {
+#pragma clang fp contract(off)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (k < kmax) {
+                        const double hk = (double)h[k];
+                        const double kk = (double)(k * k) * hk;
+#pragma unroll
+                        for (int q = 0; q < kPotSigmas; ++q) {
+                            const double wk = G.w64[(int64_t)(s + q) * G.K + k];
+                            a2[q] = a2[q] + hk * wk;
+                            a1[q] = a1[q] + kk * wk;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kPotSigmas; ++q) {
+                const int64_t o = (int64_t)(s + q) * n + i;
+                const double v64 = canonical_ratio(a1[q], a2[q], G.inv_a[s + q]);
+                const float psi32 = (float)a2[q], v32 = (float)v64;
+                G.v64[o] = v64;
+                G.v[o] = v32;
+                const int64_t ou = job.out_off + (int64_t)(s + q) * out_ld + i;
+                if (psi_out) psi_out[ou] = psi32;
+                else G.psi[o] = psi32;   // resident only when the caller takes none
+                if (v_out) v_out[ou] = v32;
+            }
+        }
+    }
+    for (; s < G.n_sigmas; ++s) {
         float psi32, v32;
         const int64_t o = (int64_t)s * n + i;
         if constexpr (PREC == 0) {
@@ -244,10 +286,10 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
             psi32 = p;
             v32 = __fdiv_rn(q, p);
         }
-        G.psi[o] = psi32;
         G.v[o] = v32;
         const int64_t ou = job.out_off + (int64_t)s * out_ld + i;
         if (psi_out) psi_out[ou] = psi32;
+        else G.psi[o] = psi32;   // resident only when the caller takes none
         if (v_out) v_out[ou] = v32;
     }
 }
