@@ -194,7 +194,7 @@ qc_status ensure_sigma_buffers(qc_graph g, int S)
         gfree(g, g->d_v64);
         gfree(g, g->d_parent);
         QC_TRY(galloc(g, &g->d_psi, (size_t)S * g->n));
-        QC_TRY(galloc(g, &g->d_v, (size_t)S * g->n));
+        QC_TRY(galloc(g, &g->d_v, (size_t)v_floats(g->n, S)));
         QC_TRY(galloc(g, &g->d_v64, (size_t)S * g->n));
         QC_TRY(galloc(g, &g->d_parent, (size_t)S * g->n));
         g->pot_cap = S;

@@ -69,7 +69,7 @@ struct GraphDev {
     int8_t *dist;             // [n*n] row-major
     int32_t *hist;            // [n*K]
     float *psi;               // [n_sigmas*n] resident
-    float *v;                 // [n_sigmas*n] resident
+    float *v;                 // resident, sigma groups of kVGroup interleaved by node (v_index)
     double *v64;              // [n_sigmas*n] canonical FP64 V, or null (FP32C potentials)
     const double *w64;        // [n_sigmas*K] exp(-k^2/a), host C library exp
     const double *u64;        // [n_sigmas*K] k^2 * w / a
@@ -101,6 +101,20 @@ constexpr int kOrderWindow = QC_ORDER_WINDOW;
 // Neighbours one descent thread loads per round (the sliced neighbour lists
 // carry this many padding rows after the last slice).
 constexpr int kGgdPad = 4;
+// The resident FP32 V keeps the sigmas in groups of kVGroup, interleaved by
+// node: entry (s, i) at v_index(n, s, i), so the descent, which decides a
+// node for a group of sigmas, gathers a neighbour's values with one 16-byte
+// load. Allocations round the sigma count up to a whole group.
+constexpr int kVGroup = 4;
+__host__ __device__ inline int64_t v_index(int n, int s, int i)
+{
+    return ((int64_t)(s / kVGroup) * n + i) * kVGroup + (s % kVGroup);
+}
+inline int64_t v_floats(int n, int n_sigmas)
+{
+    return (int64_t)((n_sigmas + kVGroup - 1) / kVGroup) * kVGroup * n;
+}
+
 // Sigmas one descent thread decides (when the launch covers that many).
 #ifndef QC_GGD_SIGMAS
 #define QC_GGD_SIGMAS 4

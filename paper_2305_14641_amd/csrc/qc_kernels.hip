@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
                 const double v64 = canonical_ratio(a1[q], a2[q], G.inv_a[s + q]);
                 const float psi32 = (float)a2[q], v32 = (float)v64;
                 G.v64[o] = v64;
-                G.v[o] = v32;
+                G.v[v_index(n, s + q, i)] = v32;
                 const int64_t ou = job.out_off + (int64_t)(s + q) * out_ld + i;
                 if (psi_out) psi_out[ou] = psi32;
                 else G.psi[o] = psi32;   // resident only when the caller takes none
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
             psi32 = p;
             v32 = __fdiv_rn(q, p);
         }
-        G.v[o] = v32;
+        G.v[v_index(n, s, i)] = v32;
         const int64_t ou = job.out_off + (int64_t)s * out_ld + i;
         if (psi_out) psi_out[ou] = psi32;
         else G.psi[o] = psi32;   // resident only when the caller takes none
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_potential_bf16(const GraphDev *__restri
                     const float v = num / psi;
                     const int64_t o = (int64_t)s * n + node;
                     G.psi[o] = psi;
-                    G.v[o] = v;
+                    G.v[v_index(n, s, node)] = v;
                     const int64_t ou = job.out_off + (int64_t)s * out_ld + node;
                     if (psi_out) psi_out[ou] = psi;
                     if (v_out) v_out[ou] = v;
@@ -451,7 +451,7 @@ __device__ __forceinline__ double fp64_v(const GraphDev &G, int s, int node)
 // compared with the node's own.
 __device__ __noinline__ int fp64_decide(int tie_mode, const GraphDev &G, int s, int i, float m1)
 {
-    const float *__restrict__ V = G.v + (int64_t)s * G.n;
+    const float *__restrict__ V = G.v;
     const int32_t *__restrict__ col = G.col;
     const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
     const double vi64 = fp64_v(G, s, i);
@@ -459,7 +459,7 @@ __device__ __noinline__ int fp64_decide(int tie_mode, const GraphDev &G, int s, 
     int best = -1;
     for (int e = e0; e < e1; ++e) {
         const int j = col[e];
-        const float vj = V[j];
+        const float vj = V[v_index(G.n, s, j)];
         if (vj - m1 <= kTieTau * vj) {
             const double d = fp64_v(G, s, j);
             if (d < bv) {
@@ -482,8 +482,8 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
                                                     int sigma_end)
 {
     // blockIdx.y selects the sigmas: the blocks in flight share them, so the
-    // gathered V values (one FP32 plane per sigma, a few MB for a whole
-    // batch) stay in L2 while the neighbour lists stream past.
+    // gathered V values (one interleaved group of sigmas, a few MB for a
+    // whole batch) stay in L2 while the neighbour lists stream past.
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
@@ -497,14 +497,26 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
         // within the job, threads take its nodes by decreasing degree, so the
         // neighbour loops of one wavefront have similar trip counts
         const int i = G.order[t];
-        const float *V[KS];
         float vi[KS], m1[KS], m2[KS];
         int j1[KS];
+        // V of node j for this thread's sigmas: with a whole, aligned group
+        // of kVGroup sigmas one 16-byte load (the values of sigmas past the
+        // end are padding and are never used), else one load per sigma
+        auto load_v = [&](int j, float (&out)[KS]) {
+            if constexpr (KS == kVGroup) {
+                const float4 x = *(const float4 *)(G.v + v_index(n, s0, j));
+                out[0] = x.x;
+                out[1] = x.y;
+                out[2] = x.z;
+                out[3] = x.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < KS; ++q) out[q] = G.v[v_index(n, min(s0 + q, s_end - 1), j)];
+            }
+        };
+        load_v(i, vi);
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
-            // sigmas past the end repeat the last one (loads stay in bounds)
-            V[q] = G.v + (int64_t)min(s0 + q, s_end - 1) * n;
-            vi[q] = V[q][i];
             m1[q] = m2[q] = FLT_MAX;
             j1[q] = -1;
         }
@@ -520,20 +532,18 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
         const int32_t *__restrict__ sc = G.sell_col + G.sell_off[t >> 6] + (t & 63);
         for (int k = 0; k < deg; k += kGgdPad) {
             int j[kGgdPad];
-            float vj[KS][kGgdPad];
+            float vj[kGgdPad][KS];
 #pragma unroll
             for (int u = 0; u < kGgdPad; ++u) j[u] = sc[64 * (k + u)];
 #pragma unroll
-            for (int q = 0; q < KS; ++q)
-#pragma unroll
-                for (int u = 0; u < kGgdPad; ++u) vj[q][u] = V[q][j[u]];
+            for (int u = 0; u < kGgdPad; ++u) load_v(j[u], vj[u]);
 #pragma unroll
             for (int u = 0; u < kGgdPad; ++u) {
                 if (k + u < deg) {
 #pragma unroll
                     for (int q = 0; q < KS; ++q) {
-                        if (vj[q][u] < m1[q]) { m2[q] = m1[q]; m1[q] = vj[q][u]; j1[q] = j[u]; }
-                        else if (vj[q][u] < m2[q]) m2[q] = vj[q][u];
+                        if (vj[u][q] < m1[q]) { m2[q] = m1[q]; m1[q] = vj[u][q]; j1[q] = j[u]; }
+                        else if (vj[u][q] < m2[q]) m2[q] = vj[u][q];
                     }
                 }
             }
@@ -570,7 +580,8 @@ hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob
 {
     if (n_jobs <= 0 || n_sig <= 0) return hipSuccess;
     const int end = sigma_base + n_sig;
-    if (n_sig >= kGgdSigmas) {
+    static_assert(kGgdSigmas == kVGroup || kGgdSigmas == 1, "the descent's sigma groups are V's");
+    if (n_sig >= kGgdSigmas && sigma_base % kVGroup == 0) {
         hipLaunchKernelGGL(k_ggd_parent<kGgdSigmas>, dim3(n_jobs, (n_sig + kGgdSigmas - 1) / kGgdSigmas),
                            dim3(256), 0, stream, tie_mode, graphs, jobs, sigma_base, end);
     } else {

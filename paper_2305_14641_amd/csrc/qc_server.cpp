@@ -136,7 +136,9 @@ qc_status run_request(qc_server s, Request *r, int slot, void **stage, size_t *s
         QC_TRY(qc_ggd_labels(g, k, s->opts.tie_mode, d_labels + (size_t)k * n, stream));
     const size_t lab_bytes = (size_t)S * n * sizeof(int32_t);
     const size_t pot_bytes = s->opts.want_potentials ? (size_t)S * n * sizeof(float) : 0;
-    const size_t need = lab_bytes + 2 * pot_bytes;
+    // the resident V keeps its sigmas interleaved in groups (v_index)
+    const size_t v_bytes = s->opts.want_potentials ? (size_t)v_floats(n, S) * sizeof(float) : 0;
+    const size_t need = lab_bytes + pot_bytes + v_bytes;
     if (*stage_bytes < need) {
         if (*stage) (void)hipHostFree(*stage);
         *stage = nullptr;
@@ -148,13 +150,16 @@ qc_status run_request(qc_server s, Request *r, int slot, void **stage, size_t *s
     QC_HIP(hipMemcpyAsync(h, d_labels, lab_bytes, hipMemcpyDeviceToHost, st));
     if (pot_bytes) {
         QC_HIP(hipMemcpyAsync(h + lab_bytes, g->d_psi, pot_bytes, hipMemcpyDeviceToHost, st));
-        QC_HIP(hipMemcpyAsync(h + lab_bytes + pot_bytes, g->d_v, pot_bytes, hipMemcpyDeviceToHost, st));
+        QC_HIP(hipMemcpyAsync(h + lab_bytes + pot_bytes, g->d_v, v_bytes, hipMemcpyDeviceToHost, st));
     }
     QC_HIP(hipStreamSynchronize(st));
     r->labels.assign((int32_t *)h, (int32_t *)(h + lab_bytes));
     if (pot_bytes) {
         r->psi.assign((float *)(h + lab_bytes), (float *)(h + lab_bytes + pot_bytes));
-        r->v.assign((float *)(h + lab_bytes + pot_bytes), (float *)(h + lab_bytes + 2 * pot_bytes));
+        const float *hv = (const float *)(h + lab_bytes + pot_bytes);
+        r->v.resize((size_t)S * n);
+        for (int k = 0; k < S; ++k)
+            for (int32_t i = 0; i < n; ++i) r->v[(size_t)k * n + i] = hv[v_index(n, k, i)];
     }
     return QC_OK;
 }
@@ -242,7 +247,7 @@ int64_t qc_request_footprint(int32_t n, int64_t nnz, int32_t n_sigmas)
     add(4 * N * K);                   // histograms
     add(16 * N);                      // histogram jobs
     add(4 * N * S);                   // psi
-    add(4 * N * S);                   // V
+    add(4 * v_floats(n, n_sigmas));   // V (sigma groups rounded up)
     add(8 * N * S);                   // FP64 V
     add(4 * N * S);                   // parents
     add(8 * S * K);                   // w64
