@@ -60,19 +60,16 @@ def profiled_bfs():
     return prof.get("k_bfs_tuned")
 
 
-def profiled_traffic():
+def profiled_traffic(launches_per_step):
     """HBM bytes per k_bfs launch measured by rocprofv3 FETCH_SIZE / WRITE_SIZE
     (scaled by a copy-kernel calibration) for the kernel sources as they are
-    now; None when no such profile exists or a kernel source changed since."""
-    import hashlib
-    if not os.path.exists(PROFILE):
+    now: the profiled batched step's BFS bytes over this run's BFS launches per
+    step (the autotuner's grouping can differ between runs); None when no such
+    profile exists or a kernel source changed since."""
+    prof = profiled_bfs()
+    if not prof or not prof.get("hbm_bytes_per_step"):
         return None
-    prof = json.load(open(PROFILE))
-    for rel, digest in prof.get("kernel_sources_sha256", {}).items():
-        path = os.path.join(ROOT, rel)
-        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
-            return None
-    return prof["k_bfs_tuned"]["hbm_bytes_per_launch"]
+    return prof["hbm_bytes_per_step"] / launches_per_step
 
 
 def cpu_baseline(graphs, sigmas, budget_s: float) -> dict:
@@ -231,13 +228,13 @@ def bfs_alu(stages):
     wavefront instructions x 64 lanes, from the committed counter summary)
     against the issue rate of 256 CUs x 64 lanes x 2.4 GHz."""
     prof = profiled_bfs()
-    if not prof or not prof.get("valu_wave_instructions_per_launch"):
+    if not prof or not prof.get("valu_wave_instructions_per_step"):
         return None
-    ops = prof["valu_wave_instructions_per_launch"] * 64 / (stages["bfs"]["avg_launch_ms"] * 1e-3) / 1e12
+    ops = prof["valu_wave_instructions_per_step"] * 64 / (stages["bfs"]["ms_per_step"] * 1e-3) / 1e12
     return {"bound": "alu", "kernel": "k_bfs", "achieved": ops, "peak": VALU_PEAK_TOPS,
             "unit": "T VALU lane-ops/s", "frac": ops / VALU_PEAK_TOPS,
-            "valu_wave_instructions_per_launch": prof["valu_wave_instructions_per_launch"],
-            "lds_wave_instructions_per_launch": prof.get("lds_wave_instructions_per_launch")}
+            "valu_wave_instructions_per_step": prof["valu_wave_instructions_per_step"],
+            "lds_wave_instructions_per_step": prof.get("lds_wave_instructions_per_step")}
 
 
 def dense_leg(args, qc, torch) -> dict:
@@ -504,7 +501,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_bfs",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(bfs_launches),
             "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
             "algorithmic_bytes_per_launch": bytes_step / bfs_launches,
         },
