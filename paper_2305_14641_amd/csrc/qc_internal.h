@@ -76,7 +76,7 @@ struct GraphDev {
     const double *inv_a;      // [n_sigmas] 1/a, a = (2 sigma) sigma
     const float *w32c;        // [n_sigmas*K*4] FP32 (w_hi, w_lo, u_hi, u_lo)
     const uint16_t *wbf16;    // [n_sigmas*K*2] BF16 (w, u) pairs for the matrix-core variant
-    int32_t *parent;          // [n_sigmas*n] descent parents
+    int32_t *parent;          // [n_sigmas][n] descent parents, node order[t]'s at t
     int32_t *status;          // [2]: 0 largest finite distance, 1 overflow flag
     unsigned long long *recheck;  // count of FP64 re-decided nodes
 };

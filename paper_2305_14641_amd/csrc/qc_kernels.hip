@@ -565,7 +565,7 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
                     rechecked[q] = true;
                 }
             }
-            G.parent[(int64_t)s * n + i] = parent;
+            G.parent[(int64_t)s * n + t] = parent;   // thread order: coalesced
         }
     }
     // one counter update per wavefront
@@ -609,9 +609,10 @@ __global__ __launch_bounds__(1024) void k_jump(const GraphDev *__restrict__ grap
     const int n = G.n;
     const int s = sigma_base + (int)blockIdx.y;
     if (s >= G.n_sigmas) return;
+    // parents are stored in the descent's thread order: node order[t]'s at t
     const int32_t *__restrict__ par = G.parent + (int64_t)s * n;
     int32_t *lab = labels_base + (int64_t)blockIdx.y * labels_ld + job.out_off;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = par[i];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) lab[G.order[t]] = par[t];
     __syncthreads();
     for (int round = 0; round < 64; ++round) {
         int changed = 0;
@@ -641,8 +642,9 @@ __global__ __launch_bounds__(1024) void k_jump_lds(const GraphDev *__restrict__ 
     const int n = G.n;
     const int s = sigma_base + (int)blockIdx.y;
     if (s >= G.n_sigmas || n > CAP) return;
+    // parents are stored in the descent's thread order: node order[t]'s at t
     const int32_t *__restrict__ par = G.parent + (int64_t)s * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = par[i];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) lab[G.order[t]] = par[t];
     __syncthreads();
     for (int round = 0; round < 64; ++round) {
         int changed = 0;
