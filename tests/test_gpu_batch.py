@@ -78,6 +78,34 @@ def test_batch_without_hipgraph_and_fp32c(setup):
     np.testing.assert_array_equal(o2[2].cpu().numpy(), o1[2].cpu().numpy())
 
 
+@pytest.mark.parametrize("S", [1, 5, 7])
+def test_batch_sigma_counts(setup, S):
+    """Sigma counts that are not a multiple of four: the potential sums four
+    sigmas at a time and then one by one, the descent decides groups of four
+    sigmas (its last group partly padding), the resident V interleaves
+    groups of four; all must match the oracle."""
+    torch, qc, graphs, sigmas = setup
+    gs = [graphs[1], graphs[3], graphs[-1]]
+    sig = list(np.geomspace(0.4, 5.0, S))
+    handles = [qc.Graph.from_graph(g) for g in gs]
+    b = qc.Batch(handles, sig, hipgraph=False)
+    psi, v, lab = b.outputs()
+    b.run(psi, v, lab)
+    torch.cuda.synchronize()
+    psi, v, lab = psi.cpu().numpy(), v.cpu().numpy(), lab.cpu().numpy()
+    for i, g in enumerate(gs):
+        o0, o1 = b.offsets[i], b.offsets[i + 1]
+        dist, dmax = oracle.distances(g.n, g.row_ptr, g.col)
+        hist = oracle.hist_rows(dist, dmax + 1)
+        for s, sigma in enumerate(sig):
+            psi_c, v_c = oracle.potential_canonical(hist, sigma)
+            np.testing.assert_allclose(psi[s, o0:o1], psi_c, rtol=1e-6, atol=0)
+            np.testing.assert_allclose(v[s, o0:o1], v_c, rtol=1e-6, atol=0)
+            ref = oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v_c, 0))
+            np.testing.assert_array_equal(lab[s, o0:o1], ref, err_msg=f"S={S} sigma={sigma}")
+    b.close()
+
+
 def test_batch_autotune_changes_no_output(setup):
     """QC_BATCH_AUTOTUNE times the candidate BFS launch shapes of each graph
     and keeps the fastest; the outputs are bitwise those of the planner's
