@@ -62,46 +62,62 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     constexpr int64_t kStep = 64 * 16;   // bytes one wavefront covers per chunk
     uint32_t *const col = &bins[wave][0][lane];
 
+    // bin min(u, K) of this lane: 256 bytes per bin row (one shift-add)
     auto count = [&](uint32_t u) {
-        __hip_atomic_fetch_add(col + 64 * min(u, (uint32_t)K), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add((uint32_t *)((char *)col + (min(u, (uint32_t)K) << 8)), 1u,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
 
     for (int rr = 0; rr < RPW; ++rr) {
-        const int row = job.i0 + rr * WAVES + wave;
+        const int row = __builtin_amdgcn_readfirstlane(job.i0 + rr * WAVES + wave);
         const bool active = row < n;
 #pragma unroll
         for (int k = 0; k <= K; ++k) bins[wave][k][lane] = 0;
         if (active && vec_ok) {
             const int64_t r0 = (int64_t)row * n;
             const int64_t r1 = r0 + n;
-            const int64_t first = (r0 & ~(int64_t)15) + lane * 16;
-            // Whole 16-byte chunks inside the row are counted in the loop;
-            // a chunk that is not (the row's first or last, cut by its ends)
-            // adds to the junk bin K instead, so the loop has no branches and
-            // the next group of loads stays in flight. Loads past the row's
-            // last chunk re-read that chunk (an L2 hit); a whole chunk inside
-            // the row is never clamped.
+            const int64_t wb0 = r0 & ~(int64_t)15;   // the wavefront's first chunk
+            const int64_t first = wb0 + lane * 16;
+            // Whole 16-byte chunks inside the row are counted in the loop; a
+            // chunk cut by a row end has its bytes set to all ones, which the
+            // clamp sends to the junk bin K, so the byte loop has no selects
+            // or branches. Loads past the row's last chunk re-read that chunk
+            // (an L2 hit); a whole chunk inside the row is never clamped.
             const int64_t last_c = min((r1 - 1) & ~(int64_t)15, last_whole);
-            u32x4 cur[kHistDepth];
-#pragma unroll
-            for (int u = 0; u < kHistDepth; ++u) cur[u] = *(global_u4)(base + min(first + u * kStep, last_c));
-            for (int64_t c = first; c < r1; c += kHistDepth * kStep) {
-                u32x4 ahead[kHistDepth];
+            auto load = [&](u32x4 *set, int64_t c) {
 #pragma unroll
                 for (int u = 0; u < kHistDepth; ++u)
-                    ahead[u] = *(global_u4)(base + min(c + (kHistDepth + u) * kStep, last_c));
+                    set[u] = *(global_u4)(base + min(c + u * kStep, last_c));
+                // keeps the loads here: the compiler would otherwise sink them
+                // past the exit test, next to their use
+                asm volatile("" ::: "memory");
+            };
+            auto count_set = [&](const u32x4 *set, int64_t c) {
 #pragma unroll
                 for (int u = 0; u < kHistDepth; ++u) {
                     const int64_t cc = c + u * kStep;
-                    const bool whole = (cc >= r0) && (cc + 16 <= r1);
-                    const uint32_t wv[4] = {cur[u].x, cur[u].y, cur[u].z, cur[u].w};
+                    const uint32_t jm = (cc >= r0 && cc + 16 <= r1) ? 0u : 0xFFFFFFFFu;
+                    const uint32_t wv[4] = {set[u].x | jm, set[u].y | jm, set[u].z | jm,
+                                            set[u].w | jm};
 #pragma unroll
-                    for (int p = 0; p < 16; ++p)
-                        count(whole ? (wv[p / 4] >> (8 * (p % 4))) & 0xFFu : (uint32_t)K);
+                    for (int p = 0; p < 16; ++p) count((wv[p / 4] >> (8 * (p % 4))) & 0xFFu);
                 }
-#pragma unroll
-                for (int u = 0; u < kHistDepth; ++u) cur[u] = ahead[u];
+            };
+            // Two register sets take turns: one is counted while the other's
+            // loads are in flight (a copy from one to the other would make
+            // the compiler wait for every load before the next round). The
+            // exits test the wavefront's first chunk, so no set that starts
+            // past the row is counted.
+            constexpr int64_t kHalf = kHistDepth * kStep;
+            u32x4 a[kHistDepth], b[kHistDepth];
+            load(a, first);
+            for (int64_t c = first, wb = wb0;; c += 2 * kHalf, wb += 2 * kHalf) {
+                load(b, c + kHalf);
+                count_set(a, c);
+                if (wb + kHalf >= r1) break;
+                load(a, c + 2 * kHalf);
+                count_set(b, c + kHalf);
+                if (wb + 2 * kHalf >= r1) break;
             }
             // the row's bytes outside whole chunks: at most 15 at each end
             const int64_t head_end = min(r1, (r0 + 15) & ~(int64_t)15);
