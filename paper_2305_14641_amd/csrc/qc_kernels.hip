@@ -571,9 +571,13 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
             int parent = i;
             if (j1[q] >= 0) {
                 const float tau = kTieTau;
-                bool ambiguous = (m2[q] - m1[q] <= tau * m2[q]);
                 const float hi = fmaxf(m1[q], vi[q]), lo = fminf(m1[q], vi[q]);
-                if (hi - lo <= tau * hi) ambiguous = true;
+                bool ambiguous = (hi - lo <= tau * hi);
+                // which neighbour is lowest matters only when the node moves:
+                // with the lowest clearly above the node, every neighbour's
+                // FP64 V is above the node's too (tau exceeds twice the FP32
+                // error), and the node is a root whatever the near ties
+                if (m1[q] < vi[q] && m2[q] - m1[q] <= tau * m2[q]) ambiguous = true;
                 if (!ambiguous) {
                     parent = (m1[q] < vi[q]) ? j1[q] : i;
                 } else {
