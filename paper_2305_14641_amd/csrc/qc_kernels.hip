@@ -49,7 +49,7 @@ template <int K, int WAVES, int RPW>
 __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict__ graphs,
                                                      const NodeJob *__restrict__ jobs)
 {
-    __shared__ uint32_t bins[WAVES][K + 1][64];
+    __shared__ __attribute__((aligned(16))) uint32_t bins[WAVES][K + 1][64];
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
@@ -61,6 +61,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
     constexpr int64_t kStep = 64 * 16;   // bytes one wavefront covers per chunk
     uint32_t *const col = &bins[wave][0][lane];
+    // the wavefront's bins as 16-byte quads, 16 per bin row
+    constexpr int kQuads = 16;
+    uint4 *const quads = (uint4 *)&bins[wave][0][0];
+    const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = lane; i < (K + 1) * kQuads; i += 64) quads[i] = zero4;
+    __syncthreads();
 
     // bin min(u, K) of this lane: 256 bytes per bin row (one shift-add)
     auto count = [&](uint32_t u) {
@@ -71,8 +77,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     for (int rr = 0; rr < RPW; ++rr) {
         const int row = __builtin_amdgcn_readfirstlane(job.i0 + rr * WAVES + wave);
         const bool active = row < n;
-#pragma unroll
-        for (int k = 0; k <= K; ++k) bins[wave][k][lane] = 0;
         if (active && vec_ok) {
             const int64_t r0 = (int64_t)row * n;
             const int64_t r1 = r0 + n;
@@ -132,11 +136,25 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
         }
         __syncthreads();
         if (active) {
+            // bin k = the sum of its 64 columns: kLanes lanes per bin each add
+            // a share of its quads (rotated by lane, so the 16-byte reads of
+            // eight consecutive lanes cover all banks) and clear them for the
+            // next row; the next row's counts come after the barrier below
             int32_t *__restrict__ h = G.hist + (int64_t)row * G.K;
-            for (int k = lane; k < K; k += 64) {
+            constexpr int kLanes = (K >= 64) ? 1 : 64 / K;
+            constexpr int kShare = kQuads / kLanes;
+            const int part = lane % kLanes;
+            for (int k = lane / kLanes; k < K; k += 64 / kLanes) {
                 uint32_t sum = 0;
-                for (int l = 0; l < 64; ++l) sum += bins[wave][k][(l + k) & 63];
-                h[k] = (int32_t)sum;
+#pragma unroll
+                for (int i = 0; i < kShare; ++i) {
+                    const int q = k * kQuads + part * kShare + (i + lane) % kShare;
+                    const uint4 x = quads[q];
+                    sum += x.x + x.y + x.z + x.w;
+                    quads[q] = zero4;
+                }
+                if constexpr (kLanes == 2) sum += (uint32_t)__shfl_xor((int)sum, 1);
+                if (part == 0) h[k] = (int32_t)sum;
             }
             for (int k = K + lane; k < G.K; k += 64) h[k] = 0;
         }
