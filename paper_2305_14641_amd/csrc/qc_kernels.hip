@@ -30,13 +30,12 @@ hipError_t launch_bfs(int bw, int nw, int planes, int shape, const GraphDev *gra
 // into its own LDS column (bins[k][lane]), so increments never collide, with
 // one extra bin that absorbs unreachable entries (-1 read as 255), which keeps
 // the per-byte work branch-free: extract and clamp the byte, form the bin's
-// address, one no-return LDS add. Lane k then sums bin k over the 64 columns
-// with a rotated start, free of bank conflicts. (Two bins per word as 16-bit
-// halves would halve the LDS but doubles the per-byte ALU work, and the
-// registers already cap the kernel at four wavefronts per SIMD.)
-// Loads are aligned 16-byte chunks, kHistDepth per lane in flight while the
-// previous group is counted (the kernel is bound by HBM latency otherwise;
-// depths 2 / 3 / 4 / 6 / 8 measured 1.30 / 1.30 / 1.34 / 1.82 / 2.03 ms per
+// address, one no-return LDS add. The lanes then sum each bin over its 64
+// columns with 16-byte reads and clear the bins for the next row. (Two bins
+// per word as 16-bit halves would halve the LDS but double the per-byte ALU
+// work.) Loads are aligned 16-byte chunks in two sets of kHistDepth per lane
+// that take turns: one set is counted while the other's loads are in flight
+// (sets of 2 / 3 / 4 / 6 chunks measured 1.18 / 1.19 / 1.23 / 1.32 ms per
 // sweep step).
 // ===========================================================================
 
@@ -61,12 +60,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
     constexpr int64_t kStep = 64 * 16;   // bytes one wavefront covers per chunk
     uint32_t *const col = &bins[wave][0][lane];
+    // The bins are this wavefront's own, so its lanes only need ordering
+    // among themselves (counts before the column sum, the sum's clears
+    // before the next row's counts): a wavefront-scope fence, no workgroup
+    // barrier, and the workgroup's wavefronts run their rows independently.
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
     // the wavefront's bins as 16-byte quads, 16 per bin row
     constexpr int kQuads = 16;
     uint4 *const quads = (uint4 *)&bins[wave][0][0];
     const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
     for (int i = lane; i < (K + 1) * kQuads; i += 64) quads[i] = zero4;
-    __syncthreads();
+    wave_sync();
 
     // bin min(u, K) of this lane: 256 bytes per bin row (one shift-add)
     auto count = [&](uint32_t u) {
@@ -134,7 +141,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
             const int64_t r0 = (int64_t)row * n;
             for (int64_t f = r0 + lane; f < r0 + n; f += 64) count((uint32_t)(uint8_t)base[f]);
         }
-        __syncthreads();
+        wave_sync();
         if (active) {
             // bin k = the sum of its 64 columns: kLanes lanes per bin each add
             // a share of its quads (rotated by lane, so the 16-byte reads of
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
             }
             for (int k = K + lane; k < G.K; k += 64) h[k] = 0;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
