@@ -146,7 +146,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
             // bin k = the sum of its 64 columns: kLanes lanes per bin each add
             // a share of its quads (rotated by lane, so the 16-byte reads of
             // eight consecutive lanes cover all banks) and clear them for the
-            // next row; the next row's counts come after the barrier below
+            // next row; the next row's counts come after the fence below
             int32_t *__restrict__ h = G.hist + (int64_t)row * G.K;
             constexpr int kLanes = (K >= 64) ? 1 : 64 / K;
             constexpr int kShare = kQuads / kLanes;
