@@ -197,7 +197,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     // The fields share one LDS array, the field the pull gathers from first
     // (LDS address 0, so a gather's address is the column's word offset):
     // two fields [seen | nxt], three fields [front | nxt | seen].
-    __shared__ T fields[(WIDE ? 2 : 3) * kLdsWords];
+    __shared__ __attribute__((aligned(16))) T fields[(WIDE ? 2 : 3) * kLdsWords];
     __shared__ uint32_t found_pairs;
     __shared__ int32_t srcs[BW];          // the batch's sources
     T *const front = fields;
@@ -329,7 +329,14 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     // rows srcs[0..nb-1], columns = owned nodes. Unreached pairs get -1 (0xFF).
     // Only the loop over words is unrolled (so the planes keep static register
     // indices); the loop over the word's dwords shifts by a variable amount.
-    int8_t *__restrict__ out = G.dist;
+    // The output row of every source, dist + srcs[b] * n, computed once into
+    // the LDS of nxt (which the search no longer needs), so that a byte's
+    // address is its row pointer plus its column: four pointers per group of
+    // four bytes come with two 16-byte LDS reads.
+    typedef __attribute__((address_space(1))) int8_t gbyte;
+    gbyte **const rows = (gbyte **)nxt;
+    if (tid < nb) rows[tid] = (gbyte *)G.dist + (int64_t)srcs[tid] * n;
+    __syncthreads();
     // words of the graph's own nodes (the first n)
     const int own_words = WEIGHTED ? (n + W::kPer - 1) / W::kPer : nwords;
     const int td = opaque(tid);
@@ -347,15 +354,16 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
                 uint32_t d = spread4((uint32_t)(~sw >> (4 * t)) & 0xFu) * 0xFFu;
 #pragma unroll
                 for (int p = 0; p < P; ++p) d |= spread4((uint32_t)(lp[p] >> (4 * t)) & 0xFu) << p;
+                // pairs 4t..4t+3: one node, sources b0..b0+3 (BW is a multiple of 4)
+                const int qn = (4 * t) / BW;       // node within the word
+                const int b0 = (4 * t) % BW;       // first source of the four
+                const int v = w * W::kPer + qn;
+                gbyte *r[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int i = 4 * t + k;       // pair index in the word
-                    const int qn = i / BW;         // node within the word
-                    const int b = i % BW;          // source within the batch
-                    const int v = w * W::kPer + qn;
-                    if (v < n && b < nb)
-                        out[(int64_t)srcs[b] * n + v] = (int8_t)((d >> (8 * k)) & 0xFFu);
-                }
+                for (int k = 0; k < 4; ++k) r[k] = rows[b0 + k];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (v < n && b0 + k < nb) r[k][v] = (int8_t)((d >> (8 * k)) & 0xFFu);
             }
         }
     }
