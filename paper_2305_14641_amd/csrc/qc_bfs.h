@@ -350,20 +350,30 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             for (int p = 0; p < P; ++p) lp[p] = plane[j][p];
 #pragma unroll 1
             for (int t = 0; t < W::kBits / 4; ++t) {
+                // pairs 4t..4t+3: one node, sources b0..b0+3 (BW is a multiple
+                // of 4); their four row pointers are read first, together
+                // (entries past nb are never stored through)
+                const int qn = (4 * t) / BW;       // node within the word
+                const int b0 = (4 * t) % BW;       // first source of the four
+                const int v = w * W::kPer + qn;
+                const ulonglong2 r01 = *(const ulonglong2 *)(rows + b0);
+                const ulonglong2 r23 = *(const ulonglong2 *)(rows + b0 + 2);
+                asm volatile("" ::: "memory");   // keeps the reads ahead of the byte assembly
+                gbyte *const r[4] = {(gbyte *)r01.x, (gbyte *)r01.y, (gbyte *)r23.x, (gbyte *)r23.y};
                 // pairs 4t..4t+3 of the word -> one dword of 4 distance bytes
                 uint32_t d = spread4((uint32_t)(~sw >> (4 * t)) & 0xFu) * 0xFFu;
 #pragma unroll
                 for (int p = 0; p < P; ++p) d |= spread4((uint32_t)(lp[p] >> (4 * t)) & 0xFu) << p;
-                // pairs 4t..4t+3: one node, sources b0..b0+3 (BW is a multiple of 4)
-                const int qn = (4 * t) / BW;       // node within the word
-                const int b0 = (4 * t) % BW;       // first source of the four
-                const int v = w * W::kPer + qn;
-                gbyte *r[4];
+                if (b0 + 4 <= nb) {   // all four sources in the batch (uniform)
+                    if (v < n) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) r[k] = rows[b0 + k];
+                        for (int k = 0; k < 4; ++k) r[k][v] = (int8_t)((d >> (8 * k)) & 0xFFu);
+                    }
+                } else {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (v < n && b0 + k < nb) r[k][v] = (int8_t)((d >> (8 * k)) & 0xFFu);
+                    for (int k = 0; k < 4; ++k)
+                        if (v < n && b0 + k < nb) r[k][v] = (int8_t)((d >> (8 * k)) & 0xFFu);
+                }
             }
         }
     }
