@@ -334,6 +334,8 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     // address is its row pointer plus its column: four pointers per group of
     // four bytes come with two 16-byte LDS reads.
     typedef __attribute__((address_space(1))) int8_t gbyte;
+    typedef uint32_t __attribute__((aligned(1))) u32_any;   // rows need not be 4-byte aligned
+    typedef __attribute__((address_space(1))) u32_any gu32;
     gbyte **const rows = (gbyte **)nxt;
     if (tid < nb) rows[tid] = (gbyte *)G.dist + (int64_t)srcs[tid] * n;
     __syncthreads();
@@ -351,25 +353,33 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
 #pragma unroll 1
             for (int t = 0; t < W::kBits / 4; ++t) {
                 // pairs 4t..4t+3: one node, sources b0..b0+3 (BW is a multiple
-                // of 4); their four row pointers are read first, together
-                // (entries past nb are never stored through)
+                // of 4)
                 const int qn = (4 * t) / BW;       // node within the word
                 const int b0 = (4 * t) % BW;       // first source of the four
                 const int v = w * W::kPer + qn;
-                const ulonglong2 r01 = *(const ulonglong2 *)(rows + b0);
-                const ulonglong2 r23 = *(const ulonglong2 *)(rows + b0 + 2);
-                asm volatile("" ::: "memory");   // keeps the reads ahead of the byte assembly
-                gbyte *const r[4] = {(gbyte *)r01.x, (gbyte *)r01.y, (gbyte *)r23.x, (gbyte *)r23.y};
                 // pairs 4t..4t+3 of the word -> one dword of 4 distance bytes
                 uint32_t d = spread4((uint32_t)(~sw >> (4 * t)) & 0xFu) * 0xFFu;
 #pragma unroll
                 for (int p = 0; p < P; ++p) d |= spread4((uint32_t)(lp[p] >> (4 * t)) & 0xFu) << p;
-                if (b0 + 4 <= nb) {   // all four sources in the batch (uniform)
-                    if (v < n) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) r[k][v] = (int8_t)((d >> (8 * k)) & 0xFFu);
-                    }
+                // One node per lane (W::kPer == 1): the four lanes of a quad
+                // hold four consecutive nodes. A 4 x 4 byte transpose within
+                // the quad (swap 16-bit halves with lane ^ 2, then bytes with
+                // lane ^ 1) gives lane q the bytes of source b0 + q for the
+                // quad's four nodes: one 4-byte store instead of four byte
+                // stores. Taken when the whole quad is in the graph and all
+                // four sources in the batch (the same for its four lanes).
+                const int q = td & 3;
+                if (W::kPer == 1 && b0 + 4 <= nb && v - q + 3 < n) {
+                    const uint32_t hi = (uint32_t)(q >> 1), odd = (uint32_t)(q & 1);
+                    const uint32_t p2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0x4E, 0xF, 0xF, false);
+                    const uint32_t a = __builtin_amdgcn_perm(p2, d, hi ? 0x03020706u : 0x05040100u);
+                    const uint32_t p1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)a, 0xB1, 0xF, 0xF, false);
+                    const uint32_t e = __builtin_amdgcn_perm(p1, a, odd ? 0x03070105u : 0x06020400u);
+                    *(gu32 *)(rows[b0 + q] + (v - q)) = e;
                 } else {
+                    const ulonglong2 r01 = *(const ulonglong2 *)(rows + b0);
+                    const ulonglong2 r23 = *(const ulonglong2 *)(rows + b0 + 2);
+                    gbyte *const r[4] = {(gbyte *)r01.x, (gbyte *)r01.y, (gbyte *)r23.x, (gbyte *)r23.y};
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         if (v < n && b0 + k < nb) r[k][v] = (int8_t)((d >> (8 * k)) & 0xFFu);
