@@ -168,11 +168,19 @@ def test_large_sigma_limit_mean_square_distance():
     np.testing.assert_allclose(v * 2 * sigma * sigma, mean_sq, rtol=1e-6)
 
 
-def test_weights_are_libm_exp():
-    w, a = oracle.weights(6, 1.5)
-    assert a == (2.0 * 1.5) * 1.5
-    for k in range(6):
-        assert w[k] == math.exp(-(k * k) / a)
+def test_weights_match_high_precision_exp():
+    """The canonical weights w_k = exp(-k^2 / a), a = 2 sigma^2 (Eq. 2's
+    Gaussian at hop distance k), are the exponential of the rounded FP64
+    quotient to within one rounding of a 50-digit evaluation; for a dyadic
+    sigma, a itself is exact."""
+    for sigma in (0.3, 1.5, 6.0):
+        w, a = oracle.weights(12, sigma)
+        if sigma != 0.3:
+            assert a == float(2 * mpmath.mpf(sigma) ** 2)
+        for k in range(12):
+            q = -(k * k) / a                      # one IEEE division, as in the definition
+            x = mpmath.e ** mpmath.mpf(q)
+            assert abs(w[k] - float(x)) <= 2.3e-16 * float(x), (sigma, k)
 
 
 @pytest.mark.parametrize("g", [gg.random_graph(25, 0.15, 7), gg.barbell_graph(5), gg.config1()],
@@ -227,3 +235,63 @@ def test_dense_form_vs_mpmath_and_literal():
     psi_l, v_l = oracle.potential_literal(g.n, g.row_ptr, g.col, 1.3, cap=2.0)
     np.testing.assert_allclose(psi_d, psi_l, rtol=1e-14)
     np.testing.assert_allclose(v_d, v_l, rtol=1e-14)
+
+
+def test_literal_reading_weighted_star_closed_form():
+    """Section 3.1 read literally with real edge weights: on a star whose
+    edges all differ, the centre sees every leaf at its own edge's weight and
+    a leaf sees the centre at its edge's weight and every other leaf at the
+    cap. Both follow from the construction alone (50 digits, mpmath), so an
+    entry's weight taken from the wrong index (the neighbour's id instead of
+    the entry, or the row's first entry) moves the result far off."""
+    leaves = 6
+    g = gg.star_graph(leaves)
+    # weights per CSR entry; the two entries of an edge carry the same value
+    w_edge = {leaf: 0.25 + 0.375 * leaf for leaf in range(1, leaves + 1)}
+    weight = np.empty(g.nnz, dtype=np.float64)
+    for i in range(g.n):
+        for e in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            j = int(g.col[e])
+            weight[e] = w_edge[max(i, j)]
+    cap = 3.5
+    for sigma in (0.6, 1.0, 2.2):
+        psi, v = oracle.potential_literal(g.n, g.row_ptr, g.col, sigma, weight=weight, cap=cap)
+        a = 2 * mpmath.mpf(sigma) ** 2
+
+        def pv(ds):
+            ds = [mpmath.mpf(x) for x in ds]
+            p = mpmath.fsum(mpmath.e ** (-(x * x) / a) for x in ds)
+            return p, mpmath.fsum(x * x * mpmath.e ** (-(x * x) / a) for x in ds) / (a * p)
+
+        for i in range(g.n):
+            if i == 0:
+                ds = [0.0] + [w_edge[l] for l in range(1, leaves + 1)]
+            else:
+                ds = [0.0, w_edge[i]] + [cap] * (leaves - 1)
+            psi_x, v_x = pv(ds)
+            assert abs(psi[i] - float(psi_x)) <= 1e-14 * float(psi_x), (sigma, i)
+            assert abs(v[i] - float(v_x)) <= 1e-14 * float(v_x), (sigma, i)
+
+
+def test_literal_reading_weighted_equals_dense_on_written_matrix():
+    """The weighted literal reading equals the dense form (itself pinned to a
+    50-digit evaluation above) on the literal matrix written out on the host:
+    the entry's weight for an edge, the cap for a missing edge, 0 on the
+    diagonal. Random symmetric weights, exactly representable in float32."""
+    g = gg.random_graph(60, 0.12, 11)
+    rng = np.random.default_rng(5)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    w_sym = np.zeros((g.n, g.n))
+    up = rows < g.col
+    w_sym[rows[up], g.col[up]] = rng.integers(1, 40, up.sum()) / 8.0
+    w_sym = w_sym + w_sym.T
+    weight = w_sym[rows, g.col].astype(np.float64)
+    cap = 6.0
+    lit = np.full((g.n, g.n), cap, dtype=np.float32)
+    lit[rows, g.col] = weight.astype(np.float32)
+    np.fill_diagonal(lit, 0.0)
+    for sigma in (0.8, 1.7, 4.0):
+        psi_l, v_l = oracle.potential_literal(g.n, g.row_ptr, g.col, sigma, weight=weight, cap=cap)
+        psi_d, v_d = oracle.potential_dense(lit, sigma)
+        np.testing.assert_allclose(psi_l, psi_d, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(v_l, v_d, rtol=1e-14, atol=0)
