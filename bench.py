@@ -11,8 +11,14 @@ pointer jumping to labels. Inputs (CSR) are resident before timing starts.
 Metric: pair-terms per second, a pair-term being one (i, j, sigma) term of the
 potential sum (sum over graphs of N^2 times the number of sigmas), for the
 batched form replayed as one HIP graph. Also reported: graphs/s, the plain
-per-graph path on the same GPU, per-stage kernel times, the roofline of the
-dominant kernel and the CPU oracle on a bounded sample.
+per-graph path on the same GPU, per-stage kernel times, the search's edge
+visits and LDS bytes gathered, the roofline of the dominant kernel, the
+smaller workloads (one 200-node graph's latency, the 2,708- and 19,717-node
+graphs end to end, psi/V from a resident matrix), the serving form on the
+whole 1,024-request stream (p50/p99 latency and graphs/s at several arrival
+rates, against one request at a time), the fully connected dense workload,
+and the CPU oracle on bounded samples (every core and one thread), whose
+labels are compared with the GPU's.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -31,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # vector lane-operations/s: 256 CUs x 64 lanes x 2.4 GHz
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # LDS bytes/s: 256 CUs x 128 bytes per clock x 2.4 GHz
 
 
 def log(msg):
@@ -72,32 +79,65 @@ def profiled_traffic(launches_per_step):
     return prof["hbm_bytes_per_step"] / launches_per_step
 
 
-def cpu_baseline(graphs, sigmas, budget_s: float) -> dict:
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(graphs, sigmas, budget_s: float, gpu_labels=None, offsets=None,
+                 threads=None) -> dict:
     """The oracle (as it stands) on the first graphs of the workload, in order
-    of increasing size, until about `budget_s` seconds of CPU work."""
+    of increasing size, until about `budget_s` seconds of CPU work, on
+    `threads` threads (default: every core). When the GPU's labels of the
+    same graphs are given, the oracle's labels are compared with them (after
+    the timed work of each graph)."""
     import oracle
-    order = sorted(range(len(graphs)), key=lambda i: graphs[i].n)
-    done, terms, t_total = [], 0.0, 0.0
-    for i in order:
-        g = graphs[i]
-        t0 = time.perf_counter()
-        dist, dmax = oracle.distances(g.n, g.row_ptr, g.col)
-        hist = oracle.hist_rows(dist, dmax + 1)
-        for s in sigmas:
-            _, v = oracle.potential_canonical(hist, s)
-            oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v, 0))
-        t_total += time.perf_counter() - t0
-        terms += float(g.n) ** 2 * len(sigmas)
-        done.append(g.n)
-        if t_total >= budget_s:
-            break
-    return {
-        "value": terms / t_total, "unit": "pair-terms/s", "cores": oracle.num_threads(),
+    before = oracle.num_threads()
+    if threads:
+        oracle.set_num_threads(threads)
+    try:
+        order = sorted(range(len(graphs)), key=lambda i: graphs[i].n)
+        done, terms, t_total = [], 0.0, 0.0
+        mismatches = 0
+        for i in order:
+            g = graphs[i]
+            t0 = time.perf_counter()
+            dist, dmax = oracle.distances(g.n, g.row_ptr, g.col)
+            hist = oracle.hist_rows(dist, dmax + 1)
+            labels = []
+            for s in sigmas:
+                _, v = oracle.potential_canonical(hist, s)
+                labels.append(oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v, 0)))
+            t_total += time.perf_counter() - t0
+            if gpu_labels is not None:
+                got = gpu_labels[:, offsets[i]:offsets[i + 1]]
+                mismatches += int((got != np.stack(labels)).sum())
+            terms += float(g.n) ** 2 * len(sigmas)
+            done.append(g.n)
+            if t_total >= budget_s:
+                break
+        cores = oracle.num_threads()
+    finally:
+        if threads:
+            oracle.set_num_threads(before)
+    out = {
+        "value": terms / t_total, "unit": "pair-terms/s", "cores": cores,
         "kind": "oracle",
         "sample": (f"{len(done)} smallest of the {len(graphs)} graphs (N={min(done)}..{max(done)}), "
                    f"all {len(sigmas)} sigmas: BFS distances, histograms, canonical FP64 psi/V, "
                    f"descent labels; {t_total:.1f} s"),
+        "cpu_model": cpu_model(),
     }
+    if gpu_labels is not None:
+        out["parity_ok"] = mismatches == 0
+        out["labels_compared"] = int(sum(done) * len(sigmas))
+        out["label_mismatches"] = mismatches
+    return out
 
 
 def _gen_request(r):
@@ -106,22 +146,26 @@ def _gen_request(r):
     return g.n, g.row_ptr, g.col, sig
 
 
-def serve(args):
+def gen_requests(count: int) -> list:
+    """The serving stream's requests, drawn in worker processes. Called before
+    anything touches the GPU, so no process that has initialised it forks."""
+    import concurrent.futures as cf
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        reqs = list(ex.map(_gen_request, range(count), chunksize=4))
+    log(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f}s "
+        f"(N {min(r[0] for r in reqs)}..{max(r[0] for r in reqs)})")
+    return reqs
+
+
+def serve(args, reqs):
     """Serving form on the request stream: open-loop Poisson arrivals, p50/p99
     latency (scheduled arrival -> labels on the host), graphs/s, and the same
     requests run one at a time."""
-    import concurrent.futures as cf
     import threading
-    import torch
     from paper_2305_14641_amd import graphgen as gg
     from paper_2305_14641_amd import qc
 
-    torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
-        reqs = list(ex.map(_gen_request, range(args.serve), chunksize=4))
-    log(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f}s "
-        f"(N {min(r[0] for r in reqs)}..{max(r[0] for r in reqs)})")
     budget = int(args.serve_budget_gib * (1 << 30))
     # the plain path: one request at a time through the same server (1 slot)
     srv1 = qc.Server(max_slots=1, hbm_budget_bytes=budget)
@@ -132,7 +176,10 @@ def serve(args):
         srv1.wait(srv1.submit(r[0], r[1], r[2], r[3]))
     plain_s = time.perf_counter() - t0
     srv1.close()
+    log(f"serving, one request at a time: {len(reqs) / plain_s:.1f} graphs/s")
     results = {"requests": len(reqs), "slots": args.serve_slots,
+               "budget_gib": args.serve_budget_gib,
+               "sum_n2": float(sum(float(r[0]) ** 2 for r in reqs)),
                "plain_graphs_per_s": len(reqs) / plain_s, "rates": []}
     for rate in args.serve_rates:
         arrivals = gg.poisson_arrivals(len(reqs), rate, seed=77)
@@ -162,11 +209,86 @@ def serve(args):
         lat_ms = np.sort(np.array(lat) * 1e3)
         entry = {"rate_per_s": rate, "p50_ms": float(np.percentile(lat_ms, 50)),
                  "p99_ms": float(np.percentile(lat_ms, 99)),
-                 "graphs_per_s": len(reqs) / (end - start), **stats}
+                 "graphs_per_s": len(reqs) / (end - start),
+                 "vs_plain": (len(reqs) / (end - start)) / results["plain_graphs_per_s"], **stats}
         results["rates"].append(entry)
         log(f"rate {rate}/s: p50 {entry['p50_ms']:.1f} ms, p99 {entry['p99_ms']:.1f} ms, "
             f"{entry['graphs_per_s']:.1f} graphs/s, peak in flight {stats['peak_requests_in_flight']}")
     return results
+
+
+def configs_leg(args, qc, gg, torch) -> dict:
+    """The smaller workloads, each on its own: the 200-node graph's latency per
+    call, the 2,708-node (4 sigmas) and 19,717-node (sigma 2) graphs end to
+    end on the plain path, and psi/V from the 19,717-node graph's resident
+    distance matrix (the histogram pass plus the potential kernel)."""
+    out = {}
+
+    def path(G, sigmas, dist=None):
+        G.distances(dist)
+        G.potential(sigmas)
+        for s in range(len(sigmas)):
+            G.labels(s, qc.TIE_STRICT)
+        G.sync()
+
+    # 200 nodes: one call of Algorithm 4 from host CSR (temporary handle), and
+    # the same on a resident handle
+    g1 = gg.config1()
+    lat_call, lat_res = [], []
+    G1 = qc.Graph.from_graph(g1)
+    for k in range(60):
+        t0 = time.perf_counter()
+        qc.cluster(g1.n, g1.row_ptr, g1.col, gg.SIGMAS_C1, qc.TIE_STRICT)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        path(G1, gg.SIGMAS_C1)
+        t2 = time.perf_counter()
+        if k >= 10:
+            lat_call.append((t1 - t0) * 1e3)
+            lat_res.append((t2 - t1) * 1e3)
+    G1.close()
+    out["c1"] = {"workload": "SBM N=200, 4 blocks, sigma 1",
+                 "call_from_host_csr_ms": {"p50": float(np.percentile(lat_call, 50)),
+                                           "p99": float(np.percentile(lat_call, 99))},
+                 "resident_graph_ms": {"p50": float(np.percentile(lat_res, 50)),
+                                       "p99": float(np.percentile(lat_res, 99))}}
+    log(f"config 1 latency: {out['c1']['call_from_host_csr_ms']['p50']:.3f} ms per call, "
+        f"{out['c1']['resident_graph_ms']['p50']:.3f} ms on a resident graph")
+    for key, g, sigmas in (("c2", gg.config2(), gg.SIGMAS_C2), ("c3", gg.config3(), gg.SIGMAS_C3)):
+        G = qc.Graph.from_graph(g)
+        dist = torch.empty((g.n, g.n), dtype=torch.int8, device="cuda")
+        for _ in range(2):
+            path(G, sigmas, dist)        # the first run learns dmax and re-plans
+        ts = []
+        for _ in range(max(args.steps, 5)):
+            t0 = time.perf_counter()
+            path(G, sigmas, dist)
+            ts.append((time.perf_counter() - t0) * 1e3)
+        ms = float(np.median(ts))
+        terms = float(g.n) ** 2 * len(sigmas)
+        out[key] = {"workload": f"DC-SBM N={g.n}, {len(sigmas)} sigma(s)", "end_to_end_ms": ms,
+                    "pair_terms_per_s": terms / (ms * 1e-3), "graphs_per_s": 1e3 / ms}
+        if key == "c3":
+            # psi/V from the resident matrix: the histogram pass over it and
+            # the potential kernel, device times from the stage events
+            qc.timing_enable(True)
+            reps = max(args.steps, 5)
+            for _ in range(reps):
+                G.distances(dist)
+                G.potential(sigmas)
+            torch.cuda.synchronize()
+            h_ms, _ = qc.timing_read(qc.STAGE_HIST)
+            p_ms, _ = qc.timing_read(qc.STAGE_POTENTIAL)
+            qc.timing_enable(False)
+            t = (h_ms + p_ms) / reps
+            out[key]["potential_from_resident_matrix"] = {
+                "hist_ms": h_ms / reps, "potential_ms": p_ms / reps, "ms": t,
+                "pair_terms_per_s": terms / (t * 1e-3),
+                "hbm_gbs": (float(g.n) ** 2 + 8.0 * g.n * 32 + 8.0 * g.n * len(sigmas)) / (t * 1e-3) / 1e9}
+        log(f"{key}: {ms:.3f} ms end to end, {terms / (ms * 1e-3):.3e} pair-terms/s")
+        del dist
+        G.close()
+    return out
 
 
 def quality_sweep(qc, gg, torch) -> dict:
@@ -318,18 +440,28 @@ def main():
                     help="sigma-sweep quality study: label quality vs the planted blocks")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
-    ap.add_argument("--serve", type=int, default=0,
-                    help="run the serving form on the first SERVE requests of the stream instead")
+    ap.add_argument("--serve-requests", type=int, default=1024,
+                    help="requests of the serving stream the serving leg runs (0: no serving leg)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg and print its result")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[10, 50, 200, 500])
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the smaller workloads (latency, end to end, resident matrix)")
+    ap.add_argument("--cpu-1t-budget-s", type=float, default=6.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    if args.serve:
-        res = serve(args)
+    # the serving stream is drawn in worker processes before anything
+    # touches the GPU
+    reqs = gen_requests(args.serve_requests) if args.serve_requests > 0 and not args.quality else None
+    if args.serve_only:
+        import torch
+        torch.cuda.set_device(0)
+        res = serve(args, reqs)
         print(json.dumps({"metric": "serving: p50/p99 latency and graphs/s on the request stream",
                           "config": {"workload": "serving: Poisson stream of DC-SBM clustering "
                                                  "requests, N log-uniform [500, 5e4], 1-8 sigmas"},
@@ -389,6 +521,8 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     log(f"batched: {dt * 1e3:.2f} ms/step")
     rechecks = batch.recheck_count()
+    edge_visits, lds_gathered = batch.search_stats()
+    lab_host = lab.cpu().numpy()
 
     # -- per-kernel device time: the same launches, not captured, with events --
     batch_nograph = qc.Batch(handles, sigmas, tie_mode=qc.TIE_STRICT, hipgraph=False)
@@ -467,11 +601,18 @@ def main():
         log(f"bf16 sweep: {ms:.3f} ms, max rel err psi {worst_psi:.2e} V {worst_v:.2e}")
 
     dense = None if args.no_dense else dense_leg(args, qc, torch)
+    configs = None if args.no_configs else configs_leg(args, qc, gg, torch)
+    serving = serve(args, reqs) if reqs else None
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(graphs, sigmas, args.cpu_budget_s)
-        log(f"cpu oracle: {cpu['value']:.3e} pair-terms/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(graphs, sigmas, args.cpu_budget_s, lab_host, batch.offsets)
+        log(f"cpu oracle: {cpu['value']:.3e} pair-terms/s on {cpu['cores']} threads, "
+            f"labels {'equal' if cpu['parity_ok'] else 'DIFFERENT'}")
+        one = cpu_baseline(graphs, sigmas, args.cpu_1t_budget_s, lab_host, batch.offsets, threads=1)
+        cpu["one_thread"] = {k: one[k] for k in ("value", "cores", "sample", "parity_ok")}
+        cpu["parity_ok"] = cpu["parity_ok"] and one["parity_ok"]
+        log(f"cpu oracle, one thread: {one['value']:.3e} pair-terms/s")
 
     result = {
         "metric": "pair-terms/sec for psi/V (+ graphs/sec); batched vs plain at 1e-6",
@@ -506,10 +647,22 @@ def main():
             "algorithmic_bytes_per_launch": bytes_step / bfs_launches,
         },
         "bfs_alu": bfs_alu(stages),
+        "bfs_search": {
+            "edge_visits_per_step": edge_visits,
+            "edge_visits_per_s": edge_visits / (bfs_ms * 1e-3),
+            "lds_bytes_gathered_per_step": lds_gathered,
+            "lds_gather_tbs": lds_gathered / (bfs_ms * 1e-3) / 1e12,
+            "lds_peak_tbs": LDS_PEAK_TBS,
+            "lds_gather_frac": lds_gathered / (bfs_ms * 1e-3) / 1e12 / LDS_PEAK_TBS,
+            "note": "visits counted on the device (pulled levels x edge entries + pushed row "
+                    "entries); time = the search's device time per step",
+        },
         "hist_kernel_gbs": hist_gbs,
         "plain": plain,
         "bf16_sweep": bf16,
         "dense": dense,
+        "configs": configs,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result))

@@ -48,7 +48,9 @@ enum {
     QC_E_DEVICE = 4,        /* no gfx950 device visible, or a HIP call failed */
     QC_E_OVERFLOW = 5,      /* a finite hop distance above 126 */
     QC_E_STATE = 6,         /* call order violated (e.g. labels before potential) */
-    QC_E_BUSY = 7           /* serving: request does not fit the memory budget now */
+    QC_E_BUSY = 7,          /* serving: request does not fit the memory budget, or is already running */
+    QC_E_TIMEOUT = 8,       /* serving: request not admitted before its queue deadline */
+    QC_E_CANCELLED = 9      /* serving: request withdrawn by qc_server_cancel */
 };
 
 /* Tie rules of the descent (Algorithm 2 and the prose after Algorithm 4).
@@ -231,13 +233,63 @@ qc_status qc_potential_dense(const float *dist, int64_t n_rows, int64_t n_cols, 
                              const double *sigmas, int32_t n_sigmas, double *psi_out,
                              double *v_out, void *stream);
 
+/*
+ * Copy the resident canonical FP64 potential of the last qc_potential call
+ * (or batch run) to the caller: the values on which the descent re-decides
+ * near ties. V = (1/a) (S1/S2) with a = (2 sigma) sigma, S2 = sum_k h_k w_k,
+ * S1 = sum_k (k^2 h_k) w_k, w_k = exp(-k^2/a) from the host C library, both
+ * sums in ascending k from +0.0 with every product and sum rounded on its own
+ * (Algorithm 1 regrouped by distance value; Eq. 7's approximate form).
+ *   v64_out  device, double[n_sigmas][n], node order
+ * Errors: QC_E_INVAL for a NULL pointer; QC_E_STATE before qc_potential, or
+ * when the last potential was not QC_PREC_FP64ACC (the other precisions keep
+ * no FP64 values).
+ */
+qc_status qc_get_potential64(qc_graph g, double *v64_out, void *stream);
+
+/*
+ * Algorithm 4 in one call, on a temporary handle released before the call
+ * returns (the call waits for `stream`): hop distances, psi and V (Eq. 2,
+ * Algorithm 1) for every width, and the descent's labels (Algorithms 2-3)
+ * for every width.
+ *   n, nnz, row_ptr, col_idx  host CSR as for qc_graph_create with flags 0
+ *                (canonical and undirected, else QC_E_NOT_SYMMETRIC)
+ *   sigmas, n_sigmas          host, as for qc_potential
+ *   tie_mode     QC_TIE_STRICT or QC_TIE_MERGE
+ *   dist_out     device, int8[n*n] row-major, 16-byte aligned, or NULL (the
+ *                library then uses a matrix of its own for the call)
+ *   psi_out, v_out  device, float[n_sigmas][n], or NULL
+ *   labels_out   device, int32[n_sigmas][n] (sigma-major), required
+ * Potentials are accumulated in FP64 (QC_PREC_FP64ACC). On QC_E_OVERFLOW the
+ * outputs are undefined. Other errors as the calls it makes.
+ */
+qc_status qc_cluster(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *sigmas, int32_t n_sigmas, uint32_t tie_mode, int8_t *dist_out,
+                     float *psi_out, float *v_out, int32_t *labels_out, void *stream);
+
 /* Number of node decisions the last qc_ggd_labels call (or batch run)
  * re-decided in FP64 (waits for the stream). */
 qc_status qc_last_recheck_count(qc_graph g, int64_t *count_out);
 
 /* Wait for all work issued on `stream` and return any error the device
- * latched (QC_E_OVERFLOW) since the last check. */
+ * latched since the last check: QC_E_OVERFLOW for a finite distance above
+ * 126, QC_E_DEVICE for a search level beyond the handle's distance planes. */
 qc_status qc_graph_sync(qc_graph g, void *stream);
+
+/*
+ * Testing hook for out-of-memory handling; not meant for production use.
+ * After this call the fail_at-th device allocation the library attempts
+ * (counted from 1, in any thread; every buffer a serving request carves from
+ * the server's arena counts as one) fails with QC_E_OOM, and later ones
+ * succeed again;
+ * fail_at = 0 disarms it.
+ *   live_out  host, may be NULL: receives the number of device-allocator
+ *             blocks the library holds at this moment (allocated and not yet
+ *             freed), so a test can check that a failed call released what
+ *             it had taken.
+ * Process-wide. Errors: QC_E_INVAL for fail_at < 0.
+ */
+qc_status qc_debug_alloc_fault(int64_t fail_at, int64_t *live_out);
 
 /*
  * Kernel timing, for benchmarks (process-wide). While enabled, the library

@@ -30,8 +30,11 @@ enum {
  *              uses their resident buffers (distance matrix, histograms,
  *              potentials, weights), so a graph must not be used elsewhere
  *              while a batch run is in flight, and must outlive the batch.
- *              A graph appears at most once. The batch keeps the resident
- *              distance matrix each graph has when the batch is created.
+ *              A graph appears at most once. The batch computes each
+ *              graph's distances into a matrix the graph's handle owns
+ *              (allocated here when the handle has none), never into a
+ *              caller's buffer an earlier qc_distances call was given; that
+ *              owned matrix becomes the graph's resident matrix.
  *   n_graphs   1 <= n_graphs <= 65536
  *   sigmas     host, double[n_sigmas], each finite and > 0 (1..1024 values),
  *              shared by every graph
@@ -67,6 +70,16 @@ qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels
 
 /* Number of node decisions re-decided in FP64 by the last run (waits). */
 qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out);
+
+/*
+ * Work of the last run's multi-source searches (waits for the device), as
+ * counted by the search kernel: edge_visits = sum over the batches of
+ * sources of (levels pulled over the whole edge list x edge entries + the
+ * sources' row entries pushed at level 1); lds_bytes = the bytes of bit
+ * field those visits gathered from LDS (4 or 8 per visit, by batch width).
+ * Either pointer (host) may be NULL.
+ */
+qc_status qc_batch_search_stats(qc_batch b, int64_t *edge_visits, int64_t *lds_bytes);
 
 /* Release the batch (the graphs stay valid). */
 qc_status qc_batch_destroy(qc_batch b);

@@ -5,12 +5,20 @@
  * clustering requests of mixed sizes.
  *
  * Continuous batching: up to `max_slots` requests are on the GPU at once,
- * each on its own stream, and a queued request is admitted (first in, first
- * out) as soon as a slot is free and its device-memory footprint fits what is
- * left of the budget. Device memory is one arena reserved when the server is
- * created and sub-allocated per request, so serving itself never calls the
- * device allocator. A request's results are bitwise identical to the plain
+ * each on its own stream, and a queued request is admitted as soon as a slot
+ * is free and its device-memory footprint fits what is left of the budget
+ * (oldest first; see max_bypass for passing a request that does not fit).
+ * Device memory is one arena reserved when the server is created and
+ * sub-allocated per request, so serving itself never calls the device
+ * allocator. A request's results are bitwise identical to the plain
  * per-graph calls of qc.h.
+ *
+ * Robustness: a request that cannot be admitted before its queue deadline
+ * completes with QC_E_TIMEOUT, a queued request can be withdrawn
+ * (qc_server_cancel), and a request that fails (e.g. QC_E_OOM) releases its
+ * arena region and slot, so later requests are served normally. A request
+ * that has started is never interrupted: every kernel of the path ends on
+ * its own (a search ends after at most 127 levels).
  */
 #ifndef QC_SERVER_H_
 #define QC_SERVER_H_
@@ -28,6 +36,14 @@ typedef struct {
     int64_t hbm_budget_bytes;   /* device arena for request state, > 0 */
     uint32_t tie_mode;          /* QC_TIE_STRICT or QC_TIE_MERGE */
     int32_t want_potentials;    /* 1: also keep psi and V for qc_server_wait */
+    double queue_timeout_s;     /* > 0: a request still queued this many seconds after its
+                                   submission completes with QC_E_TIMEOUT without running;
+                                   0: no deadline (finite, >= 0) */
+    int32_t max_bypass;         /* 0: strict first-in first-out admission. k > 0: when the
+                                   oldest queued request does not fit, younger ones that fit
+                                   may be admitted before it, but each request can be passed
+                                   at most k times; after that nothing is admitted before it
+                                   (0..1000000) */
 } qc_server_opts;
 
 typedef struct {
@@ -74,6 +90,15 @@ qc_status qc_server_poll(qc_server s, int64_t id, int32_t *done_out);
  */
 qc_status qc_server_wait(qc_server s, int64_t id, int32_t *labels_out, float *psi_out,
                          float *v_out, qc_request_info *info);
+
+/*
+ * Withdraw a request that is still queued: it completes with QC_E_CANCELLED
+ * (collect it with qc_server_wait as any other). Returns QC_OK when it was
+ * withdrawn, QC_E_BUSY when it has already been admitted (it then runs to
+ * completion), QC_E_STATE when it has already completed, QC_E_INVAL for an
+ * unknown id.
+ */
+qc_status qc_server_cancel(qc_server s, int64_t id);
 
 /* Largest arena bytes and number of requests in flight at the same time so far. */
 qc_status qc_server_stats(qc_server s, int64_t *peak_bytes_out, int32_t *peak_requests_out);

@@ -78,6 +78,8 @@ def lib():
         L.qco_dijkstra_rows.restype = I
         L.qco_num_threads.argtypes = []
         L.qco_num_threads.restype = I
+        L.qco_set_num_threads.argtypes = [I]
+        L.qco_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -94,6 +96,11 @@ def _csr(row_ptr, col):
 
 def num_threads() -> int:
     return int(lib().qco_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from now on (at least 1)."""
+    lib().qco_set_num_threads(int(k))
 
 
 # --------------------------------------------------------------------------

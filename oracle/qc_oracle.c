@@ -405,3 +405,15 @@ int qco_num_threads(void)
     }
     return t;
 }
+
+/* Threads of the parallel regions that follow (timing at one thread and at
+ * every core); k < 1 is taken as 1. */
+void qco_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(k < 1 ? 1 : k);
+#else
+    (void)k;
+#endif
+}

@@ -27,6 +27,23 @@ qc_status from_hip(hipError_t e)
     return QC_E_DEVICE;
 }
 
+// Out-of-memory injection: allocations left before the one that fails
+// (0: disarmed), and the device allocator blocks currently held.
+static std::atomic<int64_t> g_fault_countdown{0};
+static std::atomic<int64_t> g_live_allocs{0};
+
+bool alloc_fault_now()
+{
+    int64_t c = g_fault_countdown.load(std::memory_order_relaxed);
+    while (c > 0) {
+        if (g_fault_countdown.compare_exchange_weak(c, c - 1, std::memory_order_relaxed))
+            return c == 1;
+    }
+    return false;
+}
+
+void note_device_alloc(int delta) { g_live_allocs.fetch_add(delta, std::memory_order_relaxed); }
+
 qc_status check_device(int *dev_out)
 {
     // The architecture of each device is looked up once (device properties
@@ -115,9 +132,17 @@ qc_status set_plan(qc_graph g, const BfsPlan &plan, bool reorder)
         const int s0 = (p.n_batches - 1 - b) * p.bw;
         jobs[b] = BfsJob{0, s0, batch_target(g, s0, p.bw), 0u};
     }
+    // the new table replaces the old one only once it is in place, so a
+    // failed allocation leaves the handle's plan and jobs as they were
+    BfsJob *d_jobs = nullptr;
+    QC_TRY(galloc(g, &d_jobs, jobs.size()));
+    const qc_status s = upload(d_jobs, jobs);
+    if (s != QC_OK) {
+        gfree(g, d_jobs);
+        return s;
+    }
     gfree(g, g->d_bfs_jobs);
-    QC_TRY(galloc(g, &g->d_bfs_jobs, jobs.size()));
-    QC_TRY(upload(g->d_bfs_jobs, jobs));
+    g->d_bfs_jobs = d_jobs;
     g->plan = p;
     return QC_OK;
 }
@@ -125,12 +150,18 @@ qc_status set_plan(qc_graph g, const BfsPlan &plan, bool reorder)
 qc_status ensure_hist_jobs(qc_graph g)
 {
     if (g->d_hist_jobs && g->hist_jobs_k == g->K) return QC_OK;
-    gfree(g, g->d_hist_jobs);
     const int rows = hist_rows_per_job(g->K);
     std::vector<NodeJob> jobs;
     for (int i = 0; i < g->n; i += rows) jobs.push_back(NodeJob{0, i, 0});
-    QC_TRY(galloc(g, &g->d_hist_jobs, jobs.size()));
-    QC_TRY(upload(g->d_hist_jobs, jobs));
+    NodeJob *d_jobs = nullptr;
+    QC_TRY(galloc(g, &d_jobs, jobs.size()));
+    const qc_status s = upload(d_jobs, jobs);
+    if (s != QC_OK) {
+        gfree(g, d_jobs);
+        return s;
+    }
+    gfree(g, g->d_hist_jobs);
+    g->d_hist_jobs = d_jobs;
     g->n_hist_jobs = (int)jobs.size();
     g->hist_jobs_k = g->K;
     return QC_OK;
@@ -152,18 +183,31 @@ qc_status run_distances(qc_graph g, hipStream_t st)
         int32_t status[2];
         QC_HIP(hipMemcpyAsync(status, g->d_status, sizeof status, hipMemcpyDeviceToHost, st));
         QC_HIP(hipStreamSynchronize(st));
-        if (status[1]) return QC_E_OVERFLOW;
-        if (status[1] & 2) return QC_E_DEVICE;  // cannot happen with 7 planes
+        if (status[1] & 1) return QC_E_OVERFLOW;
+        // a level beyond the planes of a plan with fewer than 7 (cannot
+        // happen on a first search, which always carries 7)
+        if (status[1] & 2) return QC_E_DEVICE;
         // the largest level the search reached; with weighted edges it can
         // be that of a node inside an edge, above the graph's own dmax
+        const int old_k = g->K;
         g->dmax_bfs = status[0];
         g->dmax = status[0];
         g->K = bins_for(g->dmax);
+        // a failed allocation leaves dmax unknown (the next call redoes this
+        // step) with every buffer the handle had still in place
+        int32_t *hist = nullptr;
+        qc_status s = galloc(g, &hist, (size_t)g->n * g->K);
         // later runs need only enough planes for dmax: maybe a wider batch
-        QC_TRY(set_plan(g, plan_bfs(g->n_bfs, g->dmax_bfs)));
+        if (s == QC_OK) s = set_plan(g, plan_bfs(g->n_bfs, g->dmax_bfs));
+        if (s == QC_OK) s = ensure_hist_jobs(g);
+        if (s != QC_OK) {
+            if (hist) gfree(g, hist);
+            g->dmax = g->dmax_bfs = -1;
+            g->K = old_k;
+            return s;
+        }
         gfree(g, g->d_hist);
-        QC_TRY(galloc(g, &g->d_hist, (size_t)g->n * g->K));
-        QC_TRY(ensure_hist_jobs(g));
+        g->d_hist = hist;
         QC_TRY(push_desc(g, st));
     }
     {
@@ -188,28 +232,60 @@ qc_status run_distances(qc_graph g, hipStream_t st)
 
 qc_status ensure_sigma_buffers(qc_graph g, int S)
 {
+    // New buffers replace the old ones only once all of them are in place,
+    // so a failed allocation leaves the handle's buffers as they were.
     if (S > g->pot_cap) {
+        float *psi = nullptr, *v = nullptr;
+        double *v64 = nullptr;
+        int32_t *parent = nullptr;
+        qc_status s = galloc(g, &psi, (size_t)S * g->n);
+        if (s == QC_OK) s = galloc(g, &v, (size_t)v_floats(g->n, S));
+        if (s == QC_OK) s = galloc(g, &v64, (size_t)S * g->n);
+        if (s == QC_OK) s = galloc(g, &parent, (size_t)S * g->n);
+        if (s != QC_OK) {
+            gfree(g, psi);
+            gfree(g, v);
+            gfree(g, v64);
+            gfree(g, parent);
+            return s;
+        }
         gfree(g, g->d_psi);
         gfree(g, g->d_v);
         gfree(g, g->d_v64);
         gfree(g, g->d_parent);
-        QC_TRY(galloc(g, &g->d_psi, (size_t)S * g->n));
-        QC_TRY(galloc(g, &g->d_v, (size_t)v_floats(g->n, S)));
-        QC_TRY(galloc(g, &g->d_v64, (size_t)S * g->n));
-        QC_TRY(galloc(g, &g->d_parent, (size_t)S * g->n));
+        g->d_psi = psi;
+        g->d_v = v;
+        g->d_v64 = v64;
+        g->d_parent = parent;
         g->pot_cap = S;
     }
     if (S * g->K > g->w_cap) {
+        double *w64 = nullptr, *u64 = nullptr, *inv_a = nullptr;
+        float *w32c = nullptr;
+        uint16_t *wbf16 = nullptr;
+        qc_status s = galloc(g, &wbf16, (size_t)S * g->K * 2);
+        if (s == QC_OK) s = galloc(g, &w64, (size_t)S * g->K);
+        if (s == QC_OK) s = galloc(g, &u64, (size_t)S * g->K);
+        if (s == QC_OK) s = galloc(g, &inv_a, (size_t)S);
+        if (s == QC_OK) s = galloc(g, &w32c, (size_t)S * g->K * 4);
+        if (s != QC_OK) {
+            gfree(g, wbf16);
+            gfree(g, w64);
+            gfree(g, u64);
+            gfree(g, inv_a);
+            gfree(g, w32c);
+            return s;
+        }
         gfree(g, g->d_w64);
         gfree(g, g->d_u64);
         gfree(g, g->d_inv_a);
         gfree(g, g->d_w32c);
         gfree(g, g->d_wbf16);
-        QC_TRY(galloc(g, &g->d_wbf16, (size_t)S * g->K * 2));
-        QC_TRY(galloc(g, &g->d_w64, (size_t)S * g->K));
-        QC_TRY(galloc(g, &g->d_u64, (size_t)S * g->K));
-        QC_TRY(galloc(g, &g->d_inv_a, (size_t)S));
-        QC_TRY(galloc(g, &g->d_w32c, (size_t)S * g->K * 4));
+        g->d_w64 = w64;
+        g->d_u64 = u64;
+        g->d_inv_a = inv_a;
+        g->d_w32c = w32c;
+        g->d_wbf16 = wbf16;
         g->w_cap = S * g->K;
     }
     return QC_OK;
@@ -237,6 +313,62 @@ qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStr
         QC_TRY(push_desc(g, st));
     }
     return QC_OK;
+}
+
+int64_t handle_footprint(int32_t n, int64_t nnz, int32_t n_sigmas, bool with_dist,
+                         bool with_labels)
+{
+    if (n < 1 || n > kMaxNodes || nnz < 0 || nnz >= kMaxEdges || n_sigmas < 1 ||
+        n_sigmas > 1024)
+        return -1;
+    const int64_t N = n, S = n_sigmas, K = 128;  // histogram bins: the largest row length
+    const int64_t quads = (nnz + 3) / 4 * 4 + 4;
+    int64_t b = 0;
+    auto add = [&](int64_t bytes) { b += ((bytes > 0 ? bytes : 1) + 255) & ~(int64_t)255; };
+    add(4 * (N + 1));                 // row_ptr
+    add(4 * nnz);                     // col
+    add(4 * N);                       // descent thread order
+    add(4 * N + 4 * (N / 64 + 2));    // sliced neighbour lists: degrees, slice offsets
+    {
+        // and entries: within a window of degree-sorted nodes the padding
+        // adds up to at most 63 times the window's largest degree
+        const int64_t windows = (N + kOrderWindow - 1) / kOrderWindow;
+        add(4 * (nnz + 63 * std::min<int64_t>(nnz, windows * (N - 1)) + 64 * kGgdPad));
+    }
+    add(4 * N);                       // BFS source order
+    add(4 * quads);                   // packed edges
+    add(8);                           // status
+    add(8);                           // recheck counter
+    add((int64_t)sizeof(GraphDev));   // descriptor
+    add(16 * ((N + kNodesPerJob - 1) / kNodesPerJob));  // node jobs
+    add(8 * N);                       // BFS jobs (first plan, <= one job per node)
+    add(8 * N);                       // BFS jobs (plan after dmax is known)
+    if (with_dist) add(N * N + 16);   // distance matrix
+    add(4 * N * K);                   // histograms
+    add(16 * N);                      // histogram jobs
+    add(4 * N * S);                   // psi
+    add(4 * v_floats(n, n_sigmas));   // V (sigma groups rounded up)
+    add(8 * N * S);                   // FP64 V
+    add(4 * N * S);                   // parents
+    add(8 * S * K);                   // w64
+    add(8 * S * K);                   // u64
+    add(8 * S);                       // 1/a
+    add(16 * S * K);                  // FP32 split weights
+    add(4 * S * K);                   // BF16 weights
+    if (with_labels) add(4 * N * S);  // labels
+    return b;
+}
+
+qc_status cluster_on_handle(qc_graph g, const double *sigmas, int32_t n_sigmas,
+                            uint32_t tie_mode, int8_t *dist_out, float *psi_out, float *v_out,
+                            int32_t *labels_out, hipStream_t st)
+{
+    void *stream = (void *)st;
+    QC_TRY(qc_distances(g, dist_out, nullptr, stream));
+    QC_TRY(qc_potential(g, sigmas, n_sigmas, psi_out, v_out, QC_PREC_FP64ACC, stream));
+    for (int32_t k = 0; k < n_sigmas; ++k)
+        QC_TRY(qc_ggd_labels(g, k, tie_mode, labels_out + (size_t)k * g->n, stream));
+    return qc_graph_sync(g, stream);
 }
 
 void destroy(qc_graph g, bool sync)
@@ -287,7 +419,9 @@ const char *qc_status_str(qc_status s)
     case QC_E_DEVICE: return "QC_E_DEVICE: no gfx950 device or a HIP call failed";
     case QC_E_OVERFLOW: return "QC_E_OVERFLOW: a finite hop distance exceeds 126";
     case QC_E_STATE: return "QC_E_STATE: call order violated";
-    case QC_E_BUSY: return "QC_E_BUSY: request does not fit the memory budget now";
+    case QC_E_BUSY: return "QC_E_BUSY: request does not fit the memory budget, or is running";
+    case QC_E_TIMEOUT: return "QC_E_TIMEOUT: request not admitted before its queue deadline";
+    case QC_E_CANCELLED: return "QC_E_CANCELLED: request withdrawn before it ran";
     default: return "unknown qc_status";
     }
 }
@@ -515,6 +649,9 @@ qc_status qc_potential(qc_graph g, const double *sigmas, int32_t n_sigmas, float
     hipStream_t st = as_stream(stream);
     if (!g->have_dist) QC_TRY(qc_distances(g, nullptr, nullptr, stream));
 
+    // until this call has succeeded the handle holds no potentials (the
+    // descent refuses to run on a half-made set)
+    g->have_pot = false;
     QC_TRY(load_sigmas(g, sigmas, n_sigmas, st));
     if (precision != g->pot_precision) {
         // the descriptor's FP64 table pointer depends on the precision
@@ -549,6 +686,15 @@ qc_status qc_ggd_labels(qc_graph g, int32_t sigma_index, uint32_t tie_mode, int3
         QC_HIP(launch_pointer_jump(g->d_desc, g->d_node_jobs, 1, sigma_index, 1, labels_out, 0,
                                    g->n, st));
     }
+    return QC_OK;
+}
+
+qc_status qc_get_potential64(qc_graph g, double *v64_out, void *stream)
+{
+    if (!g || !v64_out) return QC_E_INVAL;
+    if (!g->have_pot || g->pot_precision != QC_PREC_FP64ACC) return QC_E_STATE;
+    QC_HIP(hipMemcpyAsync(v64_out, g->d_v64, (size_t)g->n_sigmas * g->n * sizeof(double),
+                          hipMemcpyDeviceToDevice, as_stream(stream)));
     return QC_OK;
 }
 
@@ -589,7 +735,33 @@ qc_status qc_graph_sync(qc_graph g, void *stream)
     QC_HIP(hipStreamSynchronize(st));
     int32_t status[2] = {0, 0};
     QC_HIP(hipMemcpy(status, g->d_status, sizeof status, hipMemcpyDeviceToHost));
-    if (status[1]) return QC_E_OVERFLOW;
+    if (status[1] & 1) return QC_E_OVERFLOW;
+    if (status[1] & 2) return QC_E_DEVICE;
+    return QC_OK;
+}
+
+qc_status qc_cluster(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *sigmas, int32_t n_sigmas, uint32_t tie_mode, int8_t *dist_out,
+                     float *psi_out, float *v_out, int32_t *labels_out, void *stream)
+{
+    if (!labels_out || tie_mode > QC_TIE_MERGE) return QC_E_INVAL;
+    if (dist_out && ((uintptr_t)dist_out) % 16) return QC_E_INVAL;
+    QC_TRY(validate_sigmas(sigmas, n_sigmas));
+    hipStream_t st = as_stream(stream);
+    qc_graph g = nullptr;
+    QC_TRY(create_graph(n, nnz, row_ptr, col_idx, 0, st, nullptr, 0, &g));
+    const qc_status s =
+        cluster_on_handle(g, sigmas, n_sigmas, tie_mode, dist_out, psi_out, v_out, labels_out, st);
+    (void)hipStreamSynchronize(st);
+    destroy(g, false);
+    return s;
+}
+
+qc_status qc_debug_alloc_fault(int64_t fail_at, int64_t *live_out)
+{
+    if (fail_at < 0) return QC_E_INVAL;
+    g_fault_countdown.store(fail_at, std::memory_order_relaxed);
+    if (live_out) *live_out = g_live_allocs.load(std::memory_order_relaxed);
     return QC_OK;
 }
 

@@ -36,6 +36,7 @@ struct qc_batch_s {
 
     GraphDev *d_descs = nullptr;
     unsigned long long *d_recheck = nullptr;
+    unsigned long long *d_visits = nullptr;   // [2] the last run's BFS edge visits, bytes gathered
     std::vector<BfsGroup> bfs;
     std::vector<KGroup> hist;
     std::vector<KGroup> pot;
@@ -60,6 +61,7 @@ void free_batch(qc_batch b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     dfree(b->d_descs);
     dfree(b->d_recheck);
+    dfree(b->d_visits);
     for (auto &g : b->bfs) dfree(g.d_jobs);
     for (auto &g : b->hist) dfree(g.d_jobs);
     for (auto &g : b->pot) dfree(g.d_jobs);
@@ -218,6 +220,7 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
     const int S = (int)b->sigmas.size();
     const int64_t total = b->offsets.back();
     QC_HIP(launch_fill_u64(b->d_recheck, 1, st));
+    QC_HIP(launch_fill_u64(b->d_visits, 2, st));
     for (auto &g : b->bfs) {
         StageTimer t(QC_STAGE_BFS, st);
         QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, st));
@@ -275,18 +278,21 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     b->offsets.assign(n_graphs + 1, 0);
     for (int i = 0; i < n_graphs; ++i) {
         qc_graph g = graphs[i];
-        if (!g->d_dist) {
+        // the batch writes distances only into a matrix the handle owns,
+        // never into a caller's buffer an earlier qc_distances was given
+        if (!g->d_dist_owned) {
             qc_status s = galloc(g, &g->d_dist_owned, (size_t)g->n * g->n + 16);
             if (s) return fail(s);
-            g->d_dist = g->d_dist_owned;
         }
+        g->d_dist = g->d_dist_owned;
         if (g->dmax < 0) {
             qc_status s = run_distances(g, st);
             if (s) return fail(s);
         }
+        // the graph's potentials are the batch's once a run has computed them
+        g->have_pot = false;
         qc_status s = load_sigmas(g, sigmas, n_sigmas, st);
         if (s) return fail(s);
-        g->have_pot = true;
         g->pot_precision = (uint32_t)b->precision;
         b->offsets[i + 1] = b->offsets[i] + g->n;
     }
@@ -299,11 +305,14 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     }
 
     qc_status s;
-    if ((s = dalloc(&b->d_recheck, 1)) || (s = dalloc(&b->d_descs, (size_t)n_graphs))) return fail(s);
+    if ((s = dalloc(&b->d_recheck, 1)) || (s = dalloc(&b->d_visits, 2)) ||
+        (s = dalloc(&b->d_descs, (size_t)n_graphs)))
+        return fail(s);
     std::vector<GraphDev> descs(n_graphs);
     for (int i = 0; i < n_graphs; ++i) {
         descs[i] = graphs[i]->desc();
         descs[i].recheck = b->d_recheck;
+        descs[i].visits = b->d_visits;
     }
     if ((s = upload(b->d_descs, descs))) return fail(s);
 
@@ -389,7 +398,11 @@ qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels
     if (!b || !labels_out) return QC_E_INVAL;
     hipStream_t st = as_stream(stream);
     const bool use_graph = (b->flags & QC_BATCH_HIPGRAPH) && st != nullptr;
-    if (!use_graph) return enqueue(b, psi_out, v_out, labels_out, st);
+    if (!use_graph) {
+        QC_TRY(enqueue(b, psi_out, v_out, labels_out, st));
+        for (qc_graph g : b->graphs) g->have_pot = true;
+        return QC_OK;
+    }
 
     const bool same = b->exec && b->cap_psi == psi_out && b->cap_v == v_out &&
                       b->cap_labels == labels_out && b->cap_stream == st;
@@ -410,6 +423,7 @@ qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels
         b->cap_stream = st;
     }
     QC_HIP(hipGraphLaunch(b->exec, st));
+    for (qc_graph g : b->graphs) g->have_pot = true;
     return QC_OK;
 }
 
@@ -420,6 +434,17 @@ qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out)
     QC_HIP(hipDeviceSynchronize());
     QC_HIP(hipMemcpy(&c, b->d_recheck, sizeof c, hipMemcpyDeviceToHost));
     *count_out = (int64_t)c;
+    return QC_OK;
+}
+
+qc_status qc_batch_search_stats(qc_batch b, int64_t *edge_visits, int64_t *lds_bytes)
+{
+    if (!b) return QC_E_INVAL;
+    unsigned long long c[2] = {0, 0};
+    QC_HIP(hipDeviceSynchronize());
+    QC_HIP(hipMemcpy(c, b->d_visits, sizeof c, hipMemcpyDeviceToHost));
+    if (edge_visits) *edge_visits = (int64_t)c[0];
+    if (lds_bytes) *lds_bytes = (int64_t)c[1];
     return QC_OK;
 }
 

@@ -248,6 +248,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
 
     int last = 0;
     int overflow = 0;
+    int pulled = 0;   // levels pulled over the whole edge list
     for (int level = 1;; ++level) {
         if (level == 1) {
             // A'. level 1 is pushed from the sources along their CSR rows
@@ -255,6 +256,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             //     the whole edge list.
             push_level1<BW, kT, WEIGHTED>(G, srcs, nb, nxt);
         } else {
+            ++pulled;
             // A. pull over every edge, 8 consecutive edges (two quads) per
             //    thread, the next 8 in flight. Loads past the end read no-op
             //    edges, so they need no bounds check.
@@ -390,6 +392,20 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     if (tid == 0) {
         atomicMax(&G.status[0], last);
         if (overflow) atomicOr(&G.status[1], overflow);
+    }
+    if (G.visits && tid < 64) {
+        // the work of this batch: every edge entry per pulled level, and the
+        // sources' row entries the first level pushed
+        const int32_t *__restrict__ rp = WEIGHTED ? G.bfs_row_ptr : G.row_ptr;
+        const uint32_t deg = (tid < nb) ? (uint32_t)(rp[srcs[tid] + 1] - rp[srcs[tid]]) : 0u;
+        const uint32_t pushed = wave_sum(deg);
+        if (tid == 0) {
+            const unsigned long long v =
+                (unsigned long long)pulled * (unsigned long long)(WEIGHTED ? G.nnz_bfs : G.nnz) +
+                pushed;
+            atomicAdd(&G.visits[0], v);
+            atomicAdd(&G.visits[1], v * (unsigned long long)sizeof(T));
+        }
     }
 }
 

@@ -129,24 +129,46 @@ qc_status from_hip(hipError_t e);
     } while (0)
 #define QC_HIP(expr) QC_TRY(from_hip(expr))
 
-template <class T>
-qc_status dalloc(T **p, size_t count)
+// Out-of-memory injection (qc_debug_alloc_fault): true when the device
+// allocation being attempted is the one the armed countdown selects. Every
+// device allocation path of the library asks first (the device allocator
+// and the carving of arena regions).
+bool alloc_fault_now();
+// Device allocator blocks the library holds (hipMalloc'd, not yet freed).
+void note_device_alloc(int delta);
+
+// The library's device allocator: every hipMalloc of the library goes here.
+inline qc_status device_malloc(void **p, size_t bytes)
 {
     *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (alloc_fault_now()) return QC_E_OOM;
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
         return e == hipErrorOutOfMemory ? QC_E_OOM : QC_E_DEVICE;
     }
+    note_device_alloc(1);
     return QC_OK;
+}
+
+inline void device_free(void *p)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    note_device_alloc(-1);
+}
+
+template <class T>
+qc_status dalloc(T **p, size_t count)
+{
+    return device_malloc((void **)p, (count ? count : 1) * sizeof(T));
 }
 
 template <class T>
 void dfree(T *&p)
 {
-    if (p) (void)hipFree((void *)p);
+    device_free((void *)p);
     p = nullptr;
 }
 
@@ -156,7 +178,7 @@ qc_status galloc(qc_graph g, T **p, size_t count)
 {
     if (!g->bump_base) return dalloc(p, count);
     const size_t bytes = (((count ? count : 1) * sizeof(T)) + 255) & ~(size_t)255;
-    if (g->bump_off + bytes > g->bump_size) {
+    if (alloc_fault_now() || g->bump_off + bytes > g->bump_size) {
         *p = nullptr;
         return QC_E_OOM;
     }
@@ -197,6 +219,18 @@ qc_status run_distances(qc_graph g, hipStream_t st);
 qc_status ensure_sigma_buffers(qc_graph g, int S);
 // Load the weight tables of a sigma list into g (no-op if already loaded).
 qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStream_t st);
+// Device bytes a handle of n nodes, nnz CSR entries and n_sigmas widths
+// carves from an arena region for the whole path (histograms sized for the
+// largest row length); with_dist: including the n*n distance matrix,
+// with_labels: including an [n_sigmas][n] label buffer. -1 out of range.
+int64_t handle_footprint(int32_t n, int64_t nnz, int32_t n_sigmas, bool with_dist,
+                         bool with_labels);
+// Algorithm 4 on a created handle: distances (into dist_out, or the handle's
+// own matrix when null), FP64-accumulated potentials, labels of every width
+// into labels_out [n_sigmas][n]; waits for st and returns any latched error.
+qc_status cluster_on_handle(qc_graph g, const double *sigmas, int32_t n_sigmas,
+                            uint32_t tie_mode, int8_t *dist_out, float *psi_out, float *v_out,
+                            int32_t *labels_out, hipStream_t st);
 // Release a handle; `sync` waits for the whole device first (handles that
 // live in an arena region are released after their own stream has drained).
 void destroy(qc_graph g, bool sync = true);

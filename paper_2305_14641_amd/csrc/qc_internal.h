@@ -79,6 +79,11 @@ struct GraphDev {
     int32_t *parent;          // [n_sigmas][n] descent parents, node order[t]'s at t
     int32_t *status;          // [2]: 0 largest finite distance, 1 overflow flag
     unsigned long long *recheck;  // count of FP64 re-decided nodes
+    // Search work counted by the BFS, or null: [0] edge visits (every edge
+    // entry of every pulled level, plus the row entries the first level
+    // pushes from the sources), [1] bytes of the bit fields those visits
+    // gathered from LDS.
+    unsigned long long *visits;
 };
 
 // graph index, first source, and the number of (source, node) pairs the

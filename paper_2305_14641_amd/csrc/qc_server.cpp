@@ -1,7 +1,9 @@
-// Serving form (include/qc_server.h): FIFO admission by device-memory
-// footprint into a fixed arena, `max_slots` worker threads each driving its
-// own HIP stream, so requests that arrive while others run are admitted as
-// soon as a slot and memory are free and their GPU work overlaps.
+// Serving form (include/qc_server.h): admission by device-memory footprint
+// into a fixed arena (oldest first, with a bounded bypass of a request that
+// does not fit), `max_slots` worker threads each driving its own HIP stream,
+// so requests that arrive while others run are admitted as soon as a slot and
+// memory are free and their GPU work overlaps. Queued requests can time out
+// or be cancelled; a failed request releases its region and slot.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -80,7 +82,8 @@ struct Request {
     int64_t footprint = 0;
     size_t offset = 0;
     qc_status status = QC_OK;
-    bool done = false;
+    bool admitted = false, done = false;
+    int32_t bypassed = 0;             // times younger requests were admitted before it
     int32_t dmax = -1, slot = -1;
     double t_submit = 0, t_admit = 0, t_done = 0;
     std::vector<int32_t> labels;
@@ -164,6 +167,47 @@ qc_status run_request(qc_server s, Request *r, int slot, void **stage, size_t *s
     return QC_OK;
 }
 
+// Complete the queued requests whose admission deadline has passed (the
+// caller holds s->mu).
+void expire_locked(qc_server s, double now)
+{
+    if (s->opts.queue_timeout_s <= 0) return;
+    bool any = false;
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+        Request *r = *it;
+        if (now - r->t_submit >= s->opts.queue_timeout_s) {
+            r->status = QC_E_TIMEOUT;
+            r->t_done = now;
+            r->done = true;
+            it = s->queue.erase(it);
+            any = true;
+        } else {
+            ++it;
+        }
+    }
+    if (any) s->cv_done.notify_all();
+}
+
+// The next request to admit, its arena region carved (the caller holds
+// s->mu): the oldest queued request that fits, where a request that does not
+// fit may be passed by younger ones at most max_bypass times.
+Request *admit_locked(qc_server s)
+{
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+        Request *r = *it;
+        size_t off = 0;
+        if (s->arena.alloc((size_t)r->footprint, &off)) {
+            r->offset = off;
+            r->admitted = true;
+            for (auto jt = s->queue.begin(); jt != it; ++jt) (*jt)->bypassed += 1;
+            s->queue.erase(it);
+            return r;
+        }
+        if (r->bypassed >= s->opts.max_bypass) break;   // nothing may pass it now
+    }
+    return nullptr;
+}
+
 void worker(qc_server s, int slot)
 {
     (void)hipSetDevice(s->device);
@@ -174,19 +218,20 @@ void worker(qc_server s, int slot)
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
+                expire_locked(s, mono_now());
                 if (!s->queue.empty()) {
-                    Request *head = s->queue.front();
-                    size_t off = 0;
-                    if (s->arena.alloc((size_t)head->footprint, &off)) {
-                        head->offset = off;
-                        s->queue.pop_front();
-                        r = head;
-                        break;
-                    }
+                    if ((r = admit_locked(s))) break;
                 } else if (s->stop) {
                     break;
                 }
-                s->cv_work.wait(lk);
+                if (s->opts.queue_timeout_s > 0 && !s->queue.empty()) {
+                    // wake at the oldest queued request's deadline at the latest
+                    const double left =
+                        s->queue.front()->t_submit + s->opts.queue_timeout_s - mono_now();
+                    s->cv_work.wait_for(lk, std::chrono::duration<double>(left > 0 ? left : 0.0));
+                } else {
+                    s->cv_work.wait(lk);
+                }
             }
             if (!r) break;
             r->t_admit = mono_now();
@@ -218,69 +263,34 @@ extern "C" {
 
 int64_t qc_request_footprint(int32_t n, int64_t nnz, int32_t n_sigmas)
 {
-    if (n < 1 || n > kMaxNodes || nnz < 0 || nnz >= kMaxEdges || n_sigmas < 1 ||
-        n_sigmas > 1024)
-        return -1;
-    const int64_t N = n, S = n_sigmas, K = 128;  // histogram bins: the largest row length
-    const int64_t quads = (nnz + 3) / 4 * 4 + 4;
-    int64_t b = 0;
-    auto add = [&](int64_t bytes) { b += (int64_t)align256((size_t)(bytes > 0 ? bytes : 1)); };
-    add(4 * (N + 1));                 // row_ptr
-    add(4 * nnz);                     // col
-    add(4 * N);                       // descent thread order
-    add(4 * N + 4 * (N / 64 + 2));    // sliced neighbour lists: degrees, slice offsets
-    {
-        // and entries: within a window of degree-sorted nodes the padding
-        // adds up to at most 63 times the window's largest degree
-        const int64_t windows = (N + kOrderWindow - 1) / kOrderWindow;
-        add(4 * (nnz + 63 * std::min<int64_t>(nnz, windows * (N - 1)) + 64 * kGgdPad));
-    }
-    add(4 * N);                       // BFS source order
-    add(4 * quads);                   // packed edges
-    add(8);                           // status
-    add(8);                           // recheck counter
-    add((int64_t)sizeof(GraphDev));   // descriptor
-    add(16 * ((N + kNodesPerJob - 1) / kNodesPerJob));  // node jobs
-    add(8 * N);                       // BFS jobs (first plan, <= one job per node)
-    add(8 * N);                       // BFS jobs (plan after dmax is known)
-    add(N * N + 16);                  // distance matrix
-    add(4 * N * K);                   // histograms
-    add(16 * N);                      // histogram jobs
-    add(4 * N * S);                   // psi
-    add(4 * v_floats(n, n_sigmas));   // V (sigma groups rounded up)
-    add(8 * N * S);                   // FP64 V
-    add(4 * N * S);                   // parents
-    add(8 * S * K);                   // w64
-    add(8 * S * K);                   // u64
-    add(8 * S);                       // 1/a
-    add(16 * S * K);                  // FP32 split weights
-    add(4 * S * K);                   // BF16 weights
-    add(4 * N * S);                   // labels
-    return b;
+    return handle_footprint(n, nnz, n_sigmas, true, true);
 }
 
 qc_status qc_server_create(const qc_server_opts *opts, qc_server *out)
 {
     if (!opts || !out) return QC_E_INVAL;
     if (opts->max_slots < 1 || opts->max_slots > 64 || opts->hbm_budget_bytes <= 0 ||
-        opts->tie_mode > QC_TIE_MERGE)
+        opts->tie_mode > QC_TIE_MERGE || !(opts->queue_timeout_s >= 0) ||
+        opts->queue_timeout_s > 1e9 || opts->max_bypass < 0 || opts->max_bypass > 1000000)
         return QC_E_INVAL;
     int dev = 0;
     QC_TRY(check_device(&dev));
     qc_server s = new qc_server_s();
     s->opts = *opts;
     s->device = dev;
-    if (hipMalloc((void **)&s->d_arena, (size_t)opts->hbm_budget_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        delete s;
-        return QC_E_OOM;
+    {
+        const qc_status a = device_malloc((void **)&s->d_arena, (size_t)opts->hbm_budget_bytes);
+        if (a != QC_OK) {
+            delete s;
+            return a;
+        }
     }
     s->arena.reset((size_t)opts->hbm_budget_bytes);
     for (int k = 0; k < opts->max_slots; ++k) {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             for (auto x : s->streams) (void)hipStreamDestroy(x);
-            (void)hipFree(s->d_arena);
+            device_free(s->d_arena);
             delete s;
             return QC_E_DEVICE;
         }
@@ -330,6 +340,7 @@ qc_status qc_server_poll(qc_server s, int64_t id, int32_t *done_out)
 {
     if (!s || !done_out) return QC_E_INVAL;
     std::lock_guard<std::mutex> lk(s->mu);
+    expire_locked(s, mono_now());
     auto it = s->all.find(id);
     if (it == s->all.end()) return QC_E_INVAL;
     *done_out = it->second->done ? 1 : 0;
@@ -346,7 +357,16 @@ qc_status qc_server_wait(qc_server s, int64_t id, int32_t *labels_out, float *ps
         auto it = s->all.find(id);
         if (it == s->all.end()) return QC_E_INVAL;
         r = it->second;
-        s->cv_done.wait(lk, [&] { return r->done; });
+        while (!r->done) {
+            if (s->opts.queue_timeout_s > 0 && !r->admitted) {
+                // every worker may be busy: expire the request here at its deadline
+                const double left = r->t_submit + s->opts.queue_timeout_s - mono_now();
+                s->cv_done.wait_for(lk, std::chrono::duration<double>(left > 0 ? left : 0.0));
+                expire_locked(s, mono_now());
+            } else {
+                s->cv_done.wait(lk);
+            }
+        }
         s->all.erase(it);
     }
     const size_t cells = r->sigmas.size() * (size_t)r->n;
@@ -370,6 +390,31 @@ qc_status qc_server_wait(qc_server s, int64_t id, int32_t *labels_out, float *ps
     return st;
 }
 
+qc_status qc_server_cancel(qc_server s, int64_t id)
+{
+    if (!s) return QC_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->all.find(id);
+        if (it == s->all.end()) return QC_E_INVAL;
+        Request *r = it->second;
+        if (r->done) return QC_E_STATE;
+        if (r->admitted) return QC_E_BUSY;
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q) {
+            if (*q == r) {
+                s->queue.erase(q);
+                break;
+            }
+        }
+        r->status = QC_E_CANCELLED;
+        r->t_done = mono_now();
+        r->done = true;
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();   // a request it blocked may fit now
+    return QC_OK;
+}
+
 qc_status qc_server_stats(qc_server s, int64_t *peak_bytes_out, int32_t *peak_requests_out)
 {
     if (!s) return QC_E_INVAL;
@@ -389,7 +434,7 @@ qc_status qc_server_destroy(qc_server s)
     s->cv_work.notify_all();
     for (auto &t : s->workers) t.join();
     for (auto st : s->streams) (void)hipStreamDestroy(st);
-    (void)hipFree(s->d_arena);
+    device_free(s->d_arena);
     for (auto &kv : s->all) delete kv.second;
     delete s;
     return QC_OK;

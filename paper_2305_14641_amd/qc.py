@@ -23,6 +23,8 @@ QC_E_DEVICE = 4
 QC_E_OVERFLOW = 5
 QC_E_STATE = 6
 QC_E_BUSY = 7
+QC_E_TIMEOUT = 8
+QC_E_CANCELLED = 9
 
 TIE_STRICT = 0
 TIE_MERGE = 1
@@ -40,9 +42,10 @@ EXPORTED = [
     "qc_graph_destroy",
     "qc_graph_info", "qc_graph_bfs_plan", "qc_distances", "qc_get_histograms", "qc_potential",
     "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync", "qc_timing_enable",
-    "qc_timing_read", "qc_potential_dense",
+    "qc_timing_read", "qc_potential_dense", "qc_debug_alloc_fault", "qc_get_potential64",
+    "qc_cluster",
     "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
-    "qc_batch_destroy",
+    "qc_batch_search_stats", "qc_batch_destroy",
 ]
 
 BATCH_HIPGRAPH = 1
@@ -50,12 +53,13 @@ BATCH_FP32C = 2
 BATCH_AUTOTUNE = 4
 
 EXPORTED += ["qc_request_footprint", "qc_server_create", "qc_server_submit", "qc_server_poll",
-             "qc_server_wait", "qc_server_stats", "qc_server_destroy"]
+             "qc_server_wait", "qc_server_cancel", "qc_server_stats", "qc_server_destroy"]
 
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
-                ("tie_mode", ctypes.c_uint32), ("want_potentials", ctypes.c_int32)]
+                ("tie_mode", ctypes.c_uint32), ("want_potentials", ctypes.c_int32),
+                ("queue_timeout_s", ctypes.c_double), ("max_bypass", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -113,10 +117,14 @@ def lib():
         L.qc_timing_enable.argtypes = [I32]
         L.qc_timing_read.argtypes = [I32, P, P]
         L.qc_potential_dense.argtypes = [P, I64, I64, I64, P, I32, P, P, P]
+        L.qc_debug_alloc_fault.argtypes = [I64, P]
+        L.qc_get_potential64.argtypes = [P, P, P]
+        L.qc_cluster.argtypes = [I32, I64, P, P, P, I32, U32, P, P, P, P, P]
         L.qc_batch_create.argtypes = [P, I32, P, I32, U32, U32, P, P]
         L.qc_batch_node_offsets.argtypes = [P, P]
         L.qc_batch_run.argtypes = [P, P, P, P, P]
         L.qc_batch_recheck_count.argtypes = [P, P]
+        L.qc_batch_search_stats.argtypes = [P, P, P]
         L.qc_batch_destroy.argtypes = [P]
         L.qc_request_footprint.argtypes = [I32, I64, I32]
         L.qc_request_footprint.restype = I64
@@ -124,6 +132,7 @@ def lib():
         L.qc_server_submit.argtypes = [P, I32, I64, P, P, P, I32, P]
         L.qc_server_poll.argtypes = [P, I64, P]
         L.qc_server_wait.argtypes = [P, I64, P, P, P, P]
+        L.qc_server_cancel.argtypes = [P, I64]
         L.qc_server_stats.argtypes = [P, P, P]
         L.qc_server_destroy.argtypes = [P]
         for name in EXPORTED[1:]:
@@ -146,6 +155,14 @@ def device_count() -> int:
     c = ctypes.c_int32(0)
     _check(lib().qc_device_count(ctypes.byref(c)), "qc_device_count")
     return int(c.value)
+
+
+def debug_alloc_fault(fail_at: int) -> int:
+    """Make the fail_at-th device allocation from now on fail (0 disarms);
+    returns the number of device-allocator blocks the library holds."""
+    live = ctypes.c_int64(0)
+    _check(lib().qc_debug_alloc_fault(int(fail_at), ctypes.byref(live)), "qc_debug_alloc_fault")
+    return int(live.value)
 
 
 def timing_enable(on: bool = True):
@@ -213,6 +230,7 @@ class Graph:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().qc_graph_destroy(self._h)
             self._h = None
+        self._dist_ref = None
 
     def __del__(self):
         try:
@@ -247,6 +265,9 @@ class Graph:
         dmax = ctypes.c_int32(-1)
         _check(lib().qc_distances(self._h, _dptr(out), ctypes.byref(dmax), _stream_ptr(stream)),
                "qc_distances")
+        # the handle reads (and may rewrite) this buffer until the next
+        # distances() call or close(): keep the caller's tensor alive
+        self._dist_ref = out
         return int(dmax.value)
 
     def histograms(self, stream=None):
@@ -284,6 +305,15 @@ class Graph:
         _check(lib().qc_ggd_labels(self._h, int(sigma_index), int(tie_mode), _dptr(out),
                                    _stream_ptr(stream)), "qc_ggd_labels")
         return out
+
+    def potential64(self, stream=None):
+        """The resident canonical FP64 V [n_sigmas, n] of the last potential."""
+        import torch
+        S = 0 if self.sigmas is None else self.sigmas.shape[0]
+        out = torch.empty((max(S, 1), self.n), dtype=torch.float64, device="cuda")
+        _check(lib().qc_get_potential64(self._h, _dptr(out), _stream_ptr(stream)),
+               "qc_get_potential64")
+        return out[:S]
 
     def recheck_count(self) -> int:
         c = ctypes.c_int64(0)
@@ -340,6 +370,14 @@ class Batch:
         _check(lib().qc_batch_recheck_count(self._h, ctypes.byref(c)), "qc_batch_recheck_count")
         return int(c.value)
 
+    def search_stats(self) -> tuple:
+        """(edge visits, LDS bytes gathered) of the last run's searches."""
+        v = ctypes.c_int64(0)
+        b = ctypes.c_int64(0)
+        _check(lib().qc_batch_search_stats(self._h, ctypes.byref(v), ctypes.byref(b)),
+               "qc_batch_search_stats")
+        return int(v.value), int(b.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().qc_batch_destroy(self._h)
@@ -360,9 +398,9 @@ class Server:
     """Continuous-batching request loop (include/qc_server.h)."""
 
     def __init__(self, max_slots=4, hbm_budget_bytes=16 << 30, tie_mode=TIE_STRICT,
-                 want_potentials=False):
+                 want_potentials=False, queue_timeout_s=0.0, max_bypass=0):
         o = ServerOpts(int(max_slots), int(hbm_budget_bytes), int(tie_mode),
-                       1 if want_potentials else 0)
+                       1 if want_potentials else 0, float(queue_timeout_s), int(max_bypass))
         h = ctypes.c_void_p()
         _check(lib().qc_server_create(ctypes.byref(o), ctypes.byref(h)), "qc_server_create")
         self._h = h
@@ -401,6 +439,11 @@ class Server:
         _check(st, f"request {rid}")
         d = {k: getattr(info, k) for k, _ in RequestInfo._fields_}
         return lab, psi, v, d
+
+    def cancel(self, rid) -> int:
+        """Withdraw a queued request; returns the library status (QC_OK when
+        withdrawn, QC_E_BUSY when already running, QC_E_STATE when done)."""
+        return int(lib().qc_server_cancel(self._h, int(rid)))
 
     def stats(self) -> dict:
         b = ctypes.c_int64(0)
@@ -447,11 +490,30 @@ def potential_dense(dist, sigmas, n_cols=None, psi=None, v=None, stream=None):
     return psi, v
 
 
-def cluster(g, sigmas, tie_mode=TIE_STRICT, precision=PREC_FP64ACC, dist_out=None):
-    """Algorithm 4 for a list of sigmas on the GPU: returns (dmax, psi, V, labels)."""
+def _cluster_args(n, row_ptr, col, sigmas, dist, psi, v, labels):
     import torch
-    G = Graph.from_graph(g)
-    dmax = G.distances(dist_out)
-    psi, v = G.potential(sigmas, precision=precision)
-    labels = torch.stack([G.labels(s, tie_mode) for s in range(len(sigmas))])
-    return G, dmax, psi, v, labels
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).reshape(-1))
+    S = sig.shape[0]
+    if labels is None:
+        labels = torch.empty((S, n), dtype=torch.int32, device="cuda")
+    Graph._check_tensor(labels, (S, n), "int32")
+    if dist is not None:
+        Graph._check_tensor(dist, (n, n), "int8")
+    for t in (psi, v):
+        if t is not None:
+            Graph._check_tensor(t, (S, n), "float32")
+    return rp, c, sig, labels
+
+
+def cluster(n, row_ptr, col, sigmas, tie_mode=TIE_STRICT, dist=None, psi=None, v=None,
+            labels=None, stream=None):
+    """Algorithm 4 in one call (qc_cluster): labels [S, n] int32 on the GPU
+    (and the optional dist / psi / v outputs filled)."""
+    rp, c, sig, labels = _cluster_args(n, row_ptr, col, sigmas, dist, psi, v, labels)
+    _check(lib().qc_cluster(int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+                            c.ctypes.data_as(ctypes.c_void_p), sig.ctypes.data_as(ctypes.c_void_p),
+                            sig.shape[0], int(tie_mode), _dptr(dist), _dptr(psi), _dptr(v),
+                            _dptr(labels), _stream_ptr(stream)), "qc_cluster")
+    return labels

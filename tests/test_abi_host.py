@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for s in range(8):
+    for s in range(10):
         assert qc.status_str(s).startswith("QC_")
     assert "unknown" in qc.status_str(99)
 
@@ -209,3 +209,48 @@ def test_weighted_graph_validation_on_host():
     np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
     assert create_w(n, rp, cols, np.full(cols.shape[0], 126, dtype=np.uint8)) == qc.QC_E_INVAL
     assert create_w(n, rp, cols, np.full(cols.shape[0], 100, dtype=np.uint8)) == ok
+
+
+def test_cluster_arguments_checked_on_host():
+    """qc_cluster validates its arguments and the CSR before any device work."""
+    L = qc.lib()
+    g = gg.config1()
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    sig = np.array([1.0, 2.0])
+    P = ctypes.c_void_p
+
+    def call(n=g.n, rp_=rp, col_=col, sig_=sig, tie=0, dist=None, labels=P(64)):
+        return L.qc_cluster(n, col_.shape[0], rp_.ctypes.data_as(P), col_.ctypes.data_as(P),
+                            sig_.ctypes.data_as(P), sig_.shape[0], tie, dist, None, None,
+                            labels, None)
+
+    assert call(labels=None) == qc.QC_E_INVAL                 # labels are required
+    assert call(tie=2) == qc.QC_E_INVAL
+    assert call(dist=P(65)) == qc.QC_E_INVAL                  # distances not 16-byte aligned
+    assert call(sig_=np.array([1.0, 0.0])) == qc.QC_E_INVAL
+    bad = col.copy()
+    bad[0], bad[1] = bad[1], bad[0]                           # an unsorted row
+    if g.row_ptr[1] - g.row_ptr[0] >= 2:
+        assert call(col_=bad) == qc.QC_E_NOT_SYMMETRIC
+    if qc.device_count() == 0:
+        assert call() == qc.QC_E_DEVICE
+
+
+def test_hooks_and_new_entry_points_reject_bad_handles():
+    L = qc.lib()
+    live = ctypes.c_int64(-1)
+    assert L.qc_debug_alloc_fault(-1, None) == qc.QC_E_INVAL
+    assert L.qc_debug_alloc_fault(0, ctypes.byref(live)) == qc.QC_OK
+    assert live.value >= 0
+    assert L.qc_get_potential64(None, ctypes.c_void_p(64), None) == qc.QC_E_INVAL
+    assert L.qc_batch_search_stats(None, None, None) == qc.QC_E_INVAL
+    assert L.qc_server_cancel(None, 1) == qc.QC_E_INVAL
+
+
+@pytest.mark.parametrize("timeout,bypass", [(-1.0, 0), (float("nan"), 0), (0.0, -1),
+                                            (0.0, 2_000_000)])
+def test_server_options_checked_on_host(timeout, bypass):
+    o = qc.ServerOpts(2, 1 << 20, 0, 0, timeout, bypass)
+    h = ctypes.c_void_p()
+    assert qc.lib().qc_server_create(ctypes.byref(o), ctypes.byref(h)) == qc.QC_E_INVAL

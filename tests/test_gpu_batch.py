@@ -140,3 +140,34 @@ def test_batch_rejects_bad_arguments(setup):
         qc.Batch([G], [1.0, -2.0])
     with pytest.raises(qc.QCError):
         qc.Batch([G], sigmas, tie_mode=3)
+
+
+def test_batch_search_stats_count_the_searches_work(setup, monkeypatch):
+    """The search kernel's own count of its work: with the sources taken in
+    node order (batches of consecutive nodes), a batch pulls one level less
+    than its sources' largest eccentricity (level 1 is pushed from the
+    sources, and the search stops once every reachable pair is found), so
+    edge visits = sum over batches of max(0, max ecc - 1) x edge entries +
+    the edge entries pushed at level 1 (every node is a source once), and
+    every visit gathers one bit-field word (4 bytes, or 8 for batches of 64)."""
+    torch, qc, graphs, sigmas = setup
+    monkeypatch.setenv("QC_SOURCE_ORDER", "identity")
+    gs = [gg.config2(), gg.config1(), gg.path_graph(70)]
+    handles = [qc.Graph.from_graph(g) for g in gs]
+    b = qc.Batch(handles, sigmas[:2], hipgraph=True)
+    psi, v, lab = b.outputs()
+    for _ in range(2):
+        b.run(psi, v, lab)
+    visits, lds = b.search_stats()
+    want_visits = want_bytes = 0
+    for g, G in zip(gs, handles):
+        bw = G.bfs_plan()[0]
+        dist, _ = oracle.distances(g.n, g.row_ptr, g.col)
+        ecc = dist.max(axis=1).astype(np.int64)
+        pulled = sum(max(0, int(ecc[s0:s0 + bw].max()) - 1) for s0 in range(0, g.n, bw))
+        vis = pulled * g.nnz + g.nnz
+        want_visits += vis
+        want_bytes += vis * (8 if bw == 64 else 4)
+    assert visits == want_visits
+    assert lds == want_bytes
+    b.close()

@@ -132,6 +132,19 @@ def test_config3_full(torch_cuda):
         assert rel_err(res["v"][s][rows], v_p) <= RTOL
 
 
+def test_config3_fp32c(torch_cuda):
+    """Config 3 (N=19,717) with compensated FP32 potentials and the FP64
+    re-decision of near ties: psi/V within 1e-6 of the oracle's canonical FP64
+    values and labels bit-exact in both tie modes."""
+    from paper_2305_14641_amd import qc
+    g = gg.config3()
+    sig = [2.0, 0.5]
+    print(f"[gpu] config3 fp32c n={g.n}", flush=True)
+    res = run_gpu(torch_cuda, g, sig, precision=qc.PREC_FP32C, want_dist=False)
+    assert res["G"].recheck_count() >= 0
+    check_against_oracle(g, sig, res, pairsum=False)
+
+
 @pytest.mark.parametrize("n,deg,seed", [
     (3000, 5.0, 21),     # batch width 64
     (9000, 4.0, 22),     # 32, then 64 (two fields, 1024 threads, 18 words) once dmax is known
