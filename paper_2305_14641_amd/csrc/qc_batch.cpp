@@ -346,8 +346,10 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         grp.planes = std::get<2>(kv.first);
         grp.shape = std::get<3>(kv.first);
         grp.n_jobs = (int)jobs.size();
-        if ((s = upload_jobs(&grp.d_jobs, jobs))) return fail(s);
+        // the group joins the batch before its table is allocated, so that a
+        // failure later in the set-up frees the table with the batch
         b->bfs.push_back(grp);
+        if ((s = upload_jobs(&b->bfs.back().d_jobs, jobs))) return fail(s);
     }
     // Histogram and potential jobs grouped by bin count.
     std::map<int, std::vector<int>> by_k;
@@ -364,9 +366,10 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         h.K = p.K = K;
         h.n_jobs = (int)hj.size();
         p.n_jobs = (int)pj.size();
-        if ((s = upload_jobs(&h.d_jobs, hj)) || (s = upload_jobs(&p.d_jobs, pj))) return fail(s);
         b->hist.push_back(h);
         b->pot.push_back(p);
+        if ((s = upload_jobs(&b->hist.back().d_jobs, hj)) || (s = upload_jobs(&b->pot.back().d_jobs, pj)))
+            return fail(s);
     }
     std::vector<qc_graph> gv(graphs, graphs + n_graphs);
     std::vector<NodeJob> gj = xcd_pinned_node_jobs(gv), jj;
