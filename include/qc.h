@@ -50,7 +50,8 @@ enum {
     QC_E_STATE = 6,         /* call order violated (e.g. labels before potential) */
     QC_E_BUSY = 7,          /* serving: request does not fit the memory budget, or is already running */
     QC_E_TIMEOUT = 8,       /* serving: request not admitted before its queue deadline */
-    QC_E_CANCELLED = 9      /* serving: request withdrawn by qc_server_cancel */
+    QC_E_CANCELLED = 9,     /* serving: request withdrawn by qc_server_cancel */
+    QC_E_TOO_LARGE = 10     /* qc_cluster_noalloc: the problem exceeds its fixed device scratch */
 };
 
 /* Tie rules of the descent (Algorithm 2 and the prose after Algorithm 4).
@@ -268,6 +269,35 @@ qc_status qc_cluster(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
                      float *psi_out, float *v_out, int32_t *labels_out, void *stream);
 
 /* Number of node decisions the last qc_ggd_labels call (or batch run)
+/*
+ * qc_cluster without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, outputs and errors as qc_cluster; the caller
+ * still provides the output buffers. Every buffer the call needs besides
+ * them (CSR, packed edges, histograms, resident potentials, parents, weight
+ * tables, job tables, status words, and the distance matrix when dist_out is
+ * NULL) is carved from one fixed array of QC_NOALLOC_SCRATCH_BYTES of device
+ * memory, a static device symbol of the library: each device the call runs
+ * on holds its own copy until the process ends. The call never calls
+ * hipMalloc or hipFree, and no stage timing is recorded for it.
+ *   Size limit: the bytes it needs (about 4(n+1) + 4 nnz for the CSR, a
+ *   sliced copy of the neighbour lists, 4 n K with K = 128 for histograms,
+ *   20 n S for potentials and parents, plus n*n when dist_out is NULL) must
+ *   not exceed QC_NOALLOC_SCRATCH_BYTES, else QC_E_TOO_LARGE before any
+ *   device work (e.g. n = 19,717 with 88,726 entries and one width fits only
+ *   with a caller's dist_out).
+ *   Sharing: every call on one device uses that device's array, which keeps
+ *   the last call's contents (the call initialises whatever it reads). Calls
+ *   in one process on one device are serialised by a host lock, and the call
+ *   waits for `stream` before it returns, so the next call finds the array
+ *   free; work the caller enqueues on other streams never touches it.
+ */
+#define QC_NOALLOC_SCRATCH_BYTES (64ll * 1024 * 1024)
+qc_status qc_cluster_noalloc(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, const double *sigmas, int32_t n_sigmas,
+                             uint32_t tie_mode, int8_t *dist_out, float *psi_out, float *v_out,
+                             int32_t *labels_out, void *stream);
+
  * re-decided in FP64 (waits for the stream). */
 qc_status qc_last_recheck_count(qc_graph g, int64_t *count_out);
 

@@ -423,6 +423,7 @@ const char *qc_status_str(qc_status s)
     case QC_E_TIMEOUT: return "QC_E_TIMEOUT: request not admitted before its queue deadline";
     case QC_E_CANCELLED: return "QC_E_CANCELLED: request withdrawn before it ran";
     default: return "unknown qc_status";
+    case QC_E_TOO_LARGE: return "QC_E_TOO_LARGE: problem exceeds the fixed scratch of qc_cluster_noalloc";
     }
 }
 

@@ -189,6 +189,15 @@ class StageTimer {
 // [0, n_rows) of `dist` (row stride `ld` floats), every width of `sigmas`
 // (host); writes psi and V as FP64 [n_sigmas][n_rows].
 hipError_t launch_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64_t ld,
+// While alive, the calling thread's stage timers record nothing (and create
+// no HIP events).
+class StageTimingOff {
+  public:
+    StageTimingOff();
+    ~StageTimingOff();
+  private:
+    bool prev_;
+};
                         const double *sigmas, int n_sigmas, double *psi, double *v,
                         hipStream_t stream);
 

@@ -16,6 +16,7 @@ struct Record {
 
 std::mutex g_mu;
 bool g_on = false;
+thread_local bool t_off = false;   // this thread's timers are switched off
 std::vector<Record> g_records;
 std::vector<hipEvent_t> g_pool;
 
@@ -54,6 +55,7 @@ namespace qc {
 
 StageTimer::StageTimer(int stage, hipStream_t stream) : stage_(stage), stream_(stream)
 {
+    if (t_off) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on || capturing(stream)) return;
     hipEvent_t a = take_event(), b = take_event();
@@ -70,6 +72,9 @@ StageTimer::~StageTimer()
     if (hipEventRecord((hipEvent_t)stop_, stream_) == hipSuccess)
         g_records.push_back(Record{stage_, (hipEvent_t)start_, (hipEvent_t)stop_});
 }
+
+StageTimingOff::StageTimingOff() : prev_(t_off) { t_off = true; }
+StageTimingOff::~StageTimingOff() { t_off = prev_; }
 
 }  // namespace qc
 

@@ -25,6 +25,10 @@ QC_E_STATE = 6
 QC_E_BUSY = 7
 QC_E_TIMEOUT = 8
 QC_E_CANCELLED = 9
+QC_E_TOO_LARGE = 10
+
+# Device scratch of qc_cluster_noalloc (QC_NOALLOC_SCRATCH_BYTES in qc.h).
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 TIE_STRICT = 0
 TIE_MERGE = 1
@@ -43,7 +47,7 @@ EXPORTED = [
     "qc_graph_info", "qc_graph_bfs_plan", "qc_distances", "qc_get_histograms", "qc_potential",
     "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync", "qc_timing_enable",
     "qc_timing_read", "qc_potential_dense", "qc_debug_alloc_fault", "qc_get_potential64",
-    "qc_cluster",
+    "qc_cluster", "qc_cluster_noalloc",
     "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
     "qc_batch_search_stats", "qc_batch_destroy",
 ]
@@ -120,6 +124,7 @@ def lib():
         L.qc_debug_alloc_fault.argtypes = [I64, P]
         L.qc_get_potential64.argtypes = [P, P, P]
         L.qc_cluster.argtypes = [I32, I64, P, P, P, I32, U32, P, P, P, P, P]
+        L.qc_cluster_noalloc.argtypes = [I32, I64, P, P, P, I32, U32, P, P, P, P, P]
         L.qc_batch_create.argtypes = [P, I32, P, I32, U32, U32, P, P]
         L.qc_batch_node_offsets.argtypes = [P, P]
         L.qc_batch_run.argtypes = [P, P, P, P, P]
@@ -516,4 +521,19 @@ def cluster(n, row_ptr, col, sigmas, tie_mode=TIE_STRICT, dist=None, psi=None, v
                             c.ctypes.data_as(ctypes.c_void_p), sig.ctypes.data_as(ctypes.c_void_p),
                             sig.shape[0], int(tie_mode), _dptr(dist), _dptr(psi), _dptr(v),
                             _dptr(labels), _stream_ptr(stream)), "qc_cluster")
+    return labels
+
+
+def cluster_noalloc(n, row_ptr, col, sigmas, tie_mode=TIE_STRICT, dist=None, psi=None, v=None,
+                    labels=None, stream=None):
+    """qc_cluster_noalloc: as cluster(), with every device buffer besides the
+    outputs carved from the library's fixed device scratch (no allocation;
+    QC_E_TOO_LARGE when the problem does not fit it). Pass `labels` (and any
+    other output) preallocated to keep the call free of allocations."""
+    rp, c, sig, labels = _cluster_args(n, row_ptr, col, sigmas, dist, psi, v, labels)
+    _check(lib().qc_cluster_noalloc(int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+                                    c.ctypes.data_as(ctypes.c_void_p),
+                                    sig.ctypes.data_as(ctypes.c_void_p), sig.shape[0],
+                                    int(tie_mode), _dptr(dist), _dptr(psi), _dptr(v),
+                                    _dptr(labels), _stream_ptr(stream)), "qc_cluster_noalloc")
     return labels
