@@ -498,6 +498,9 @@ def main():
     psi, v, lab = batch.outputs()
     pair_terms = float(sum(float(g.n) ** 2 for g in graphs)) * S
     log(f"planned batch: total nodes {batch.total}, pair-terms/step {pair_terms:.3e}")
+    from collections import Counter
+    log("BFS plans (batch width, words, planes, shape): "
+        + ", ".join(f"{k}x{c}" for k, c in sorted(Counter(tuned).items())))
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20

@@ -137,7 +137,8 @@ qc_status qc_graph_destroy(qc_graph g);
  * are computed in batches of `batch` sources): batch width, 32-bit words per
  * thread and bit-field, distance bit-planes, workgroup shape (0: three
  * fields x 1024 threads, 1: two fields x 512 threads, 2: two fields x 1024
- * threads). Any output pointer may be NULL. Host only. */
+ * threads, 3: two fields x 1024 threads with the third in registers). Any
+ * output pointer may be NULL. Host only. */
 qc_status qc_graph_bfs_plan(qc_graph g, int32_t *batch, int32_t *words, int32_t *planes,
                             int32_t *shape);
 
@@ -268,7 +269,6 @@ qc_status qc_cluster(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
                      const double *sigmas, int32_t n_sigmas, uint32_t tie_mode, int8_t *dist_out,
                      float *psi_out, float *v_out, int32_t *labels_out, void *stream);
 
-/* Number of node decisions the last qc_ggd_labels call (or batch run)
 /*
  * qc_cluster without any device allocation, for callers that cannot allocate
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -298,6 +298,7 @@ qc_status qc_cluster_noalloc(int32_t n, int64_t nnz, const int32_t *row_ptr,
                              uint32_t tie_mode, int8_t *dist_out, float *psi_out, float *v_out,
                              int32_t *labels_out, void *stream);
 
+/* Number of node decisions the last qc_ggd_labels call (or batch run)
  * re-decided in FP64 (waits for the stream). */
 qc_status qc_last_recheck_count(qc_graph g, int64_t *count_out);
 

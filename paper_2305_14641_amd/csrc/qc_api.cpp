@@ -185,7 +185,8 @@ qc_status run_distances(qc_graph g, hipStream_t st)
         QC_HIP(hipStreamSynchronize(st));
         if (status[1] & 1) return QC_E_OVERFLOW;
         // a level beyond the planes of a plan with fewer than 7 (cannot
-        // happen on a first search, which always carries 7)
+        // happen: a first search with fewer planes was planned from an upper
+        // bound on every distance)
         if (status[1] & 2) return QC_E_DEVICE;
         // the largest level the search reached; with weighted edges it can
         // be that of a node inside an edge, above the graph's own dmax
@@ -422,8 +423,8 @@ const char *qc_status_str(qc_status s)
     case QC_E_BUSY: return "QC_E_BUSY: request does not fit the memory budget, or is running";
     case QC_E_TIMEOUT: return "QC_E_TIMEOUT: request not admitted before its queue deadline";
     case QC_E_CANCELLED: return "QC_E_CANCELLED: request withdrawn before it ran";
-    default: return "unknown qc_status";
     case QC_E_TOO_LARGE: return "QC_E_TOO_LARGE: problem exceeds the fixed scratch of qc_cluster_noalloc";
+    default: return "unknown qc_status";
     }
 }
 
@@ -542,14 +543,28 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     // graph keeps its node order, and so does a serving request: its one
     // search would not repay the host sweeps). QC_SOURCE_ORDER=identity keeps
     // the node order for every graph (a switch for measurements and tests).
+    // The same sweeps bound every distance of an undirected graph (by the
+    // largest eccentricity bound), so its first search can already run with
+    // the distance planes and launch shape of a known largest distance
+    // instead of 7 planes; a serving request, which searches once, takes one
+    // sweep for this bound when the 7-plane plan would narrow its batches.
     const char *so = getenv("QC_SOURCE_ORDER");
+    int32_t bound = -1;
     if (!directed && !region && !(so && strcmp(so, "identity") == 0)) {
-        g->src_order = weights ? source_order(n_bfs, brp, bcol, n, kSourceSweeps)
-                               : source_order(n, rp, col, n, kSourceSweeps);
+        g->src_order = weights ? source_order(n_bfs, brp, bcol, n, kSourceSweeps, &bound)
+                               : source_order(n, rp, col, n, kSourceSweeps, &bound);
     } else {
         g->src_order.resize(n);
         std::iota(g->src_order.begin(), g->src_order.end(), 0);
+        if (!directed && plan_bfs(n_bfs, -1).bw < kBfsFullWidth) {
+            if (weights)
+                (void)source_order(n_bfs, brp, bcol, 0, 1, &bound);
+            else
+                (void)source_order(n, rp, col, 0, 1, &bound);
+        }
     }
+    // (a bound above 126 leaves the 7-plane plan, which detects overflow)
+    if (bound > kMaxDist) bound = -1;
     std::vector<NodeJob> njobs;
     for (int i = 0; i < n; i += kNodesPerJob) njobs.push_back(NodeJob{0, i, 0});
     g->n_node_jobs = (int)njobs.size();
@@ -574,7 +589,7 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
         (st_ = upload(g->d_sell_deg, sell_deg)) ||
         (weights && ((st_ = upload(g->d_bfs_row_ptr, brp)) || (st_ = upload(g->d_bfs_col, bcol)))) ||
         (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
-        (st_ = set_plan(g, plan_bfs(n_bfs, -1))))
+        (st_ = set_plan(g, plan_bfs(n_bfs, bound))))
         return fail(st_);
     if ((st_ = from_hip(launch_fill_u64(g->d_recheck, 1, st))) || (st_ = push_desc(g, st)))
         return fail(st_);

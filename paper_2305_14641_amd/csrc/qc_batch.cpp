@@ -156,8 +156,8 @@ std::vector<NodeJob> xcd_pinned_node_jobs(const std::vector<qc_graph> &graphs)
     return out;
 }
 
-// The autotuner: g's search under each candidate plan, the planner's choice
-// for each workgroup shape and the same shape with half the batch width,
+// The autotuner: g's search under each candidate plan, the widest batch of
+// each workgroup shape and the same shape at a half and a quarter of it,
 // one untimed and kTuneReps timed runs each (HIP events on st), all in the
 // plain edge order so that no candidate starts with an order chosen for it;
 // the fastest becomes g's plan and gets its edge order.
@@ -173,10 +173,11 @@ qc_status autotune_bfs(qc_graph g, hipStream_t st)
         cands.push_back(p);
     };
     add(g->plan);
-    for (int shape : {kBfsNarrow, kBfsWide1024, kBfsWide}) {
+    for (int shape : {kBfsNarrow, kBfsWide1024, kBfsWide, kBfsFront}) {
         const BfsPlan p = plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape);
         add(p);
         if (p.bw > 4) add(plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape, p.bw / 2));
+        if (p.bw > 8) add(plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape, p.bw / 4));
     }
     if (cands.size() < 2) return QC_OK;
     hipEvent_t e0, e1;

@@ -161,8 +161,13 @@ __device__ __forceinline__ void push_level1(const GraphDev &G, const int32_t *sr
     }
 }
 
-// Workgroup shapes (kBfsNarrow, kBfsWide, kBfsWide1024):
+// Workgroup shapes (kBfsNarrow, kBfsWide, kBfsWide1024, kBfsFront):
 //   narrow   1024 threads, three fields (pull from `front`);
+//   front    1024 threads, pull from `front` like narrow, but `seen` lives in
+//            the registers of each word's owner (only the owner ever reads or
+//            writes it: phase B and the decode), so only `front` and `nxt`
+//            take LDS: the three-field search at the two-field LDS budget,
+//            for one more register per word and plane set;
 //   wide      512 threads, two fields (pull from `seen`, which is also
 //             exact: a source that reached c before the previous level has
 //             already reached r), so twice the words fit the LDS and each
@@ -176,7 +181,11 @@ __device__ __forceinline__ void push_level1(const GraphDev &G, const int32_t *sr
 // fewer atomics; the planner prefers it whenever the batch fits.
 template <int SHAPE> struct BfsShape {
     static constexpr int kThreads = (SHAPE == kBfsWide) ? kBfsThreadsWide : kBfsThreads;
-    static constexpr bool kTwoFields = SHAPE != kBfsNarrow;
+    // two LDS fields [seen | nxt], pulling from seen
+    static constexpr bool kPullSeen = SHAPE == kBfsWide || SHAPE == kBfsWide1024;
+    // seen in the owners' registers, two LDS fields [front | nxt]
+    static constexpr bool kSeenRegs = SHAPE == kBfsFront;
+    static constexpr int kFields = (kPullSeen || kSeenRegs) ? 2 : 3;
 };
 
 // WEIGHTED: the graph's edges carry integer weights and the search walks the
@@ -186,7 +195,8 @@ template <int BW, int NW, int P, int SHAPE, bool WEIGHTED>
 __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDev *__restrict__ graphs,
                                                                    const BfsJob *__restrict__ jobs)
 {
-    constexpr bool WIDE = BfsShape<SHAPE>::kTwoFields;
+    constexpr bool WIDE = BfsShape<SHAPE>::kPullSeen;
+    constexpr bool SREG = BfsShape<SHAPE>::kSeenRegs;
     using W = BfsWord<BW>;
     using T = typename W::T;
     constexpr int kT = BfsShape<SHAPE>::kThreads;
@@ -196,13 +206,15 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
 
     // The fields share one LDS array, the field the pull gathers from first
     // (LDS address 0, so a gather's address is the column's word offset):
-    // two fields [seen | nxt], three fields [front | nxt | seen].
-    __shared__ __attribute__((aligned(16))) T fields[(WIDE ? 2 : 3) * kLdsWords];
+    // two fields [seen | nxt], three fields [front | nxt | seen], or, with
+    // seen in registers, [front | nxt].
+    __shared__ __attribute__((aligned(16))) T fields[BfsShape<SHAPE>::kFields * kLdsWords];
     __shared__ uint32_t found_pairs;
     __shared__ int32_t srcs[BW];          // the batch's sources
     T *const front = fields;
     T *const nxt = fields + kLdsWords;
-    T *const seen = WIDE ? fields : fields + 2 * kLdsWords;
+    T *const seen = WIDE ? fields : fields + 2 * kLdsWords;   // (not with SREG)
+    T seen_r[SREG ? NWW : 1];             // SREG: seen of the owned words
 
     const BfsJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
@@ -228,7 +240,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
 #pragma unroll
     for (int j = 0; j < NWW; ++j) {
         const int w = j * kT + tid;
-        seen[w] = 0;
+        if constexpr (!SREG) seen[w] = 0;
         if constexpr (!WIDE) front[w] = 0;
         nxt[w] = 0;
     }
@@ -238,12 +250,20 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     if (tid < nb) {
         const int v = srcs[tid];
         const T bit = (T)1 << ((v % W::kPer) * BW + tid);
-        __hip_atomic_fetch_or(&seen[v / W::kPer], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if constexpr (!SREG)
+            __hip_atomic_fetch_or(&seen[v / W::kPer], bit, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
         if constexpr (!WIDE)
             __hip_atomic_fetch_or(&front[v / W::kPer], bit, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
+    if constexpr (SREG) {
+        // the owners take the sources' bits (level 0 = the frontier) into
+        // their registers
+#pragma unroll
+        for (int j = 0; j < NWW; ++j) seen_r[j] = front[j * kT + tid];
+    }
     uint32_t found_before = (uint32_t)nb;
 
     int last = 0;
@@ -263,7 +283,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             //    Unrolled twice where the registers allow, so the two sets of
             //    quads alternate roles instead of being copied.
             constexpr uint32_t kStep = 2u * kT * 16u;   // bytes per round of the workgroup
-            constexpr bool kAlternate = !(kT == 1024 && NWW * P > 80);
+            constexpr bool kAlternate = !(kT == 1024 && NWW * (P + (SREG ? 1 : 0)) > 80);
             uint32_t off = (uint32_t)opaque(tid) * 32u;
             u32x4 a0 = edge_quad(edges, off);
             u32x4 b0 = edge_quad(edges, off + 16u);
@@ -301,10 +321,13 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
             const int w = j * kT + tb;
             if (w < nwords) {
                 const T raw = nxt[w];
-                const T sw = seen[w];
+                const T sw = SREG ? seen_r[j] : seen[w];
                 const T y = raw & ~sw;        // newly reached (node, source) pairs
                 if constexpr (!WIDE) front[w] = y;
-                if (y) seen[w] = sw | y;
+                if constexpr (SREG)
+                    seen_r[j] = sw | y;
+                else if (y)
+                    seen[w] = sw | y;
                 cnt += (uint32_t)__popcll((unsigned long long)y);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
@@ -348,7 +371,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     for (int j = 0; j < NWW; ++j) {
         const int w = j * kT + td;
         if (w < own_words) {
-            const T sw = seen[w];
+            const T sw = SREG ? seen_r[j] : seen[w];
             T lp[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) lp[p] = plane[j][p];
@@ -487,6 +510,29 @@ hipError_t launch_bfs_wide1024_p(int nw, bool weighted, const GraphDev *graphs,
     }
 }
 
+// Seen-in-registers 1024-thread shapes (planes 4 or 5): the registers hold
+// (planes + 1) words per owned word, so up to 16 words per thread with 4
+// planes and 14 with 5 fit 128 registers without spills.
+template <int BW, int P>
+hipError_t launch_bfs_front_p(int nw, bool weighted, const GraphDev *graphs, const BfsJob *jobs,
+                              int n_jobs, hipStream_t stream)
+{
+    if constexpr (P >= 7 || BW < 8) {
+        return hipErrorInvalidValue;
+    } else {
+        switch (nw) {
+        case 4: return launch_bfs_t<BW, 4, P, kBfsFront>(weighted, graphs, jobs, n_jobs, stream);
+        case 8: return launch_bfs_t<BW, 8, P, kBfsFront>(weighted, graphs, jobs, n_jobs, stream);
+        case 12: return launch_bfs_t<BW, 12, P, kBfsFront>(weighted, graphs, jobs, n_jobs, stream);
+        case 14: return launch_bfs_t<BW, 14, P, kBfsFront>(weighted, graphs, jobs, n_jobs, stream);
+        case 16: if constexpr (P == 4)
+                     return launch_bfs_t<BW, 16, P, kBfsFront>(weighted, graphs, jobs, n_jobs, stream);
+                 return hipErrorInvalidValue;  // 6 x 16 words exceed the registers
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
 template <int BW>
 hipError_t launch_bfs_bw(int nw, int planes, int shape, const GraphDev *graphs, const BfsJob *jobs,
                          int n_jobs, hipStream_t stream)
@@ -504,6 +550,13 @@ hipError_t launch_bfs_bw(int nw, int planes, int shape, const GraphDev *graphs, 
         switch (planes) {
         case 4: return launch_bfs_wide1024_p<BW, 4>(nw, weighted, graphs, jobs, n_jobs, stream);
         case 5: return launch_bfs_wide1024_p<BW, 5>(nw, weighted, graphs, jobs, n_jobs, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (shape == kBfsFront) {
+        switch (planes) {
+        case 4: return launch_bfs_front_p<BW, 4>(nw, weighted, graphs, jobs, n_jobs, stream);
+        case 5: return launch_bfs_front_p<BW, 5>(nw, weighted, graphs, jobs, n_jobs, stream);
         default: return hipErrorInvalidValue;
         }
     }

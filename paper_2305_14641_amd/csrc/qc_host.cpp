@@ -2,6 +2,7 @@
 #include "qc_host.h"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -260,7 +261,8 @@ int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::v
 }
 
 std::vector<int32_t> source_order(int32_t n, const std::vector<int32_t> &rp,
-                                  const std::vector<int32_t> &col, int32_t n_src, int sweeps)
+                                  const std::vector<int32_t> &col, int32_t n_src, int sweeps,
+                                  int32_t *dist_bound)
 {
     auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
     // component labels (BFS) and each component's first seed
@@ -318,6 +320,11 @@ std::vector<int32_t> source_order(int32_t n, const std::vector<int32_t> &rp,
         }
         seed = far;
     }
+    if (dist_bound) {
+        int32_t b = 0;
+        for (int32_t v = 0; v < n; ++v) b = std::max(b, hi[v]);
+        *dist_bound = b;
+    }
     std::vector<int32_t> order(n_src);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -338,6 +345,7 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw)
     static const int kNarrow[] = {1, 2, 4, 6, 8, 10, 12};
     static const int kWide[] = {16, 24, 32, 38, 39};
     static const int kWide1024[] = {14, 16, 18, 19};
+    static const int kFront[] = {4, 8, 12, 14, 16};
     const int planes = planes_for(dmax);
     const bool two = shape != kBfsNarrow;
     BfsPlan none = {0, 0, planes, 0, shape};
@@ -346,7 +354,7 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw)
     // words per thread that fit the registers without spills: three-field
     // shape 12 (10 with 7 planes and 64-source batches); two-field 512-thread
     // 39 with 4 planes, 32 with 5; two-field 1024-thread 19 with 4, 16 with 5
-    // (18 for batches of 32)
+    // (18 for batches of 32); seen in registers 16 with 4, 14 with 5
     int max_nw;
     const int *opts;
     int nopts;
@@ -357,6 +365,11 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw)
     } else if (shape == kBfsWide) {
         max_nw = planes <= 4 ? 39 : 32;
         opts = kWide;
+        nopts = 5;
+    } else if (shape == kBfsFront) {
+        // seen in registers: (planes + 1) registers per owned word
+        max_nw = planes <= 4 ? 16 : 14;
+        opts = kFront;
         nopts = 5;
     } else {
         max_nw = planes <= 4 ? 19 : 18;
@@ -389,11 +402,25 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw)
 
 BfsPlan plan_bfs(int32_t n, int32_t dmax)
 {
-    // the widest batch wins; at equal width, more threads per workgroup, and
-    // three fields (fewer atomics) before two
-    BfsPlan best = plan_bfs_shape(n, dmax, kBfsNarrow);
-    for (int shape : {kBfsWide1024, kBfsWide}) {
-        const BfsPlan p = plan_bfs_shape(n, dmax, shape);
+    // QC_BFS_SHAPE=<shape> (a switch for measurements and tests): that
+    // workgroup shape whenever the graph fits it
+    if (const char *f = getenv("QC_BFS_SHAPE")) {
+        const int shape = atoi(f);
+        if (shape >= kBfsNarrow && shape <= kBfsFront) {
+            const BfsPlan p = plan_bfs_shape(n, dmax, shape);
+            if (p.bw > 0) return p;
+        }
+    }
+    // At most kBfsFullWidth sources per batch (timed on the sweep graphs,
+    // 32-source batches beat 64-source ones on every graph). The shape with
+    // seen in registers (pull from the frontier at the two-field LDS budget)
+    // first when the graph fits it at that width; otherwise the widest batch
+    // wins, at equal width more threads per workgroup, and pulling from the
+    // frontier (fewer atomics) before pulling from seen.
+    BfsPlan best = plan_bfs_shape(n, dmax, kBfsFront, kBfsFullWidth);
+    if (best.bw == kBfsFullWidth) return best;
+    for (int shape : {kBfsNarrow, kBfsWide1024, kBfsWide}) {
+        const BfsPlan p = plan_bfs_shape(n, dmax, shape, kBfsFullWidth);
         if (p.bw > best.bw) best = p;
     }
     return best;

@@ -57,8 +57,11 @@ int32_t count_components(int32_t n, const std::vector<int32_t> &rp, const std::v
 // node the previous sweep reached last; for a sweep from c with eccentricity
 // e(c), every node v of the component has max(d(v,c), e(c) - d(v,c)) <= e(v)
 // <= e(c) + d(v,c). The order lists the first n_src nodes (the sources).
+// If dist_bound is given it receives the largest upper bound, a bound on
+// every finite distance of the graph.
 std::vector<int32_t> source_order(int32_t n, const std::vector<int32_t> &rp,
-                                  const std::vector<int32_t> &col, int32_t n_src, int sweeps);
+                                  const std::vector<int32_t> &col, int32_t n_src, int sweeps,
+                                  int32_t *dist_bound = nullptr);
 
 // Integer edge weights (Section 3.1: a path's length is the sum of its edges'
 // weights): an edge of weight w >= 2 becomes a path of w unit edges through
@@ -76,10 +79,11 @@ qc_status subdivide_weighted(int32_t n, const std::vector<int32_t> &rp,
 // dmax (or -1 while unknown): `planes` distance bit-planes (enough for dmax,
 // 7 when unknown), and the widest batch of sources whose LDS bit fields and
 // register planes fit one workgroup, with nw 32-bit words per thread per
-// field. `shape` (kBfsNarrow, kBfsWide, kBfsWide1024): the three-field
-// 1024-thread shape is used whenever it fits the widest batch; otherwise the
-// two-field 1024-thread one, then the two-field 512-thread one (both only
-// with 4-5 planes).
+// field. `shape` (kBfsNarrow, kBfsWide, kBfsWide1024, kBfsFront): batches of
+// at most kBfsFullWidth sources; the seen-in-registers shape when it fits
+// that width, else the widest batch of any shape (three fields before the
+// two-field 1024-thread shape before the 512-thread one; the two-field and
+// seen-in-registers shapes only with 4-5 planes).
 struct BfsPlan { int bw; int nw; int planes; int n_batches; int shape; };
 BfsPlan plan_bfs(int32_t n, int32_t dmax);
 // The plan of one shape alone (bw = 0 when n does not fit).

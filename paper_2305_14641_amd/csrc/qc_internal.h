@@ -21,8 +21,13 @@ constexpr int64_t kMaxEdges = (int64_t)1 << 29;
 constexpr int kBfsThreads = 1024;
 constexpr int kBfsThreadsWide = 512;
 // BFS workgroup shapes: three fields x 1024 threads, two fields x 512
-// threads, two fields x 1024 threads.
-enum { kBfsNarrow = 0, kBfsWide = 1, kBfsWide1024 = 2 };
+// threads, two fields x 1024 threads, and two LDS fields x 1024 threads with
+// the third (`seen`) in registers.
+enum { kBfsNarrow = 0, kBfsWide = 1, kBfsWide1024 = 2, kBfsFront = 3 };
+// Widest batch of sources the planner picks: 64-source batches halve the
+// batches but double each workgroup's LDS and registers, while the search is
+// bound by the latency of its LDS gathers, which more wavefronts per CU hide.
+constexpr int kBfsFullWidth = 32;
 // Added to a shape at launch: the graph carries integer edge weights.
 constexpr int kBfsWeighted = 16;
 // 32-bit words of each LDS bit field one BFS thread owns at most (the three
@@ -184,11 +189,6 @@ class StageTimer {
     void *start_ = nullptr;
     void *stop_ = nullptr;
 };
-
-// Algorithm 1 over a dense float distance matrix (qc_dense.hip): rows
-// [0, n_rows) of `dist` (row stride `ld` floats), every width of `sigmas`
-// (host); writes psi and V as FP64 [n_sigmas][n_rows].
-hipError_t launch_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64_t ld,
 // While alive, the calling thread's stage timers record nothing (and create
 // no HIP events).
 class StageTimingOff {
@@ -198,6 +198,11 @@ class StageTimingOff {
   private:
     bool prev_;
 };
+
+// Algorithm 1 over a dense float distance matrix (qc_dense.hip): rows
+// [0, n_rows) of `dist` (row stride `ld` floats), every width of `sigmas`
+// (host); writes psi and V as FP64 [n_sigmas][n_rows].
+hipError_t launch_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64_t ld,
                         const double *sigmas, int n_sigmas, double *psi, double *v,
                         hipStream_t stream);
 

@@ -258,13 +258,18 @@ def test_deterministic_and_repeatable(torch_cuda):
                                gg.dcsbm(5000, [0.5, 0.3, 0.2], 5.0, seed=41)],
                          ids=lambda g: g.name)
 @pytest.mark.parametrize("env", [{"QC_SOURCE_ORDER": "identity"}, {"QC_EDGE_BANKS": "0"},
-                                 {"QC_EDGE_BANKS": "64"}], ids=lambda e: ",".join(e.values()))
+                                 {"QC_EDGE_BANKS": "64"}, {"QC_BFS_SHAPE": "0"},
+                                 {"QC_BFS_SHAPE": "1"}, {"QC_BFS_SHAPE": "2"},
+                                 {"QC_BFS_SHAPE": "3"}],
+                         ids=lambda e: ",".join(f"{k}={v}" for k, v in e.items()))
 def test_search_order_changes_nothing(torch_cuda, monkeypatch, g, env):
     """The BFS takes its sources in an order estimated from eccentricity
     bounds, and the edges of each pull group in an order that spreads the
     gathers over the LDS banks; the node order (QC_SOURCE_ORDER=identity),
-    the plain rows-ascending edge order (QC_EDGE_BANKS=0) or another bank
-    count must give the same bytes everywhere."""
+    the plain rows-ascending edge order (QC_EDGE_BANKS=0), another bank
+    count, or any workgroup shape of the search (QC_BFS_SHAPE, taken from
+    the second search on, once the largest distance is known) must give the
+    same bytes everywhere."""
     torch = torch_cuda
     print(f"[gpu] search order {g.name} n={g.n} {env}", flush=True)
     a = run_gpu(torch, g, [0.7, 2.0], repeat=2)
@@ -278,6 +283,60 @@ def test_search_order_changes_nothing(torch_cuda, monkeypatch, g, env):
     for k in a["labels"]:
         np.testing.assert_array_equal(a["labels"][k], b["labels"][k])
     check_against_oracle(g, [0.7, 2.0], b, ties=(0,), pairsum=False)
+
+
+def front_plan(n, dmax):
+    """Batch width and words per thread of the seen-in-registers shape: the
+    widest batch whose bit fields fit 16 words per thread (4 planes, largest
+    distance <= 15) or 14 (5 planes) at 1024 threads."""
+    max_nw = 16 if dmax <= 15 else 14
+    for bw in (64, 32, 16, 8):
+        need = -(-(-(-n * bw // 32)) // 1024)
+        for nw in (4, 8, 12, 14, 16):
+            if nw > max_nw:
+                break
+            if bw == 64 and nw % 2:
+                continue
+            if nw >= need:
+                return bw, nw
+    return None
+
+
+@pytest.mark.parametrize("n,deg,seed", [
+    (15000, 4.0, 26),   # 32 sources, 15 of 16 words per thread
+    (9000, 4.0, 22),    # 64 sources would need 18 words: 32 sources
+    (6000, 5.0, 21),    # 64 sources (64-bit fields)
+    (16500, 4.0, 27),   # beyond 16 words at 32 sources: 16 sources
+])
+def test_seen_in_registers_shape(torch_cuda, monkeypatch, n, deg, seed):
+    """The search shape that keeps `seen` in its owners' registers (two LDS
+    fields, pull from the frontier): sampled rows bit-exact, the whole
+    matrix equal to the planner's own shape, histograms and labels exact."""
+    from paper_2305_14641_amd import qc
+    torch = torch_cuda
+    g = gg.dcsbm(n, [0.5, 0.3, 0.2], deg, seed=seed)
+    print(f"[gpu] seen-in-registers shape n={n} nnz={g.nnz}", flush=True)
+    ref = run_gpu(torch, g, [1.5], ties=(0,), repeat=2)
+    monkeypatch.setenv("QC_BFS_SHAPE", "3")
+    G = qc.Graph.from_graph(g)
+    dist = torch.empty((n, n), dtype=torch.int8, device="cuda")
+    dmax = G.distances(dist)
+    assert G.distances(dist) == dmax
+    bw, nw, planes, shape = G.bfs_plan()
+    assert (bw, nw, shape) == front_plan(n, dmax) + (3,), (bw, nw, planes, shape)
+    assert torch.equal(dist, torch.as_tensor(ref["dist"], device="cuda"))
+    rows = np.unique(np.random.default_rng(seed).choice(n, 24, replace=False)).astype(np.int32)
+    ref_rows, _ = oracle.bfs_rows(n, g.row_ptr, g.col, rows)
+    np.testing.assert_array_equal(dist[torch.as_tensor(rows.astype(np.int64), device="cuda")]
+                                  .cpu().numpy(), ref_rows)
+    del dist
+    hist = G.histograms().cpu().numpy()
+    np.testing.assert_array_equal(hist, ref["hist"])
+    psi, v = G.potential([1.5])
+    lab = G.labels(0, qc.TIE_STRICT).cpu().numpy()
+    np.testing.assert_array_equal(lab, ref["labels"][(0, 0)])
+    if n <= 9000:
+        check_against_oracle(g, [1.5], ref, ties=(0,), pairsum=False)
 
 
 def test_recheck_counts_exact_ties(torch_cuda):
