@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # vector lane-operations/s: 256 CUs x 64 lanes x 2.4 GHz
 LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # LDS bytes/s: 256 CUs x 128 bytes per clock x 2.4 GHz
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
 
 
 def log(msg):
@@ -450,6 +451,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the smaller workloads (latency, end to end, resident matrix)")
     ap.add_argument("--cpu-1t-budget-s", type=float, default=6.0)
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the BF16 matrix-core sweep variant")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -495,12 +498,12 @@ def main():
     tuned = [G.bfs_plan() for G in handles]
     log(f"batch set-up {time.perf_counter() - t0:.2f}s; autotuner changed the BFS plan of "
         f"{sum(a != b for a, b in zip(planned, tuned))} of {len(handles)} graphs")
-    psi, v, lab = batch.outputs()
-    pair_terms = float(sum(float(g.n) ** 2 for g in graphs)) * S
-    log(f"planned batch: total nodes {batch.total}, pair-terms/step {pair_terms:.3e}")
     from collections import Counter
     log("BFS plans (batch width, words, planes, shape): "
         + ", ".join(f"{k}x{c}" for k, c in sorted(Counter(tuned).items())))
+    psi, v, lab = batch.outputs()
+    pair_terms = float(sum(float(g.n) ** 2 for g in graphs)) * S
+    log(f"planned batch: total nodes {batch.total}, pair-terms/step {pair_terms:.3e}")
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
@@ -583,25 +586,39 @@ def main():
                  "bitwise_equal_to_batched": True}
         log(f"plain: {pdt * 1e3:.2f} ms/step")
 
-    # -- BF16 matrix-core sweep variant: time and error vs the FP64 values ----
+    # -- BF16 matrix-core sweep variant over the whole batch: time, matrix-core
+    #    rate and error against the FP64-accumulated values ---------------------
     bf16 = None
-    if not args.no_plain:
+    if not args.no_bf16:
+        pb, vb = batch.sweep_bf16()
+        torch.cuda.synchronize()
+        reps = 10
         qc.timing_enable(True)
-        worst_psi = worst_v = 0.0
-        for i, (g, G) in enumerate(zip(graphs, handles)):
-            pb, vb = G.potential(sigmas, precision=qc.PREC_BF16)
-            o = batch.offsets[i]
-            pr, vr = psi[:, o:o + g.n].double(), v[:, o:o + g.n].double()
-            worst_psi = max(worst_psi, float(((pb.double() - pr).abs() / pr.abs()).max()))
-            nz = vr != 0
-            worst_v = max(worst_v, float(((vb.double() - vr).abs()[nz] / vr.abs()[nz]).max()))
+        for _ in range(reps):
+            batch.sweep_bf16(pb, vb)
         torch.cuda.synchronize()
         ms, cnt = qc.timing_read(qc.STAGE_POTENTIAL)
         qc.timing_enable(False)
-        bf16 = {"potential_ms_per_step": ms, "launches": cnt,
+        ms, cnt = ms / reps, cnt / reps
+        # psi/V of the batched run are within 1e-6 of FP64, far below the BF16 error
+        pr, vr = psi.double(), v.double()
+        worst_psi = float(((pb.double() - pr).abs() / pr.abs()).max())
+        nz = vr != 0
+        worst_v = float(((vb.double() - vr).abs()[nz] / vr.abs()[nz]).max())
+        # one 16x16x32 MFMA (16,384 flops) per 16-node tile, 16 weight columns
+        # (8 sigmas x {psi, numerator}) and 32 histogram bins
+        col_blocks = -(-2 * S // 16)
+        flops = float(sum(-(-g.n // 16) * col_blocks * (G.histograms_k() // 32) * 16384
+                          for g, G in zip(graphs, handles)))
+        bf16 = {"potential_ms_per_step": ms, "launches_per_step": cnt,
                 "fp64_potential_ms_per_step": stages["potential"]["ms_per_step"],
+                "speedup_vs_fp64_potential": stages["potential"]["ms_per_step"] / ms,
+                "mfma_flops_per_step": flops,
+                "mfma_tflops": flops / (ms * 1e-3) / 1e12, "mfma_peak_tflops": BF16_PEAK_TFLOPS,
+                "mfma_frac": flops / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
                 "max_rel_err_psi": worst_psi, "max_rel_err_v": worst_v}
-        log(f"bf16 sweep: {ms:.3f} ms, max rel err psi {worst_psi:.2e} V {worst_v:.2e}")
+        log(f"bf16 sweep: {ms:.3f} ms ({cnt:.0f} launches), {bf16['mfma_tflops']:.2f} TFLOP/s, "
+            f"max rel err psi {worst_psi:.2e} V {worst_v:.2e}")
 
     dense = None if args.no_dense else dense_leg(args, qc, torch)
     configs = None if args.no_configs else configs_leg(args, qc, gg, torch)

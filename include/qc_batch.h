@@ -68,6 +68,22 @@ qc_status qc_batch_node_offsets(qc_batch b, int64_t *offsets);
 qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
                        void *stream);
 
+/*
+ * Approximate sigma sweep on the matrix cores: psi (Eq. 2) and V
+ * (Algorithm 1, regrouped by distance value) for every (graph, sigma) of
+ * the batch from the graphs' resident distance histograms, as the product
+ * [weights x bins] . [bins x nodes] with both factors rounded to BF16 and
+ * FP32 accumulation (QC_PREC_BF16 of qc_potential, one grouped launch per
+ * histogram row length). BF16 keeps 8 significant bits: expect about 1e-3
+ * relative error against FP64. Nothing resident changes: these potentials
+ * never reach the descent, and a later qc_batch_run is unaffected.
+ *   psi_out, v_out  device, float[n_sigmas][total_nodes] (layout as for
+ *                   qc_batch_run), both required
+ * Errors: QC_E_INVAL for a NULL batch or output; QC_E_DEVICE for a launch
+ * failure.
+ */
+qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *stream);
+
 /* Number of node decisions re-decided in FP64 by the last run (waits). */
 qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out);
 

@@ -431,6 +431,19 @@ qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels
     return QC_OK;
 }
 
+qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *stream)
+{
+    if (!b || !psi_out || !v_out) return QC_E_INVAL;
+    hipStream_t st = as_stream(stream);
+    const int64_t total = b->offsets.back();
+    for (auto &g : b->pot) {
+        StageTimer t(QC_STAGE_POTENTIAL, st);
+        QC_HIP(launch_potential(QC_PREC_BF16, g.K, b->d_descs, g.d_jobs, g.n_jobs, psi_out, v_out,
+                                total, st));
+    }
+    return QC_OK;
+}
+
 qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out)
 {
     if (!b || !count_out) return QC_E_INVAL;

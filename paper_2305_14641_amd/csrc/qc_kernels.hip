@@ -335,13 +335,19 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
     }
 }
 
-// BF16 matrix-core variant: for 16 nodes at a time, the histogram tile
-// (16 nodes x 32 bins, BF16) times the weight tile (32 bins x 16 columns: for
-// 8 sigmas the psi weights w_k and the V numerator weights k^2 w_k / a, BF16)
-// accumulated in FP32 by v_mfma_f32_16x16x32_bf16. BF16 keeps 8 significant
-// bits, so psi and V carry about 1e-3 relative error: an approximate sweep,
-// never used for the descent. One wavefront per 16-node tile; each job of
-// kNodesPerJob nodes is 16 tiles handled by 4 wavefronts.
+// BF16 matrix-core variant: the product [weights x bins] . [bins x nodes]
+// on v_mfma_f32_16x16x32_bf16, accumulated in FP32. For a tile of 16 nodes,
+// A = 16 weight columns (8 sigmas x {psi weight w_k, V numerator weight
+// k^2 w_k / a}) by 32 bins and B = the 16 histogram rows (32 bins each), both
+// rounded to BF16. BF16 keeps 8 significant bits, so psi and V carry about
+// 1e-3 relative error: an approximate sweep, never used for the descent.
+// The weight fragments do not depend on the graph, so each workgroup builds
+// them once in LDS (for 32 sigmas at a time: 16 bytes per lane and column
+// block) and every tile reads them with one 16-byte LDS read per MFMA. The
+// output layout puts one node per lane column: lane (row, quad) holds psi and
+// the numerator of sigmas 2 quad and 2 quad + 1 of node row, so each store
+// covers 16 consecutive nodes of 4 sigmas. One wavefront per 16-node tile;
+// a job of kNodesPerJob nodes is 16 tiles for 4 wavefronts.
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -353,62 +359,85 @@ __device__ __forceinline__ short f32_to_bf16(float f)
     return (short)(u >> 16);
 }
 
+constexpr int kBf16SigmaGroup = 32;   // sigmas whose weight fragments sit in LDS at once
+
 template <int K>
 __global__ __launch_bounds__(256) void k_potential_bf16(const GraphDev *__restrict__ graphs,
                                                         const NodeJob *__restrict__ jobs,
                                                         float *__restrict__ psi_out,
                                                         float *__restrict__ v_out, int64_t out_ld)
 {
+    constexpr int KC = K / 32;                       // 32-bin chunks
+    constexpr int CB = 2 * kBf16SigmaGroup / 16;     // 16-column blocks per sigma group
+    __shared__ bf16x8 wfrag[KC][CB][64];             // K = 32: 4 KB
     const NodeJob job = jobs[blockIdx.x];
     const GraphDev &G = graphs[job.g];
     const int n = G.n;
     const int S = G.n_sigmas;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int row = lane % 16, quad = lane / 16;
-    for (int tile = wave; tile < kNodesPerJob / 16; tile += 4) {
-        const int node0 = job.i0 + tile * 16;
-        if (node0 >= n) break;
-        // A fragments: lane holds bins 8*quad .. 8*quad+7 of node node0+row
-        bf16x8 a[K / 32];
-        const int na = node0 + row;
+    const int kmax = min(G.dmax + 1, K);             // bins past the largest distance count 0
+    constexpr int kTiles = kNodesPerJob / 16 / 4;    // tiles per wavefront
+
+    for (int sg = 0; sg < S; sg += kBf16SigmaGroup) {
+        // A fragments of this sigma group: column c = 2 s + kind of the group
+        __syncthreads();
+        for (int f = threadIdx.x; f < KC * CB * 64; f += 256) {
+            const int l = f % 64, cb = (f / 64) % CB, kc = f / (64 * CB);
+            const int c = cb * 16 + l % 16, q = l / 16;
+            const int sig = sg + c / 2, kind = c % 2;
+            bf16x8 a;
 #pragma unroll
-        for (int kc = 0; kc < K / 32; ++kc) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int k = kc * 32 + quad * 8 + t;
-                const float h = (na < n) ? (float)G.hist[(int64_t)na * G.K + k] : 0.f;
-                a[kc][t] = f32_to_bf16(h);
+            for (int e = 0; e < 8; ++e) {
+                const int k = kc * 32 + q * 8 + e;
+                a[e] = (sig < S) ? (short)G.wbf16[((int64_t)sig * G.K + k) * 2 + kind] : (short)0;
             }
+            wfrag[kc][cb][l] = a;
         }
-        // 16 output columns per step: sigma = col / 2, (psi, numerator) = col % 2
-        for (int c0 = 0; c0 < 2 * S; c0 += 16) {
-            const int col = c0 + row;
-            const int s = col / 2, kind = col % 2;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        __syncthreads();
+#pragma unroll 1
+        for (int t = 0; t < kTiles; ++t) {
+            const int node0 = job.i0 + (wave + 4 * t) * 16;
+            if (node0 >= n) break;
+            const int node = node0 + row;
+            // B fragments: lane holds bins 8 quad .. 8 quad + 7 of node
+            // node0 + row, two 16-byte loads per chunk
+            bf16x8 hb[KC];
 #pragma unroll
-            for (int kc = 0; kc < K / 32; ++kc) {
-                bf16x8 b;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int k = kc * 32 + quad * 8 + t;
-                    b[t] = (s < S) ? (short)G.wbf16[((int64_t)s * G.K + k) * 2 + kind] : (short)0;
+            for (int kc = 0; kc < KC; ++kc) {
+                u32x4 lo = {0u, 0u, 0u, 0u}, hi = {0u, 0u, 0u, 0u};
+                if (node < n) {
+                    const global_u4 src =
+                        (global_u4)(G.hist + (int64_t)node * G.K + kc * 32 + quad * 8);
+                    lo = src[0];
+                    hi = src[1];
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc], b, acc, 0, 0, 0);
-            }
-            // lane holds D[4*quad + r][col]; the numerator sits in the next lane
+                const uint32_t h8[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float num = __shfl_xor(acc[r], 1);
-                const int node = node0 + 4 * quad + r;
-                if (kind == 0 && s < S && node < n) {
-                    const float psi = acc[r];
-                    const float v = num / psi;
-                    const int64_t o = (int64_t)s * n + node;
-                    G.psi[o] = psi;
-                    G.v[v_index(n, s, node)] = v;
-                    const int64_t ou = job.out_off + (int64_t)s * out_ld + node;
-                    if (psi_out) psi_out[ou] = psi;
-                    if (v_out) v_out[ou] = v;
+                for (int e = 0; e < 8; ++e)
+                    hb[kc][e] = (kc * 32 + quad * 8 + e < kmax) ? f32_to_bf16((float)h8[e]) : (short)0;
+            }
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                if (sg + cb * 8 >= S) break;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfrag[kc][cb][lane], hb[kc], acc,
+                                                                  0, 0, 0);
+                // acc[r] = column 4 quad + r of the block for node `row`:
+                // sigma sg + 8 cb + 2 quad + r / 2, psi (r even) or numerator
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int sig = sg + cb * 8 + 2 * quad + j;
+                    if (sig < S && node < n) {
+                        const float psi = acc[2 * j], v = acc[2 * j + 1] / psi;
+                        const int64_t ou = job.out_off + (int64_t)sig * out_ld + node;
+                        if (psi_out) psi_out[ou] = psi;
+                        else G.psi[(int64_t)sig * n + node] = psi;
+                        if (v_out) v_out[ou] = v;
+                        else G.v[v_index(n, sig, node)] = v;
+                    }
                 }
             }
         }

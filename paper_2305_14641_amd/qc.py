@@ -49,7 +49,7 @@ EXPORTED = [
     "qc_timing_read", "qc_potential_dense", "qc_debug_alloc_fault", "qc_get_potential64",
     "qc_cluster", "qc_cluster_noalloc",
     "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
-    "qc_batch_search_stats", "qc_batch_destroy",
+    "qc_batch_search_stats", "qc_batch_sweep_bf16", "qc_batch_destroy",
 ]
 
 BATCH_HIPGRAPH = 1
@@ -128,6 +128,7 @@ def lib():
         L.qc_batch_create.argtypes = [P, I32, P, I32, U32, U32, P, P]
         L.qc_batch_node_offsets.argtypes = [P, P]
         L.qc_batch_run.argtypes = [P, P, P, P, P]
+        L.qc_batch_sweep_bf16.argtypes = [P, P, P, P]
         L.qc_batch_recheck_count.argtypes = [P, P]
         L.qc_batch_search_stats.argtypes = [P, P, P]
         L.qc_batch_destroy.argtypes = [P]
@@ -275,6 +276,12 @@ class Graph:
         self._dist_ref = out
         return int(dmax.value)
 
+    def histograms_k(self) -> int:
+        """Row length K of the resident histograms (a multiple of 32)."""
+        k = ctypes.c_int32(0)
+        _check(lib().qc_get_histograms(self._h, None, ctypes.byref(k), None), "qc_get_histograms")
+        return int(k.value)
+
     def histograms(self, stream=None):
         import torch
         k = ctypes.c_int32(0)
@@ -369,6 +376,22 @@ class Batch:
     def run(self, psi, v, labels, stream=None):
         _check(lib().qc_batch_run(self._h, _dptr(psi), _dptr(v), _dptr(labels),
                                   _stream_ptr(stream)), "qc_batch_run")
+
+    def sweep_bf16(self, psi=None, v=None, stream=None):
+        """Approximate psi/V of every (sigma, node) on the matrix cores
+        (qc_batch_sweep_bf16): float32 [S, total] tensors, about 1e-3
+        relative error; nothing resident changes."""
+        import torch
+        shape = (len(self.sigmas), self.total)
+        if psi is None:
+            psi = torch.empty(shape, dtype=torch.float32, device="cuda")
+        if v is None:
+            v = torch.empty(shape, dtype=torch.float32, device="cuda")
+        Graph._check_tensor(psi, shape, "float32")
+        Graph._check_tensor(v, shape, "float32")
+        _check(lib().qc_batch_sweep_bf16(self._h, _dptr(psi), _dptr(v), _stream_ptr(stream)),
+               "qc_batch_sweep_bf16")
+        return psi, v
 
     def recheck_count(self) -> int:
         c = ctypes.c_int64(0)

@@ -171,3 +171,39 @@ def test_batch_search_stats_count_the_searches_work(setup, monkeypatch):
     assert visits == want_visits
     assert lds == want_bytes
     b.close()
+
+
+def test_batch_bf16_sweep(setup):
+    """The BF16 matrix-core sweep over the whole batch (one grouped launch per
+    histogram row length): bitwise the per-graph BF16 potentials, within the
+    BF16 error of the oracle's FP64 values (8 significant bits: a few 1e-3),
+    and the batch's own run afterwards is unchanged (nothing resident is
+    written)."""
+    torch, qc, graphs, sigmas = setup
+    sig = gg.sigmas_c4() + [1.0, 2.0]   # 34 sigmas: a second group of weight columns
+    handles = [qc.Graph.from_graph(g) for g in graphs]
+    b = qc.Batch(handles, sig, hipgraph=True)
+    psi, v, lab = b.outputs()
+    b.run(psi, v, lab)
+    torch.cuda.synchronize()
+    lab0 = lab.cpu().numpy().copy()
+    pb, vb = b.sweep_bf16()
+    torch.cuda.synchronize()
+    pb, vb = pb.cpu().numpy(), vb.cpu().numpy()
+    for i, (g, G) in enumerate(zip(graphs, handles)):
+        o0, o1 = b.offsets[i], b.offsets[i + 1]
+        hist = G.histograms().cpu().numpy()
+        dmax = int(np.nonzero(hist.any(axis=0))[0].max())
+        for s in (0, 9, 31):
+            psi_c, v_c = oracle.potential_canonical(np.ascontiguousarray(hist[:, :dmax + 1]), sig[s])
+            assert np.abs(pb[s, o0:o1] / psi_c - 1).max() < 2e-2
+            nz = v_c != 0      # (none on a one-node graph)
+            assert np.max(np.abs(vb[s, o0:o1][nz] / v_c[nz] - 1), initial=0.0) < 2e-2
+            assert (vb[s, o0:o1][~nz] == 0).all()
+        p1, v1 = G.potential(sig, precision=qc.PREC_BF16)
+        assert p1.cpu().numpy().tobytes() == np.ascontiguousarray(pb[:, o0:o1]).tobytes()
+        assert v1.cpu().numpy().tobytes() == np.ascontiguousarray(vb[:, o0:o1]).tobytes()
+    b.run(psi, v, lab)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(lab.cpu().numpy(), lab0)
+    b.close()
