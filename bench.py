@@ -501,6 +501,8 @@ def main():
     from collections import Counter
     log("BFS plans (batch width, words, planes, shape): "
         + ", ".join(f"{k}x{c}" for k, c in sorted(Counter(tuned).items())))
+    stage_tiles = batch.stage_tiles()
+    log(f"stage tiles: {stage_tiles}")
     psi, v, lab = batch.outputs()
     pair_terms = float(sum(float(g.n) ** 2 for g in graphs)) * S
     log(f"planned batch: total nodes {batch.total}, pair-terms/step {pair_terms:.3e}")
@@ -658,6 +660,13 @@ def main():
         "graphs_per_s": len(graphs) / dt,
         "fp64_rechecks_per_step": rechecks,
         "stages": stages,
+        "tiles": {"bfs_plans": {f"{bw}x{nw}x{p}x{sh}": c for (bw, nw, p, sh), c
+                                in sorted(Counter(tuned).items())},
+                  "bfs_plan_key": "sources per batch x words per thread x planes x shape",
+                  "bfs_policy": {"widest_batch": stage_tiles["bfs_widest"],
+                                 "seen_in_registers_first": stage_tiles["bfs_front_first"]},
+                  "hist_waves": {str(k): w for k, w in stage_tiles["hist_waves"].items() if w},
+                  "jump": stage_tiles["jump"]},
         "dominant_kernel": dom,
         "roofline": {
             "bound": "hbm", "kernel": "k_bfs",

@@ -21,7 +21,8 @@ typedef struct qc_batch_s *qc_batch;
 enum {
     QC_BATCH_HIPGRAPH = 1u, /* capture the launch sequence once, replay it afterwards */
     QC_BATCH_FP32C = 2u,    /* potentials in compensated FP32 instead of FP64 accumulation */
-    QC_BATCH_AUTOTUNE = 4u  /* time the candidate BFS launch shapes of every graph, keep the fastest */
+    QC_BATCH_AUTOTUNE = 4u  /* time the candidate launch shapes (BFS planning policy, histogram pass,
+                               pointer jumping, each over the whole batch), keep the fastest */
 };
 
 /*
@@ -40,10 +41,12 @@ enum {
  *              shared by every graph
  *   tie_mode   QC_TIE_STRICT or QC_TIE_MERGE
  *   flags      any of QC_BATCH_HIPGRAPH, QC_BATCH_FP32C, QC_BATCH_AUTOTUNE
- *              (AUTOTUNE: at set-up every graph's search runs once per
- *              candidate launch shape, timed with events on `stream`; the
- *              fastest becomes the graph's plan, for this batch and for the
- *              graph's own later calls. The outputs do not depend on it.)
+ *              (AUTOTUNE: at set-up the batch's searches run under each
+ *              candidate planning policy, timed with events on `stream`;
+ *              the fastest policy's plans stay with the graphs, for this
+ *              batch and for their own later calls; then the whole path runs
+ *              once and the histogram and pointer-jumping shapes are timed,
+ *              see qc_batch_stage_tiles. The outputs do not depend on it.)
  *   stream     stream for any set-up work (graphs whose largest distance is
  *              not yet known run their distances once here, synchronously)
  *   out        host, receives the batch handle
@@ -83,6 +86,31 @@ qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels
  * failure.
  */
 qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *stream);
+
+/*
+ * The launch shapes the batch's stages run with (set by QC_BATCH_AUTOTUNE,
+ * else the defaults); every output pointer is host memory or NULL:
+ *   bfs_widest_out, bfs_front_first_out  the BFS planning policy the graphs'
+ *                    plans follow: the widest batch of sources (16, 32 or
+ *                    64) and whether the seen-in-registers workgroup shape
+ *                    comes first (1) or only the other shapes are used (0);
+ *                    default 32 and 1. Each graph's plan: qc_graph_bfs_plan
+ *   hist_waves_out   host, int32[3] or NULL: wavefronts per workgroup of the
+ *                    histogram pass for row lengths 32, 64 and 128 (0: no
+ *                    graph of that row length); each workgroup counts 32 rows
+ *   jump_global_out  host or NULL: 1 when the pointer jumping runs in global
+ *                    memory, 0 when it runs in LDS
+ * The autotuner times the whole BFS stage of the batch under each planning
+ * policy (widest batch 32, 64 or 16 with the seen-in-registers shape first,
+ * and 32 without it) and keeps the fastest; then, after one run of the whole
+ * path, it times the histogram pass in three shapes (the default wavefront
+ * count, half and twice) and the pointer jumping in LDS and in global
+ * memory, and keeps the fastest of each; a later batch of the same class
+ * (row length, rows, largest graph) in the process reuses these two choices
+ * without timing. The outputs do not depend on any of these choices.
+ */
+qc_status qc_batch_stage_tiles(qc_batch b, int32_t *bfs_widest_out, int32_t *bfs_front_first_out,
+                               int32_t *hist_waves_out, int32_t *jump_global_out);
 
 /* Number of node decisions re-decided in FP64 by the last run (waits). */
 qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out);

@@ -1,9 +1,11 @@
 // Batched form (include/qc_batch.h): grouped launches over many graphs and
 // sigmas, optionally captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <set>
 #include <tuple>
 #include <utility>
@@ -24,6 +26,7 @@ struct KGroup {
     int K = 0;
     NodeJob *d_jobs = nullptr;
     int n_jobs = 0;
+    int variant = 0;   // histogram workgroup shape (launch_hist)
 };
 
 struct qc_batch_s {
@@ -43,6 +46,8 @@ struct qc_batch_s {
     NodeJob *d_ggd_jobs = nullptr;
     int n_ggd_jobs = 0;
     NodeJob *d_jump_jobs = nullptr;
+    int jump_variant = 0;   // pointer jumping in LDS when it fits (0) or in global memory (1)
+    int bfs_policy = 0;     // the BFS planning policy the autotuner kept (0: the planner's)
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -156,64 +161,52 @@ std::vector<NodeJob> xcd_pinned_node_jobs(const std::vector<qc_graph> &graphs)
     return out;
 }
 
-// The autotuner: g's search under each candidate plan, the widest batch of
-// each workgroup shape and the same shape at a half and a quarter of it,
-// one untimed and kTuneReps timed runs each (HIP events on st), all in the
-// plain edge order so that no candidate starts with an order chosen for it;
-// the fastest becomes g's plan and gets its edge order.
 constexpr int kTuneReps = 2;
 
-qc_status autotune_bfs(qc_graph g, hipStream_t st)
+// BFS launch groups of the graphs' current plans: jobs grouped by launch
+// shape (batch width, words per thread, planes, shape), each group's jobs in
+// XCD order. Groups are appended to `out` before their tables are allocated,
+// so on failure the caller frees whatever was allocated.
+qc_status build_bfs_groups(const std::vector<qc_graph> &graphs, std::vector<BfsGroup> &out)
 {
-    std::vector<BfsPlan> cands;
-    auto add = [&](const BfsPlan &p) {
-        if (p.bw <= 0) return;
-        for (const BfsPlan &c : cands)
-            if (c.bw == p.bw && c.nw == p.nw && c.planes == p.planes && c.shape == p.shape) return;
-        cands.push_back(p);
-    };
-    add(g->plan);
-    for (int shape : {kBfsNarrow, kBfsWide1024, kBfsWide, kBfsFront}) {
-        const BfsPlan p = plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape);
-        add(p);
-        if (p.bw > 4) add(plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape, p.bw / 2));
-        if (p.bw > 8) add(plan_bfs_shape(g->n_bfs, g->dmax_bfs, shape, p.bw / 4));
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by_class;
+    for (size_t i = 0; i < graphs.size(); ++i) {
+        const BfsPlan &p = graphs[i]->plan;
+        by_class[std::make_tuple(p.bw, p.nw, p.planes,
+                                 p.shape | (graphs[i]->weighted ? kBfsWeighted : 0))]
+            .push_back((int)i);
     }
-    if (cands.size() < 2) return QC_OK;
-    hipEvent_t e0, e1;
-    QC_HIP(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return QC_E_DEVICE;
-    }
-    qc_status s = plain_edges(g);
-    BfsPlan best = g->plan;
-    float best_ms = 1e30f;
-    for (size_t c = 0; c < cands.size() && s == QC_OK; ++c) {
-        if ((s = set_plan(g, cands[c], false))) break;
-        const BfsPlan &p = g->plan;
-        const int shape = p.shape | (g->weighted ? kBfsWeighted : 0);
-        float total = 0.0f;
-        for (int rep = 0; rep <= kTuneReps && s == QC_OK; ++rep) {
-            hipError_t e = launch_fill_i32(g->d_status, 2, 0, st);
-            if (e == hipSuccess) e = hipEventRecord(e0, st);
-            if (e == hipSuccess) e = launch_bfs(p.bw, p.nw, p.planes, shape, g->d_desc, g->d_bfs_jobs, p.n_batches, st);
-            if (e == hipSuccess) e = hipEventRecord(e1, st);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) s = from_hip(e);
-            if (rep > 0) total += ms;
+    for (auto &kv : by_class) {
+        std::vector<std::vector<BfsJob>> per;
+        std::vector<double> cost;
+        for (int gi : kv.second) {
+            qc_graph g = graphs[gi];
+            // last batch first: the source order puts the farthest-reaching
+            // sources (the longest searches) at the end
+            std::vector<BfsJob> js;
+            for (int bidx = g->plan.n_batches - 1; bidx >= 0; --bidx)
+                js.push_back(BfsJob{gi, bidx * g->plan.bw,
+                                    batch_target(g, bidx * g->plan.bw, g->plan.bw), 0u});
+            per.push_back(js);
+            cost.push_back((double)g->plan.n_batches * (double)(g->nnz + g->n) * (g->dmax + 2));
         }
-        if (s == QC_OK && total < best_ms) {
-            best_ms = total;
-            best = p;
-        }
+        std::vector<BfsJob> jobs = xcd_order(per, cost);
+        BfsGroup grp;
+        grp.bw = std::get<0>(kv.first);
+        grp.nw = std::get<1>(kv.first);
+        grp.planes = std::get<2>(kv.first);
+        grp.shape = std::get<3>(kv.first);
+        grp.n_jobs = (int)jobs.size();
+        out.push_back(grp);
+        QC_TRY(upload_jobs(&out.back().d_jobs, jobs));
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    QC_TRY(s);
-    return set_plan(g, best, true);
+    return QC_OK;
+}
+
+void free_bfs_groups(std::vector<BfsGroup> &gs)
+{
+    for (auto &g : gs) dfree(g.d_jobs);
+    gs.clear();
 }
 
 qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st)
@@ -228,7 +221,7 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
     }
     for (auto &g : b->hist) {
         StageTimer t(QC_STAGE_HIST, st);
-        QC_HIP(launch_hist(g.K, b->d_descs, g.d_jobs, g.n_jobs, st));
+        QC_HIP(launch_hist(g.K, b->d_descs, g.d_jobs, g.n_jobs, st, g.variant));
     }
     for (auto &g : b->pot) {
         StageTimer t(QC_STAGE_POTENTIAL, st);
@@ -244,9 +237,177 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
         int max_n = 0;
         for (qc_graph g : b->graphs) max_n = std::max(max_n, (int)g->n);
         QC_HIP(launch_pointer_jump(b->d_descs, b->d_jump_jobs, (int)b->graphs.size(), 0, S,
-                                   labels_out, total, max_n, st));
+                                   labels_out, total, max_n, st, b->jump_variant));
     }
     return QC_OK;
+}
+
+int batch_max_n(qc_batch b)
+{
+    int m = 0;
+    for (qc_graph g : b->graphs) m = std::max(m, (int)g->n);
+    return m;
+}
+
+int log2_bucket(double x)
+{
+    int k = 0;
+    while (x >= 2.0 && k < 62) {
+        x *= 0.5;
+        ++k;
+    }
+    return k;
+}
+
+// Mean time of kTuneReps launches of `launch` (after one untimed), with
+// HIP events on st; a negative value on failure.
+template <class F>
+float time_launches(F launch, hipStream_t st)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0f;
+    }
+    float ms = -1.0f;
+    hipError_t e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms /= kTuneReps;
+    else ms = -1.0f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+// The stage tiles the autotuner chose, process-wide, by workload class:
+// (stage, histogram row length or 0, log2 of the rows or nodes involved,
+// log2 of the largest graph); a batch of the same class reuses the choice.
+std::mutex g_tiles_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tiles;
+
+// The autotuner's second part: after one eager run of the whole path (so the
+// matrices, histograms and parents are the batch's own and re-running a
+// stage rewrites identical values), time the histogram pass of each row
+// length in its three workgroup shapes and the pointer jumping in LDS and in
+// global memory; keep the fastest, and remember it for the class.
+qc_status autotune_stages(qc_batch b, hipStream_t st)
+{
+    const int S = (int)b->sigmas.size();
+    const int64_t total = b->offsets.back();
+    const int max_n = batch_max_n(b);
+    int32_t *labels = nullptr;
+    QC_TRY(dalloc(&labels, (size_t)S * total));
+    qc_status s = enqueue(b, nullptr, nullptr, labels, st);
+    for (auto &g : b->hist) {
+        if (s != QC_OK) break;
+        const auto key = std::make_tuple(0, g.K, log2_bucket((double)g.n_jobs * 32),
+                                         log2_bucket(max_n));
+        {
+            std::lock_guard<std::mutex> lk(g_tiles_mu);
+            auto it = g_tiles.find(key);
+            if (it != g_tiles.end()) {
+                g.variant = it->second;
+                continue;
+            }
+        }
+        float best = 1e30f;
+        for (int v = 0; v < 3; ++v) {
+            const float ms = time_launches(
+                [&] { return launch_hist(g.K, b->d_descs, g.d_jobs, g.n_jobs, st, v); }, st);
+            if (ms < 0.0f) { s = QC_E_DEVICE; break; }
+            if (ms < best) { best = ms; g.variant = v; }
+        }
+        std::lock_guard<std::mutex> lk(g_tiles_mu);
+        if (s == QC_OK) g_tiles[key] = g.variant;
+    }
+    if (s == QC_OK && max_n <= 40704) {
+        const auto key = std::make_tuple(1, 0, log2_bucket((double)total * S), log2_bucket(max_n));
+        bool cached = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tiles_mu);
+            auto it = g_tiles.find(key);
+            if (it != g_tiles.end()) {
+                b->jump_variant = it->second;
+                cached = true;
+            }
+        }
+        if (!cached) {
+            float best = 1e30f;
+            for (int v = 0; v < 2 && s == QC_OK; ++v) {
+                const float ms = time_launches(
+                    [&] {
+                        return launch_pointer_jump(b->d_descs, b->d_jump_jobs, (int)b->graphs.size(), 0,
+                                                   S, labels, total, max_n, st, v);
+                    },
+                    st);
+                if (ms < 0.0f) s = QC_E_DEVICE;
+                else if (ms < best) { best = ms; b->jump_variant = v; }
+            }
+            std::lock_guard<std::mutex> lk(g_tiles_mu);
+            if (s == QC_OK) g_tiles[key] = b->jump_variant;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    dfree(labels);
+    return s;
+}
+
+// The BFS part of the autotuner, for the whole batch at once: the planner's
+// rule under a few policies (widest batch 32, 64 or 16 sources with the
+// seen-in-registers shape first; 32 without it) gives every graph a plan;
+// each policy's launch groups run the whole BFS stage of the batch, one
+// untimed and kTuneReps timed times (all in the plain edge order, so that no
+// policy starts with an order chosen for it), and the fastest policy's
+// plans stay with the graphs (with their edge order). Timing the stage as
+// the batch runs it counts what timing one graph alone misses: how the
+// graphs' jobs share the GPU.
+struct BfsPolicy { int max_bw; bool front_first; };
+constexpr BfsPolicy kBfsPolicies[] = {{kBfsFullWidth, true}, {64, true}, {16, true},
+                                      {kBfsFullWidth, false}};
+
+qc_status autotune_bfs_batch(qc_batch b, hipStream_t st, int *chosen)
+{
+    *chosen = 0;
+    for (qc_graph g : b->graphs) QC_TRY(plain_edges(g));
+    float best = 1e30f;
+    qc_status s = QC_OK;
+    int pi = 0;
+    for (const BfsPolicy &pol : kBfsPolicies) {
+        for (qc_graph g : b->graphs) {
+            if (s == QC_OK) s = set_plan(g, plan_bfs_policy(g->n_bfs, g->dmax_bfs, pol.max_bw, pol.front_first), false);
+        }
+        std::vector<BfsGroup> groups;
+        if (s == QC_OK) s = build_bfs_groups(b->graphs, groups);
+        if (s == QC_OK) {
+            const float ms = time_launches(
+                [&] {
+                    hipError_t e = hipSuccess;
+                    for (auto &g : groups) {
+                        e = launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, st);
+                        if (e != hipSuccess) break;
+                    }
+                    return e;
+                },
+                st);
+            if (ms < 0.0f) s = QC_E_DEVICE;
+            else if (ms < best) { best = ms; *chosen = pi; }
+        }
+        free_bfs_groups(groups);
+        if (s != QC_OK) break;
+        ++pi;
+    }
+    // the chosen plans, now with their edge order (even after a failure the
+    // graphs keep valid plans)
+    const BfsPolicy &pol = kBfsPolicies[*chosen];
+    for (qc_graph g : b->graphs) {
+        const qc_status r = set_plan(g, plan_bfs_policy(g->n_bfs, g->dmax_bfs, pol.max_bw, pol.front_first), true);
+        if (s == QC_OK) s = r;
+    }
+    return s;
 }
 
 }  // namespace
@@ -298,12 +459,6 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         b->offsets[i + 1] = b->offsets[i] + g->n;
     }
     if (hipStreamSynchronize(st) != hipSuccess) return fail(QC_E_DEVICE);
-    if (flags & QC_BATCH_AUTOTUNE) {
-        for (int i = 0; i < n_graphs; ++i) {
-            qc_status s = autotune_bfs(graphs[i], st);
-            if (s) return fail(s);
-        }
-    }
 
     qc_status s;
     if ((s = dalloc(&b->d_recheck, 1)) || (s = dalloc(&b->d_visits, 2)) ||
@@ -317,41 +472,11 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     }
     if ((s = upload(b->d_descs, descs))) return fail(s);
 
-    // BFS jobs grouped by launch shape (batch width, words per thread,
-    // planes), in XCD order.
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> by_class;
-    for (int i = 0; i < n_graphs; ++i) {
-        const BfsPlan &p = graphs[i]->plan;
-        by_class[std::make_tuple(p.bw, p.nw, p.planes,
-                                 p.shape | (graphs[i]->weighted ? kBfsWeighted : 0))]
-            .push_back(i);
-    }
-    for (auto &kv : by_class) {
-        std::vector<std::vector<BfsJob>> per;
-        std::vector<double> cost;
-        for (int gi : kv.second) {
-            qc_graph g = graphs[gi];
-            // last batch first: the source order puts the farthest-reaching
-            // sources (the longest searches) at the end
-            std::vector<BfsJob> js;
-            for (int bidx = g->plan.n_batches - 1; bidx >= 0; --bidx)
-                js.push_back(BfsJob{gi, bidx * g->plan.bw,
-                                    batch_target(g, bidx * g->plan.bw, g->plan.bw), 0u});
-            per.push_back(js);
-            cost.push_back((double)g->plan.n_batches * (double)(g->nnz + g->n) * (g->dmax + 2));
-        }
-        std::vector<BfsJob> jobs = xcd_order(per, cost);
-        BfsGroup grp;
-        grp.bw = std::get<0>(kv.first);
-        grp.nw = std::get<1>(kv.first);
-        grp.planes = std::get<2>(kv.first);
-        grp.shape = std::get<3>(kv.first);
-        grp.n_jobs = (int)jobs.size();
-        // the group joins the batch before its table is allocated, so that a
-        // failure later in the set-up frees the table with the batch
-        b->bfs.push_back(grp);
-        if ((s = upload_jobs(&b->bfs.back().d_jobs, jobs))) return fail(s);
-    }
+    // BFS jobs grouped by launch shape, in XCD order (with AUTOTUNE, of the
+    // policy that ran the batch's searches fastest)
+    if ((flags & QC_BATCH_AUTOTUNE) && (s = autotune_bfs_batch(b, st, &b->bfs_policy)))
+        return fail(s);
+    if ((s = build_bfs_groups(b->graphs, b->bfs))) return fail(s);
     // Histogram and potential jobs grouped by bin count.
     std::map<int, std::vector<int>> by_k;
     for (int i = 0; i < n_graphs; ++i) by_k[graphs[i]->K].push_back(i);
@@ -386,7 +511,34 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     for (int i = 0; i < n_graphs; ++i)
         if ((s = push_desc(graphs[i], st))) return fail(s);
     if (hipStreamSynchronize(st) != hipSuccess) return fail(QC_E_DEVICE);
+    if (flags & QC_BATCH_AUTOTUNE) {
+        if ((s = autotune_stages(b, st))) return fail(s);
+    } else {
+        // QC_HIST_VARIANT / QC_JUMP_VARIANT (switches for measurements and
+        // tests): a fixed histogram shape (0-2) and jumping variant (0-1)
+        const char *hv = getenv("QC_HIST_VARIANT"), *jv = getenv("QC_JUMP_VARIANT");
+        if (hv && atoi(hv) >= 0 && atoi(hv) <= 2)
+            for (auto &g : b->hist) g.variant = atoi(hv);
+        if (jv && (atoi(jv) == 0 || atoi(jv) == 1)) b->jump_variant = atoi(jv);
+    }
     *out = b;
+    return QC_OK;
+}
+
+qc_status qc_batch_stage_tiles(qc_batch b, int32_t *bfs_widest_out, int32_t *bfs_front_first_out,
+                               int32_t *hist_waves_out, int32_t *jump_global_out)
+{
+    if (!b) return QC_E_INVAL;
+    if (bfs_widest_out) *bfs_widest_out = kBfsPolicies[b->bfs_policy].max_bw;
+    if (bfs_front_first_out) *bfs_front_first_out = kBfsPolicies[b->bfs_policy].front_first ? 1 : 0;
+    if (hist_waves_out) {
+        for (int i = 0; i < 3; ++i) hist_waves_out[i] = 0;
+        for (auto &g : b->hist) {
+            const int slot = g.K == 32 ? 0 : g.K == 64 ? 1 : 2;
+            hist_waves_out[slot] = hist_waves(g.K, g.variant);
+        }
+    }
+    if (jump_global_out) *jump_global_out = (b->jump_variant == 1 || batch_max_n(b) > 40704) ? 1 : 0;
     return QC_OK;
 }
 

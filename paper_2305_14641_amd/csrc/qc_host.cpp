@@ -400,6 +400,24 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw)
     return none;
 }
 
+BfsPlan plan_bfs_policy(int32_t n, int32_t dmax, int max_bw, bool front_first)
+{
+    // With front_first, the shape with seen in registers (pull from the
+    // frontier at the two-field LDS budget) when the graph fits it at the
+    // widest width; otherwise the widest batch wins, at equal width more
+    // threads per workgroup, and pulling from the frontier (fewer atomics)
+    // before pulling from seen.
+    const BfsPlan front = plan_bfs_shape(n, dmax, kBfsFront, max_bw);
+    if (front_first && front.bw == max_bw) return front;
+    BfsPlan best = front;
+    if (!front_first) best.bw = 0;
+    for (int shape : {kBfsNarrow, kBfsWide1024, kBfsWide}) {
+        const BfsPlan p = plan_bfs_shape(n, dmax, shape, max_bw);
+        if (p.bw > best.bw) best = p;
+    }
+    return best.bw > 0 ? best : front;
+}
+
 BfsPlan plan_bfs(int32_t n, int32_t dmax)
 {
     // QC_BFS_SHAPE=<shape> (a switch for measurements and tests): that
@@ -412,18 +430,9 @@ BfsPlan plan_bfs(int32_t n, int32_t dmax)
         }
     }
     // At most kBfsFullWidth sources per batch (timed on the sweep graphs,
-    // 32-source batches beat 64-source ones on every graph). The shape with
-    // seen in registers (pull from the frontier at the two-field LDS budget)
-    // first when the graph fits it at that width; otherwise the widest batch
-    // wins, at equal width more threads per workgroup, and pulling from the
-    // frontier (fewer atomics) before pulling from seen.
-    BfsPlan best = plan_bfs_shape(n, dmax, kBfsFront, kBfsFullWidth);
-    if (best.bw == kBfsFullWidth) return best;
-    for (int shape : {kBfsNarrow, kBfsWide1024, kBfsWide}) {
-        const BfsPlan p = plan_bfs_shape(n, dmax, shape, kBfsFullWidth);
-        if (p.bw > best.bw) best = p;
-    }
-    return best;
+    // 32-source batches beat 64-source ones), the seen-in-registers shape
+    // first.
+    return plan_bfs_policy(n, dmax, kBfsFullWidth, true);
 }
 
 static void split_f32(double x, float &hi, float &lo)

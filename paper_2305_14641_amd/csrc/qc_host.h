@@ -86,6 +86,9 @@ qc_status subdivide_weighted(int32_t n, const std::vector<int32_t> &rp,
 // seen-in-registers shapes only with 4-5 planes).
 struct BfsPlan { int bw; int nw; int planes; int n_batches; int shape; };
 BfsPlan plan_bfs(int32_t n, int32_t dmax);
+// The planner's rule with another widest batch (max_bw) and with or without
+// the seen-in-registers shape first (the batch autotuner's candidates).
+BfsPlan plan_bfs_policy(int32_t n, int32_t dmax, int max_bw, bool front_first);
 // The plan of one shape alone (bw = 0 when n does not fit).
 BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw = 64);
 int planes_for(int32_t dmax);

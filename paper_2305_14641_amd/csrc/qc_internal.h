@@ -157,8 +157,12 @@ hipError_t launch_bfs_bw(int nw, int planes, int shape, const GraphDev *graphs, 
 
 // Histograms of the resident distance rows (one job = hist_rows_per_job(K)
 // rows of one graph). `K` is the shared bin count (32, 64 or 128).
+// `variant` picks the workgroup shape (hist_waves): 0 default, 1 half, 2
+// double the wavefronts per workgroup.
 hipError_t launch_hist(int K, const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
-                       hipStream_t stream);
+                       hipStream_t stream, int variant = 0);
+// Wavefronts per workgroup of histogram variant `variant` for row length K.
+int hist_waves(int K, int variant);
 
 // psi/V of every (node, sigma); one job = kNodesPerJob nodes of one graph.
 // Optional caller outputs: out[out_off + s*out_ld + (i - i0_of_graph)].
@@ -173,10 +177,10 @@ hipError_t launch_ggd_parent(int tie_mode, const GraphDev *graphs, const NodeJob
 // Pointer jumping, one workgroup per (graph job, sigma); labels of sigma
 // sigma_base + y go to labels_base + y*labels_ld + job.out_off. max_n: the
 // largest node count among the jobs' graphs (up to 40,704 the rounds run in
-// LDS).
+// LDS unless `variant` is 1: always in global memory).
 hipError_t launch_pointer_jump(const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
                                int sigma_base, int n_sig, int32_t *labels_base,
-                               int64_t labels_ld, int max_n, hipStream_t stream);
+                               int64_t labels_ld, int max_n, hipStream_t stream, int variant = 0);
 
 // Stage timing (qc_timing.cpp): Timer brackets one launch when enabled.
 class StageTimer {

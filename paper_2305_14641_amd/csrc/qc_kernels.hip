@@ -169,14 +169,39 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     }
 }
 
+// Workgroup shapes of the histogram pass per row length: the 32 rows of a
+// job split over W wavefronts of 32 / W rows each (the LDS bins are
+// W x (K + 1) x 256 bytes). Variant 0 is the default (about 66 KB of bins);
+// 1 halves the wavefronts, 2 doubles them.
+int hist_waves(int K, int variant)
+{
+    const int base = (K == 32) ? 8 : (K == 64) ? 4 : 2;
+    return variant == 1 ? base / 2 : variant == 2 ? base * 2 : base;
+}
+
+template <int K, int W>
+static void launch_hist_w(const GraphDev *graphs, const NodeJob *jobs, int n_jobs, hipStream_t stream)
+{
+    static_assert(W * (32 / W) == 32, "a job is 32 rows");
+    hipLaunchKernelGGL((k_hist<K, W, 32 / W>), dim3(n_jobs), dim3(W * 64), 0, stream, graphs, jobs);
+}
+
 hipError_t launch_hist(int K, const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
-                       hipStream_t stream)
+                       hipStream_t stream, int variant)
 {
     if (n_jobs <= 0) return hipSuccess;
-    switch (K) {
-    case 32: hipLaunchKernelGGL((k_hist<32, 8, 4>), dim3(n_jobs), dim3(512), 0, stream, graphs, jobs); break;
-    case 64: hipLaunchKernelGGL((k_hist<64, 4, 8>), dim3(n_jobs), dim3(256), 0, stream, graphs, jobs); break;
-    case 128: hipLaunchKernelGGL((k_hist<128, 2, 16>), dim3(n_jobs), dim3(128), 0, stream, graphs, jobs); break;
+    if (variant < 0 || variant > 2) return hipErrorInvalidValue;
+    const int w = hist_waves(K, variant);
+    switch (K * 100 + w) {
+    case 3204: launch_hist_w<32, 4>(graphs, jobs, n_jobs, stream); break;
+    case 3208: launch_hist_w<32, 8>(graphs, jobs, n_jobs, stream); break;
+    case 3216: launch_hist_w<32, 16>(graphs, jobs, n_jobs, stream); break;
+    case 6402: launch_hist_w<64, 2>(graphs, jobs, n_jobs, stream); break;
+    case 6404: launch_hist_w<64, 4>(graphs, jobs, n_jobs, stream); break;
+    case 6408: launch_hist_w<64, 8>(graphs, jobs, n_jobs, stream); break;
+    case 12801: launch_hist_w<128, 1>(graphs, jobs, n_jobs, stream); break;
+    case 12802: launch_hist_w<128, 2>(graphs, jobs, n_jobs, stream); break;
+    case 12804: launch_hist_w<128, 4>(graphs, jobs, n_jobs, stream); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -516,27 +541,40 @@ __device__ __forceinline__ double fp64_v(const GraphDev &G, int s, int node)
                        G.inv_a[s]);
 }
 
-// The FP64 decision for node i at sigma s: among the neighbours whose FP32 V
-// lies within the bound of the lowest one (m1), the lowest canonical FP64 V,
-// compared with the node's own.
-__device__ __noinline__ int fp64_decide(int tie_mode, const GraphDev &G, int s, int i, float m1)
+// The FP64 decision for node i (thread t of the descent's order) at sigma
+// s: among the neighbours whose FP32 V lies within the bound of the lowest
+// one (m1), the lowest canonical FP64 V, compared with the node's own. The
+// neighbours come from the thread's sliced list in CSR order, kGgdPad per
+// round with their loads in flight together (a hub re-deciding among many
+// twin leaves would otherwise wait for two dependent loads per neighbour);
+// the first of equal FP64 minima wins, as in a plain CSR scan.
+__device__ __noinline__ int fp64_decide(int tie_mode, const GraphDev &G, int s, int t, int i,
+                                        float m1)
 {
+    const int n = G.n;
     const float *__restrict__ V = G.v;
-    const int32_t *__restrict__ col = G.col;
-    const int e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
     const double vi64 = fp64_v(G, s, i);
+    const int deg = G.sell_deg[t];
+    const int32_t *__restrict__ sc = G.sell_col + G.sell_off[t >> 6] + (t & 63);
     double bv = DBL_MAX;
     int best = -1;
-    for (int e = e0; e < e1; ++e) {
-        const int j = col[e];
-        const float vj = V[v_index(G.n, s, j)];
-        if (vj - m1 <= kTieTau * vj) {
-            const double d = fp64_v(G, s, j);
-            if (d < bv) {
-                bv = d;
-                best = j;
+    for (int k = 0; k < deg; k += kGgdPad) {
+        int j[kGgdPad];
+        float vj[kGgdPad];
+#pragma unroll
+        for (int u = 0; u < kGgdPad; ++u) j[u] = sc[64 * (k + u)];
+#pragma unroll
+        for (int u = 0; u < kGgdPad; ++u) vj[u] = V[v_index(n, s, j[u])];
+        double d[kGgdPad];
+#pragma unroll
+        for (int u = 0; u < kGgdPad; ++u)
+            d[u] = (k + u < deg && vj[u] - m1 <= kTieTau * vj[u]) ? fp64_v(G, s, j[u]) : DBL_MAX;
+#pragma unroll
+        for (int u = 0; u < kGgdPad; ++u)
+            if (d[u] < bv) {
+                bv = d[u];
+                best = j[u];
             }
-        }
     }
     if (tie_mode == 0) return (bv < vi64) ? best : i;
     return (bv < vi64 || (bv == vi64 && best < i)) ? best : i;
@@ -635,7 +673,7 @@ __global__ __launch_bounds__(256) void k_ggd_parent(int tie_mode, const GraphDev
                 if (!ambiguous) {
                     parent = (m1[q] < vi[q]) ? j1[q] : i;
                 } else {
-                    parent = fp64_decide(tie_mode, G, s, i, m1[q]);
+                    parent = fp64_decide(tie_mode, G, s, t, i, m1[q]);
                     rechecked[q] = true;
                 }
             }
@@ -738,11 +776,14 @@ __global__ __launch_bounds__(1024) void k_jump_lds(const GraphDev *__restrict__ 
 
 hipError_t launch_pointer_jump(const GraphDev *graphs, const NodeJob *jobs, int n_jobs,
                                int sigma_base, int n_sig, int32_t *labels_base,
-                               int64_t labels_ld, int max_n, hipStream_t stream)
+                               int64_t labels_ld, int max_n, hipStream_t stream, int variant)
 {
     if (n_jobs <= 0 || n_sig <= 0) return hipSuccess;
     const dim3 grid(n_jobs, n_sig), block(1024);
-    if (max_n <= 20480)   // 80 KB of LDS: two workgroups per CU
+    if (variant == 1)     // in global memory whatever the size
+        hipLaunchKernelGGL(k_jump, grid, block, 0, stream, graphs, jobs, sigma_base, labels_base,
+                           labels_ld);
+    else if (max_n <= 20480)   // 80 KB of LDS: two workgroups per CU
         hipLaunchKernelGGL(k_jump_lds<20480>, grid, block, 0, stream, graphs, jobs, sigma_base,
                            labels_base, labels_ld);
     else if (max_n <= 40704)

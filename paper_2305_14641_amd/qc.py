@@ -49,7 +49,7 @@ EXPORTED = [
     "qc_timing_read", "qc_potential_dense", "qc_debug_alloc_fault", "qc_get_potential64",
     "qc_cluster", "qc_cluster_noalloc",
     "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
-    "qc_batch_search_stats", "qc_batch_sweep_bf16", "qc_batch_destroy",
+    "qc_batch_search_stats", "qc_batch_sweep_bf16", "qc_batch_stage_tiles", "qc_batch_destroy",
 ]
 
 BATCH_HIPGRAPH = 1
@@ -129,6 +129,7 @@ def lib():
         L.qc_batch_node_offsets.argtypes = [P, P]
         L.qc_batch_run.argtypes = [P, P, P, P, P]
         L.qc_batch_sweep_bf16.argtypes = [P, P, P, P]
+        L.qc_batch_stage_tiles.argtypes = [P, P, P, P, P]
         L.qc_batch_recheck_count.argtypes = [P, P]
         L.qc_batch_search_stats.argtypes = [P, P, P]
         L.qc_batch_destroy.argtypes = [P]
@@ -397,6 +398,17 @@ class Batch:
         c = ctypes.c_int64(0)
         _check(lib().qc_batch_recheck_count(self._h, ctypes.byref(c)), "qc_batch_recheck_count")
         return int(c.value)
+
+    def stage_tiles(self) -> dict:
+        """Launch shapes of the stages: the BFS planning policy (widest batch,
+        seen-in-registers shape first), the histogram pass (wavefronts per
+        workgroup by row length) and the pointer jumping (LDS or global)."""
+        bw, ff, j = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        w = (ctypes.c_int32 * 3)()
+        _check(lib().qc_batch_stage_tiles(self._h, ctypes.byref(bw), ctypes.byref(ff), w,
+                                          ctypes.byref(j)), "qc_batch_stage_tiles")
+        return {"bfs_widest": bw.value, "bfs_front_first": bool(ff.value),
+                "hist_waves": {32: w[0], 64: w[1], 128: w[2]}, "jump": "global" if j.value else "lds"}
 
     def search_stats(self) -> tuple:
         """(edge visits, LDS bytes gathered) of the last run's searches."""

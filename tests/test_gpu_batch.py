@@ -107,9 +107,9 @@ def test_batch_sigma_counts(setup, S):
 
 
 def test_batch_autotune_changes_no_output(setup):
-    """QC_BATCH_AUTOTUNE times the candidate BFS launch shapes of each graph
-    and keeps the fastest; the outputs are bitwise those of the planner's
-    shapes."""
+    """QC_BATCH_AUTOTUNE times the batch's searches under each planning
+    policy and the histogram and jumping shapes, and keeps the fastest; the
+    outputs are bitwise those of the planner's shapes."""
     torch, qc, graphs, sigmas = setup
     ha = [qc.Graph.from_graph(g) for g in graphs]
     hb = [qc.Graph.from_graph(g) for g in graphs]
@@ -122,11 +122,54 @@ def test_batch_autotune_changes_no_output(setup):
     torch.cuda.synchronize()
     for x, y in zip(oa, ob):
         assert x.cpu().numpy().tobytes() == y.cpu().numpy().tobytes()
+    tiles = ba.stage_tiles()
+    assert tiles["hist_waves"][32] in (4, 8, 16) and tiles["jump"] in ("lds", "global")
+    assert (tiles["bfs_widest"], tiles["bfs_front_first"]) in ((32, True), (64, True), (16, True),
+                                                                (32, False))
+    # every graph follows the kept policy
+    for G in ha:
+        assert G.bfs_plan()[0] <= tiles["bfs_widest"]
+    assert bb.stage_tiles()["bfs_widest"] == 32 and bb.stage_tiles()["bfs_front_first"]
     # the tuned plan stays with the graph: its own calls agree too
     d = torch.empty((graphs[3].n, graphs[3].n), dtype=torch.int8, device="cuda")
     ha[3].distances(d)
     dist, _ = oracle.distances(graphs[3].n, graphs[3].row_ptr, graphs[3].col)
     np.testing.assert_array_equal(d.cpu().numpy(), dist)
+    ba.close()
+    bb.close()
+
+
+@pytest.mark.parametrize("env", [{"QC_HIST_VARIANT": "1"}, {"QC_HIST_VARIANT": "2"},
+                                 {"QC_JUMP_VARIANT": "1"}], ids=lambda e: ",".join(f"{k}={v}" for k, v in e.items()))
+def test_batch_stage_shapes_change_no_output(setup, monkeypatch, env):
+    """The histogram pass in each workgroup shape and the pointer jumping in
+    global memory give the bytes of the default shapes, and the batch reports
+    the shapes it runs with."""
+    torch, qc, graphs, sigmas = setup
+    ha = [qc.Graph.from_graph(g) for g in graphs]
+    ba = qc.Batch(ha, sigmas, hipgraph=True)
+    for k, val in env.items():
+        monkeypatch.setenv(k, val)
+    hb = [qc.Graph.from_graph(g) for g in graphs]
+    bb = qc.Batch(hb, sigmas, hipgraph=True)
+    tiles = bb.stage_tiles()
+    if "QC_HIST_VARIANT" in env:
+        want = {32: (4, 16), 64: (2, 8), 128: (1, 4)}
+        for K, w in tiles["hist_waves"].items():
+            if w:
+                assert w == want[K][int(env["QC_HIST_VARIANT"]) - 1]
+    else:
+        assert tiles["jump"] == "global"
+    assert ba.stage_tiles()["jump"] == "lds"
+    oa, ob = ba.outputs(), bb.outputs()
+    for _ in range(2):
+        ba.run(*oa)
+        bb.run(*ob)
+    torch.cuda.synchronize()
+    for x, y in zip(oa, ob):
+        assert x.cpu().numpy().tobytes() == y.cpu().numpy().tobytes()
+    for G, H in zip(ha, hb):
+        assert torch.equal(G.histograms(), H.histograms())
     ba.close()
     bb.close()
 
