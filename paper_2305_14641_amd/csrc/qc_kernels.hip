@@ -230,23 +230,56 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
     e = (a - (s - z)) + (b - z);
 }
 
-template <int K>
-__device__ __forceinline__ void canonical_sums(const int32_t (&h)[K], int kmax,
-                                               const double *__restrict__ w, double &s2,
-                                               double &s1)
+// A read-only table whose loads are all uniform: through the constant
+// address space they become scalar loads into scalar registers, which
+// leaves the vector registers to the counts and sums.
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// A copy of a count the compiler cannot see through: its conversion to FP64
+// is redone inside the loop over sigma groups instead of being hoisted out
+// of it, where the 2 x K converted values (and their k^2 multiples) would
+// hold most of the registers.
+__device__ __forceinline__ int32_t fresh(int32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// The canonical FP64 sums of Q consecutive sigmas from s, independent
+// chains each in ascending k: S2 += h_k * w_k and S1 += (k^2 h_k) * w_k from
+// +0.0, every product and sum rounded on its own. Bins go in chunks of 8 up
+// to the largest distance (a uniform exit: every node of a job belongs to
+// one graph) with a chunk's weights loaded together; bins of the last chunk
+// past the largest distance hold a zero count, whose +0.0 terms leave the
+// sums unchanged. w64 rows have K entries.
+template <int K, int Q>
+__device__ __forceinline__ void canonical_group(const int32_t (&h)[K], int kmax,
+                                                const cdouble *w64, int s, double (&a2)[Q],
+                                                double (&a1)[Q])
 {
 #pragma clang fp contract(off)
-    double a2 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (k < kmax) {
-            const double hk = (double)h[k];
-            a2 = a2 + hk * w[k];
-            a1 = a1 + ((double)(k * k) * hk) * w[k];
+    for (int q = 0; q < Q; ++q) a2[q] = a1[q] = 0.0;
+#pragma unroll
+    for (int kc = 0; kc < K; kc += 8) {
+        if (kc >= kmax) break;
+        double w[8][Q];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) w[j][q] = w64[(int64_t)(s + q) * K + kc + j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc + j;
+            const double hk = (double)fresh(h[k]);
+            const double kk = (double)(k * k) * hk;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                a2[q] = a2[q] + hk * w[j][q];
+                a1[q] = a1[q] + kk * w[j][q];
+            }
         }
     }
-    s2 = a2;
-    s1 = a1;
 }
 
 __device__ __forceinline__ double canonical_ratio(double s1, double s2, double inv_a)
@@ -270,61 +303,58 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
     if (i >= n) return;
     const int kmax = min(G.dmax + 1, K);
     const int32_t *__restrict__ hrow = G.hist + (int64_t)i * G.K;
+    // the whole row (K == G.K: every graph of a launch has this row length)
+    // in 16-byte loads, then the bins past the largest distance zeroed
     int32_t h[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) h[k] = (k < kmax) ? hrow[k] : 0;
+    for (int c = 0; c < K / 4; ++c) {
+        const u32x4 q = ((global_u4)hrow)[c];
+        h[4 * c + 0] = (int32_t)q.x;
+        h[4 * c + 1] = (int32_t)q.y;
+        h[4 * c + 2] = (int32_t)q.z;
+        h[4 * c + 3] = (int32_t)q.w;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) h[k] = (k < kmax) ? h[k] : 0;
 
+    // one (node, sigma) result: FP32 psi and V for the caller (or resident
+    // psi when the caller takes none), the resident V, and with FP64
+    // accumulation the resident FP64 V
+    auto store = [&](int s, float psi32, float v32) {
+        const int64_t o = (int64_t)s * n + i;
+        G.v[v_index(n, s, i)] = v32;
+        const int64_t ou = job.out_off + (int64_t)s * out_ld + i;
+        if (psi_out) psi_out[ou] = psi32;
+        else G.psi[o] = psi32;
+        if (v_out) v_out[ou] = v32;
+    };
     int s = 0;
-    if constexpr (PREC == 0 && K <= 32) {
-        // kPotSigmas sigmas at a time: their sums are independent chains
-        // (each in the canonical order), so the FP64 adds of one sigma wait
-        // on their predecessors while the others' issue (rows of 64 or 128
-        // bins would need more registers than there are)
-        for (; s + kPotSigmas <= G.n_sigmas; s += kPotSigmas) {
-            double a2[kPotSigmas], a1[kPotSigmas];
+    if constexpr (PREC == 0) {
+        // kPotSigmas sigmas at a time (rows of up to 64 bins): their sums
+        // are independent chains (each in the canonical order), so the FP64
+        // adds of one sigma wait on their predecessors while the others'
+        // issue
+        constexpr int Q = (K <= 64) ? kPotSigmas : 1;
+        const cdouble *w64 = (const cdouble *)G.w64;
+        for (; s + Q <= G.n_sigmas; s += Q) {
+            double a2[Q], a1[Q];
+            canonical_group<K, Q>(h, kmax, w64, s, a2, a1);
 #pragma unroll
-            for (int q = 0; q < kPotSigmas; ++q) a2[q] = a1[q] = 0.0;
-            {
-#pragma clang fp contract(off)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (k < kmax) {
-                        const double hk = (double)h[k];
-                        const double kk = (double)(k * k) * hk;
-#pragma unroll
-                        for (int q = 0; q < kPotSigmas; ++q) {
-                            const double wk = G.w64[(int64_t)(s + q) * G.K + k];
-                            a2[q] = a2[q] + hk * wk;
-                            a1[q] = a1[q] + kk * wk;
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kPotSigmas; ++q) {
-                const int64_t o = (int64_t)(s + q) * n + i;
+            for (int q = 0; q < Q; ++q) {
                 const double v64 = canonical_ratio(a1[q], a2[q], G.inv_a[s + q]);
-                const float psi32 = (float)a2[q], v32 = (float)v64;
-                G.v64[o] = v64;
-                G.v[v_index(n, s + q, i)] = v32;
-                const int64_t ou = job.out_off + (int64_t)(s + q) * out_ld + i;
-                if (psi_out) psi_out[ou] = psi32;
-                else G.psi[o] = psi32;   // resident only when the caller takes none
-                if (v_out) v_out[ou] = v32;
+                G.v64[(int64_t)(s + q) * n + i] = v64;
+                store(s + q, (float)a2[q], (float)v64);
             }
         }
-    }
-    for (; s < G.n_sigmas; ++s) {
-        float psi32, v32;
-        const int64_t o = (int64_t)s * n + i;
-        if constexpr (PREC == 0) {
-            double s2, s1;
-            canonical_sums<K>(h, kmax, G.w64 + (int64_t)s * G.K, s2, s1);
-            const double v64 = canonical_ratio(s1, s2, G.inv_a[s]);
-            psi32 = (float)s2;
-            v32 = (float)v64;
-            G.v64[o] = v64;
-        } else {
+        for (; s < G.n_sigmas; ++s) {
+            double a2[1], a1[1];
+            canonical_group<K, 1>(h, kmax, w64, s, a2, a1);
+            const double v64 = canonical_ratio(a1[0], a2[0], G.inv_a[s]);
+            G.v64[(int64_t)s * n + i] = v64;
+            store(s, (float)a2[0], (float)v64);
+        }
+    } else {
+        for (; s < G.n_sigmas; ++s) {
             const float *__restrict__ wt = G.w32c + (int64_t)s * G.K * 4;
             float ps = 0.f, pe = 0.f, qs = 0.f, qe = 0.f;
 #pragma unroll
@@ -349,14 +379,8 @@ __global__ __launch_bounds__(256) void k_potential(const GraphDev *__restrict__ 
             }
             const float p = ps + pe;
             const float q = qs + qe;
-            psi32 = p;
-            v32 = __fdiv_rn(q, p);
+            store(s, p, __fdiv_rn(q, p));
         }
-        G.v[v_index(n, s, i)] = v32;
-        const int64_t ou = job.out_off + (int64_t)s * out_ld + i;
-        if (psi_out) psi_out[ou] = psi32;
-        else G.psi[o] = psi32;   // resident only when the caller takes none
-        if (v_out) v_out[ou] = v32;
     }
 }
 

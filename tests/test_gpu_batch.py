@@ -146,6 +146,7 @@ def test_batch_stage_shapes_change_no_output(setup, monkeypatch, env):
     global memory give the bytes of the default shapes, and the batch reports
     the shapes it runs with."""
     torch, qc, graphs, sigmas = setup
+    graphs = graphs + [gg.path_graph(40)]   # and a row length of 64 bins
     ha = [qc.Graph.from_graph(g) for g in graphs]
     ba = qc.Batch(ha, sigmas, hipgraph=True)
     for k, val in env.items():
@@ -224,6 +225,8 @@ def test_batch_bf16_sweep(setup):
     written)."""
     torch, qc, graphs, sigmas = setup
     sig = gg.sigmas_c4() + [1.0, 2.0]   # 34 sigmas: a second group of weight columns
+    # a 40-node path adds a second row length (64 bins): a second launch
+    graphs = graphs + [gg.path_graph(40)]
     handles = [qc.Graph.from_graph(g) for g in graphs]
     b = qc.Batch(handles, sig, hipgraph=True)
     psi, v, lab = b.outputs()
