@@ -237,6 +237,34 @@ def test_cluster_arguments_checked_on_host():
         assert call() == qc.QC_E_DEVICE
 
 
+def test_noalloc_arguments_and_size_checked_on_host():
+    """qc_cluster_noalloc validates its arguments and refuses a problem beyond
+    its fixed scratch (QC_E_TOO_LARGE) before touching any device."""
+    L = qc.lib()
+    P = ctypes.c_void_p
+    sig = np.array([1.0])
+
+    def call(g, sig_=sig, tie=0, dist=None, labels=P(64)):
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+        col = np.ascontiguousarray(g.col, dtype=np.int32)
+        return L.qc_cluster_noalloc(g.n, col.shape[0], rp.ctypes.data_as(P), col.ctypes.data_as(P),
+                                    sig_.ctypes.data_as(P), sig_.shape[0], tie, dist, None, None,
+                                    labels, None)
+
+    small = gg.config1()
+    assert call(small, labels=None) == qc.QC_E_INVAL
+    assert call(small, tie=2) == qc.QC_E_INVAL
+    assert call(small, dist=P(65)) == qc.QC_E_INVAL
+    assert call(small, sig_=np.array([-1.0])) == qc.QC_E_INVAL
+    big = gg.star_graph(8199)           # its 67 MB matrix alone exceeds the 64 MiB scratch
+    assert big.n * big.n > qc.NOALLOC_SCRATCH_BYTES
+    assert call(big) == qc.QC_E_TOO_LARGE
+    assert L.qc_status_str(qc.QC_E_TOO_LARGE).startswith(b"QC_E_TOO_LARGE")
+    if qc.device_count() == 0:
+        assert call(small) == qc.QC_E_DEVICE
+        assert call(big, dist=P(1 << 20)) == qc.QC_E_DEVICE   # fits once the caller holds the matrix
+
+
 def test_hooks_and_new_entry_points_reject_bad_handles():
     L = qc.lib()
     live = ctypes.c_int64(-1)
@@ -245,6 +273,8 @@ def test_hooks_and_new_entry_points_reject_bad_handles():
     assert live.value >= 0
     assert L.qc_get_potential64(None, ctypes.c_void_p(64), None) == qc.QC_E_INVAL
     assert L.qc_batch_search_stats(None, None, None) == qc.QC_E_INVAL
+    assert L.qc_batch_sweep_bf16(None, ctypes.c_void_p(64), ctypes.c_void_p(64), None) == qc.QC_E_INVAL
+    assert L.qc_batch_stage_tiles(None, None, None, None, None) == qc.QC_E_INVAL
     assert L.qc_server_cancel(None, 1) == qc.QC_E_INVAL
 
 
