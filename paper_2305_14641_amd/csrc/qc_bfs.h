@@ -203,6 +203,13 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     constexpr int NWW = (BW == 64) ? NW / 2 : NW;   // words of type T per thread
     constexpr int kLdsWords = NWW * kT;
     constexpr int kLevels = (P >= 7) ? kMaxDist : ((1 << P) - 1);  // largest encodable level
+    // Word ownership: with 32-bit words and a multiple of 4 per thread, a
+    // thread owns runs of 4 consecutive words, (g kT + tid) * 4 + i for its
+    // g-th run (V = 4): phase B reads and writes them with 16-byte LDS
+    // accesses, and with one node per word the decode holds 4 consecutive
+    // nodes and transposes their bytes in registers. Otherwise word
+    // j kT + tid (V = 1).
+    constexpr int V = (BW <= 32 && NWW % 4 == 0) ? 4 : 1;
 
     // The fields share one LDS array, the field the pull gathers from first
     // (LDS address 0, so a gather's address is the column's word offset):
@@ -237,12 +244,23 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
         for (int p = 0; p < P; ++p) plane[j][p] = 0;
 
     // Level 0: each source has reached itself (distance 0: no plane bits).
+    if constexpr (V == 4) {
+        const uint4 z = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (int j = 0; j < NWW; ++j) {
-        const int w = j * kT + tid;
-        if constexpr (!SREG) seen[w] = 0;
-        if constexpr (!WIDE) front[w] = 0;
-        nxt[w] = 0;
+        for (int g = 0; g < NWW / 4; ++g) {
+            const int w0 = (g * kT + tid) * 4;
+            if constexpr (!SREG) *(uint4 *)(seen + w0) = z;
+            if constexpr (!WIDE) *(uint4 *)(front + w0) = z;
+            *(uint4 *)(nxt + w0) = z;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NWW; ++j) {
+            const int w = j * kT + tid;
+            if constexpr (!SREG) seen[w] = 0;
+            if constexpr (!WIDE) front[w] = 0;
+            nxt[w] = 0;
+        }
     }
     if (tid < nb) srcs[tid] = G.src[s0 + tid];
     if (tid == 0) found_pairs = (uint32_t)nb;   // level 0: every source itself
@@ -261,8 +279,19 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     if constexpr (SREG) {
         // the owners take the sources' bits (level 0 = the frontier) into
         // their registers
+        if constexpr (V == 4) {
 #pragma unroll
-        for (int j = 0; j < NWW; ++j) seen_r[j] = front[j * kT + tid];
+            for (int g = 0; g < NWW / 4; ++g) {
+                const uint4 f = *(const uint4 *)(front + (g * kT + tid) * 4);
+                seen_r[4 * g + 0] = f.x;
+                seen_r[4 * g + 1] = f.y;
+                seen_r[4 * g + 2] = f.z;
+                seen_r[4 * g + 3] = f.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NWW; ++j) seen_r[j] = front[j * kT + tid];
+        }
     }
     uint32_t found_before = (uint32_t)nb;
 
@@ -316,6 +345,43 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
         //    still exactly this level's new pairs.
         uint32_t cnt = 0;
         const int tb = opaque(tid);
+        if constexpr (V == 4) {
+            // runs of 4 words; a run may reach past nwords into words no
+            // edge delivers to (zero in nxt, so nothing changes there)
+#pragma unroll
+            for (int g = 0; g < NWW / 4; ++g) {
+                const int w0 = (g * kT + tb) * 4;
+                if (w0 < nwords) {
+                    const uint4 raw4 = *(const uint4 *)(nxt + w0);
+                    uint4 sw4;
+                    if constexpr (SREG)
+                        sw4 = make_uint4(seen_r[4 * g], seen_r[4 * g + 1], seen_r[4 * g + 2],
+                                         seen_r[4 * g + 3]);
+                    else
+                        sw4 = *(const uint4 *)(seen + w0);
+                    const uint4 y4 = make_uint4(raw4.x & ~sw4.x, raw4.y & ~sw4.y, raw4.z & ~sw4.z,
+                                                raw4.w & ~sw4.w);
+                    if constexpr (!WIDE) *(uint4 *)(front + w0) = y4;
+                    const uint4 ns4 = make_uint4(sw4.x | y4.x, sw4.y | y4.y, sw4.z | y4.z, sw4.w | y4.w);
+                    if constexpr (SREG) {
+                        seen_r[4 * g + 0] = ns4.x;
+                        seen_r[4 * g + 1] = ns4.y;
+                        seen_r[4 * g + 2] = ns4.z;
+                        seen_r[4 * g + 3] = ns4.w;
+                    } else if (y4.x | y4.y | y4.z | y4.w) {
+                        *(uint4 *)(seen + w0) = ns4;
+                    }
+                    const uint32_t y[4] = {y4.x, y4.y, y4.z, y4.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        cnt += (uint32_t)__popc(y[i]);
+#pragma unroll
+                        for (int p = 0; p < P; ++p)
+                            if ((level >> p) & 1) plane[4 * g + i][p] |= (T)y[i];   // uniform branch
+                    }
+                }
+            }
+        } else
 #pragma unroll
         for (int j = 0; j < NWW; ++j) {
             const int w = j * kT + tb;
@@ -367,9 +433,71 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     // words of the graph's own nodes (the first n)
     const int own_words = WEIGHTED ? (n + W::kPer - 1) / W::kPer : nwords;
     const int td = opaque(tid);
+    if constexpr (V == 4 && W::kPer == 1) {
+        // runs of 4 consecutive nodes v0..v0+3: for each group of 4 sources
+        // the 4 nodes' dwords (byte k = source b0 + k) are transposed in
+        // registers into one dword per source (byte i = node v0 + i) and
+        // stored with one 4-byte store each, so a wavefront's store covers
+        // 256 consecutive bytes of a row
 #pragma unroll
-    for (int j = 0; j < NWW; ++j) {
-        const int w = j * kT + td;
+        for (int g = 0; g < NWW / 4; ++g) {
+            const int v0 = (g * kT + td) * 4;
+            if (v0 < own_words) {
+                T sw[4], lp[4][P];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    sw[i] = SREG ? seen_r[4 * g + i] : seen[v0 + i];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) lp[i][p] = plane[4 * g + i][p];
+                }
+#pragma unroll 1
+                for (int t = 0; t < BW / 4; ++t) {
+                    const int b0 = 4 * t;
+                    uint32_t d[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        d[i] = spread4((uint32_t)(~sw[i] >> (4 * t)) & 0xFu) * 0xFFu;
+#pragma unroll
+                        for (int p = 0; p < P; ++p)
+                            d[i] |= spread4((uint32_t)(lp[i][p] >> (4 * t)) & 0xFu) << p;
+                    }
+                    if (b0 + 4 <= nb && v0 + 3 < n) {
+                        // 4 x 4 byte transpose: pairs of nodes, then pairs of pairs
+                        const uint32_t t0 = __builtin_amdgcn_perm(d[1], d[0], 0x05010400u);
+                        const uint32_t t1 = __builtin_amdgcn_perm(d[1], d[0], 0x07030602u);
+                        const uint32_t t2 = __builtin_amdgcn_perm(d[3], d[2], 0x05010400u);
+                        const uint32_t t3 = __builtin_amdgcn_perm(d[3], d[2], 0x07030602u);
+                        const uint32_t o[4] = {__builtin_amdgcn_perm(t2, t0, 0x05040100u),
+                                               __builtin_amdgcn_perm(t2, t0, 0x07060302u),
+                                               __builtin_amdgcn_perm(t3, t1, 0x05040100u),
+                                               __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
+                        const ulonglong2 r01 = *(const ulonglong2 *)(rows + b0);
+                        const ulonglong2 r23 = *(const ulonglong2 *)(rows + b0 + 2);
+                        gbyte *const r[4] = {(gbyte *)r01.x, (gbyte *)r01.y, (gbyte *)r23.x,
+                                             (gbyte *)r23.y};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) *(gu32 *)(r[k] + v0) = o[k];
+                    } else {
+                        const ulonglong2 r01 = *(const ulonglong2 *)(rows + b0);
+                        const ulonglong2 r23 = *(const ulonglong2 *)(rows + b0 + 2);
+                        gbyte *const r[4] = {(gbyte *)r01.x, (gbyte *)r01.y, (gbyte *)r23.x,
+                                             (gbyte *)r23.y};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                if (v0 + i < n && b0 + k < nb)
+                                    r[k][v0 + i] = (int8_t)((d[i] >> (8 * k)) & 0xFFu);
+                    }
+                }
+            }
+        }
+    } else
+#pragma unroll
+    for (int jv = 0; jv < NWW; ++jv) {
+        // word j of the thread, at its position in the V-word runs
+        const int j = jv;
+        const int w = (V == 4) ? ((j / 4) * kT + td) * 4 + (j % 4) : j * kT + td;
         if (w < own_words) {
             const T sw = SREG ? seen_r[j] : seen[w];
             T lp[P];
