@@ -10,8 +10,10 @@ pointer jumping to labels. Inputs (CSR) are resident before timing starts.
 
 Metric: pair-terms per second, a pair-term being one (i, j, sigma) term of the
 potential sum (sum over graphs of N^2 times the number of sigmas), for the
-batched form replayed as one HIP graph. Also reported: graphs/s, the plain
-per-graph path on the same GPU, per-stage kernel times, the search's edge
+batched form replayed as one HIP graph (the stages after the search of each
+search launch's graphs run on a second stream beside the next searches).
+Also reported: graphs/s, the plain per-graph path on the same GPU, per-stage
+kernel times (from a pass with every stage in stream order), the search's edge
 visits and LDS bytes gathered, the roofline of the dominant kernel, the
 smaller workloads (one 200-node graph's latency, the 2,708- and 19,717-node
 graphs end to end, psi/V from a resident matrix), the serving form on the
@@ -532,8 +534,11 @@ def main():
     edge_visits, lds_gathered = batch.search_stats()
     lab_host = lab.cpu().numpy()
 
-    # -- per-kernel device time: the same launches, not captured, with events --
-    batch_nograph = qc.Batch(handles, sigmas, tie_mode=qc.TIE_STRICT, hipgraph=False)
+    # -- per-kernel device time: the same launches, not captured, with events,
+    #    every stage in stream order (the timed steps above run the stages
+    #    after the search beside the searches, where a kernel's duration
+    #    would include the GPU it shares) --
+    batch_nograph = qc.Batch(handles, sigmas, tie_mode=qc.TIE_STRICT, hipgraph=False, serial=True)
     batch_nograph.run(psi, v, lab)
     torch.cuda.synchronize()
     qc.timing_enable(True)
@@ -666,7 +671,8 @@ def main():
                   "bfs_policy": {"widest_batch": stage_tiles["bfs_widest"],
                                  "seen_in_registers_first": stage_tiles["bfs_front_first"]},
                   "hist_waves": {str(k): w for k, w in stage_tiles["hist_waves"].items() if w},
-                  "jump": stage_tiles["jump"]},
+                  "jump": stage_tiles["jump"],
+                  "stages_beside_searches": stage_tiles["overlap"]},
         "dominant_kernel": dom,
         "roofline": {
             "bound": "hbm", "kernel": "k_bfs",

@@ -21,8 +21,9 @@ typedef struct qc_batch_s *qc_batch;
 enum {
     QC_BATCH_HIPGRAPH = 1u, /* capture the launch sequence once, replay it afterwards */
     QC_BATCH_FP32C = 2u,    /* potentials in compensated FP32 instead of FP64 accumulation */
-    QC_BATCH_AUTOTUNE = 4u  /* time the candidate launch shapes (BFS planning policy, histogram pass,
+    QC_BATCH_AUTOTUNE = 4u, /* time the candidate launch shapes (BFS planning policy, histogram pass,
                                pointer jumping, each over the whole batch), keep the fastest */
+    QC_BATCH_SERIAL = 8u    /* run every stage in stream order on the caller's stream (see below) */
 };
 
 /*
@@ -40,7 +41,8 @@ enum {
  *   sigmas     host, double[n_sigmas], each finite and > 0 (1..1024 values),
  *              shared by every graph
  *   tie_mode   QC_TIE_STRICT or QC_TIE_MERGE
- *   flags      any of QC_BATCH_HIPGRAPH, QC_BATCH_FP32C, QC_BATCH_AUTOTUNE
+ *   flags      any of QC_BATCH_HIPGRAPH, QC_BATCH_FP32C, QC_BATCH_AUTOTUNE,
+ *              QC_BATCH_SERIAL
  *              (AUTOTUNE: at set-up the batch's searches run under each
  *              candidate planning policy, timed with events on `stream`;
  *              the fastest policy's plans stay with the graphs, for this
@@ -67,6 +69,14 @@ qc_status qc_batch_node_offsets(qc_batch b, int64_t *offsets);
  *   labels_out      device, int32[n_sigmas][total_nodes], same layout, required
  * With QC_BATCH_HIPGRAPH the first run captures the launches on `stream`
  * and every later run with the same output pointers replays that graph.
+ * When the searches take more than one launch (graphs of different launch
+ * shapes), the distance histograms of the graphs one search launch covers
+ * run on a second stream the batch owns as soon as that launch has
+ * finished, beside the following searches; `stream` waits for them before
+ * the potentials (Eq. 2 / Eq. 7) and Algorithms 2-3, so the run is ordered
+ * on `stream` like any other work (and a captured graph holds both
+ * branches). QC_BATCH_SERIAL keeps every launch on `stream`, in stream order
+ * (timing one stage at a time). The outputs are the same either way.
  */
 qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
                        void *stream);
@@ -100,6 +110,10 @@ qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *st
  *                    graph of that row length); each workgroup counts 32 rows
  *   jump_global_out  host or NULL: 1 when the pointer jumping runs in global
  *                    memory, 0 when it runs in LDS
+ *   overlap_out      host or NULL: 1 when the histograms run beside the
+ *                    searches (see qc_batch_run), 0 when every stage runs in
+ *                    stream order (2: every stage after the search beside the
+ *                    searches, a measurement switch)
  * The autotuner times the whole BFS stage of the batch under each planning
  * policy (widest batch 32, 64 or 16 with the seen-in-registers shape first,
  * and 32 without it) and keeps the fastest; then, after one run of the whole
@@ -110,7 +124,7 @@ qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *st
  * without timing. The outputs do not depend on any of these choices.
  */
 qc_status qc_batch_stage_tiles(qc_batch b, int32_t *bfs_widest_out, int32_t *bfs_front_first_out,
-                               int32_t *hist_waves_out, int32_t *jump_global_out);
+                               int32_t *hist_waves_out, int32_t *jump_global_out, int32_t *overlap_out);
 
 /* Number of node decisions re-decided in FP64 by the last run (waits). */
 qc_status qc_batch_recheck_count(qc_batch b, int64_t *count_out);

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <set>
@@ -21,12 +22,26 @@ struct BfsGroup {
     int shape = 0;
     BfsJob *d_jobs = nullptr;
     int n_jobs = 0;
+    std::vector<int> graphs;   // the batch's graphs whose searches this launch runs
+    double rows_bytes = 0.0;   // their distance matrices' bytes (sum of n^2)
 };
 struct KGroup {
     int K = 0;
     NodeJob *d_jobs = nullptr;
     int n_jobs = 0;
     int variant = 0;   // histogram workgroup shape (launch_hist)
+};
+// The stages after the search for a set of the batch's graphs: histograms,
+// then (unless `rest` is false) potentials, descent and pointer jumping.
+struct Stages {
+    int bfs_group = -1;        // the BFS launch whose matrices it reads (-1: all of them)
+    bool rest = true;
+    std::vector<KGroup> hist, pot;
+    NodeJob *d_ggd_jobs = nullptr;
+    int n_ggd_jobs = 0;
+    NodeJob *d_jump_jobs = nullptr;
+    int n_jump_jobs = 0;
+    int max_n = 0;             // largest node count among the graphs
 };
 
 struct qc_batch_s {
@@ -41,11 +56,18 @@ struct qc_batch_s {
     unsigned long long *d_recheck = nullptr;
     unsigned long long *d_visits = nullptr;   // [2] the last run's BFS edge visits, bytes gathered
     std::vector<BfsGroup> bfs;
-    std::vector<KGroup> hist;
-    std::vector<KGroup> pot;
-    NodeJob *d_ggd_jobs = nullptr;
-    int n_ggd_jobs = 0;
-    NodeJob *d_jump_jobs = nullptr;
+    // Stage sets in launch order. Serial form: one over every graph, on the
+    // caller's stream after the last search. Overlapped forms: one per BFS
+    // launch on `side`, started by that launch's event ev_bfs[i] so that it
+    // runs beside the next searches (histograms only, followed by one set of
+    // the remaining stages over every graph on the caller's stream; or every
+    // stage); the caller's stream waits for ev_join.
+    int overlap = 0;   // 0 serial, 1 histograms overlapped, 2 every stage overlapped
+    std::vector<Stages> stages;
+    std::vector<KGroup> pot_all;   // potential jobs of every graph by bin count (BF16 sweep)
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> ev_bfs;
+    hipEvent_t ev_join = nullptr;
     int jump_variant = 0;   // pointer jumping in LDS when it fits (0) or in global memory (1)
     int bfs_policy = 0;     // the BFS planning policy the autotuner kept (0: the planner's)
 
@@ -68,10 +90,16 @@ void free_batch(qc_batch b)
     dfree(b->d_recheck);
     dfree(b->d_visits);
     for (auto &g : b->bfs) dfree(g.d_jobs);
-    for (auto &g : b->hist) dfree(g.d_jobs);
-    for (auto &g : b->pot) dfree(g.d_jobs);
-    dfree(b->d_ggd_jobs);
-    dfree(b->d_jump_jobs);
+    for (auto &c : b->stages) {
+        for (auto &g : c.hist) dfree(g.d_jobs);
+        for (auto &g : c.pot) dfree(g.d_jobs);
+        dfree(c.d_ggd_jobs);
+        dfree(c.d_jump_jobs);
+    }
+    for (auto &g : b->pot_all) dfree(g.d_jobs);
+    for (hipEvent_t e : b->ev_bfs) (void)hipEventDestroy(e);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
 }
 
@@ -197,6 +225,8 @@ qc_status build_bfs_groups(const std::vector<qc_graph> &graphs, std::vector<BfsG
         grp.planes = std::get<2>(kv.first);
         grp.shape = std::get<3>(kv.first);
         grp.n_jobs = (int)jobs.size();
+        grp.graphs = kv.second;
+        for (int gi : kv.second) grp.rows_bytes += (double)graphs[gi]->n * graphs[gi]->n;
         out.push_back(grp);
         QC_TRY(upload_jobs(&out.back().d_jobs, jobs));
     }
@@ -209,35 +239,65 @@ void free_bfs_groups(std::vector<BfsGroup> &gs)
     gs.clear();
 }
 
-qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st)
+// One stage set on stream `st`.
+qc_status run_stages(qc_batch b, const Stages &c, float *psi_out, float *v_out, int32_t *labels_out,
+                     hipStream_t st)
 {
     const int S = (int)b->sigmas.size();
     const int64_t total = b->offsets.back();
-    QC_HIP(launch_fill_u64(b->d_recheck, 1, st));
-    QC_HIP(launch_fill_u64(b->d_visits, 2, st));
-    for (auto &g : b->bfs) {
-        StageTimer t(QC_STAGE_BFS, st);
-        QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, st));
-    }
-    for (auto &g : b->hist) {
+    for (auto &g : c.hist) {
         StageTimer t(QC_STAGE_HIST, st);
         QC_HIP(launch_hist(g.K, b->d_descs, g.d_jobs, g.n_jobs, st, g.variant));
     }
-    for (auto &g : b->pot) {
+    if (!c.rest) return QC_OK;
+    for (auto &g : c.pot) {
         StageTimer t(QC_STAGE_POTENTIAL, st);
         QC_HIP(launch_potential(b->precision, g.K, b->d_descs, g.d_jobs, g.n_jobs, psi_out, v_out,
                                 total, st));
     }
     {
         StageTimer t(QC_STAGE_GGD, st);
-        QC_HIP(launch_ggd_parent((int)b->tie, b->d_descs, b->d_ggd_jobs, b->n_ggd_jobs, 0, S, st));
+        QC_HIP(launch_ggd_parent((int)b->tie, b->d_descs, c.d_ggd_jobs, c.n_ggd_jobs, 0, S, st));
     }
     {
         StageTimer t(QC_STAGE_JUMP, st);
-        int max_n = 0;
-        for (qc_graph g : b->graphs) max_n = std::max(max_n, (int)g->n);
-        QC_HIP(launch_pointer_jump(b->d_descs, b->d_jump_jobs, (int)b->graphs.size(), 0, S,
-                                   labels_out, total, max_n, st, b->jump_variant));
+        QC_HIP(launch_pointer_jump(b->d_descs, c.d_jump_jobs, c.n_jump_jobs, 0, S, labels_out, total,
+                                   c.max_n, st, b->jump_variant));
+    }
+    return QC_OK;
+}
+
+qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st)
+{
+    QC_HIP(launch_fill_u64(b->d_recheck, 1, st));
+    QC_HIP(launch_fill_u64(b->d_visits, 2, st));
+    for (size_t i = 0; i < b->bfs.size(); ++i) {
+        const BfsGroup &g = b->bfs[i];
+        {
+            StageTimer t(QC_STAGE_BFS, st);
+            QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, st));
+        }
+        if (b->overlap) QC_HIP(hipEventRecord(b->ev_bfs[i], st));
+    }
+    bool forked = false;
+    for (const Stages &c : b->stages) {
+        if (c.bfs_group < 0) {
+            // after every search: on the caller's stream, joined with the side stream first
+            if (forked) {
+                QC_HIP(hipEventRecord(b->ev_join, b->side));
+                QC_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
+                forked = false;
+            }
+            QC_TRY(run_stages(b, c, psi_out, v_out, labels_out, st));
+        } else {
+            QC_HIP(hipStreamWaitEvent(b->side, b->ev_bfs[c.bfs_group], 0));
+            forked = true;
+            QC_TRY(run_stages(b, c, psi_out, v_out, labels_out, b->side));
+        }
+    }
+    if (forked) {
+        QC_HIP(hipEventRecord(b->ev_join, b->side));
+        QC_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
     }
     return QC_OK;
 }
@@ -284,73 +344,59 @@ float time_launches(F launch, hipStream_t st)
 }
 
 // The stage tiles the autotuner chose, process-wide, by workload class:
-// (stage, histogram row length or 0, log2 of the rows or nodes involved,
-// log2 of the largest graph); a batch of the same class reuses the choice.
+// (stage, overlapped form, log2 of the batch's nodes, log2 of the largest
+// graph); a batch of the same class reuses the choice.
 std::mutex g_tiles_mu;
 std::map<std::tuple<int, int, int, int>, int> g_tiles;
 
 // The autotuner's second part: after one eager run of the whole path (so the
 // matrices, histograms and parents are the batch's own and re-running a
-// stage rewrites identical values), time the histogram pass of each row
-// length in its three workgroup shapes and the pointer jumping in LDS and in
-// global memory; keep the fastest, and remember it for the class.
+// stage rewrites identical values), time whole steps with the histogram pass
+// in each of its three workgroup shapes, then with pointer jumping in LDS and
+// in global memory; keep the fastest, and remember it for the class. Whole
+// steps, because in the overlapped forms a stage's best shape is the one
+// that shares the GPU best with the searches beside it.
 qc_status autotune_stages(qc_batch b, hipStream_t st)
 {
+    StageTimingOff quiet;
     const int S = (int)b->sigmas.size();
     const int64_t total = b->offsets.back();
     const int max_n = batch_max_n(b);
     int32_t *labels = nullptr;
     QC_TRY(dalloc(&labels, (size_t)S * total));
     qc_status s = enqueue(b, nullptr, nullptr, labels, st);
-    for (auto &g : b->hist) {
-        if (s != QC_OK) break;
-        const auto key = std::make_tuple(0, g.K, log2_bucket((double)g.n_jobs * 32),
-                                         log2_bucket(max_n));
+    auto step = [&] {
+        const qc_status r = enqueue(b, nullptr, nullptr, labels, st);
+        return r == QC_OK ? hipSuccess : hipErrorUnknown;
+    };
+    auto set_hist = [&](int v) {
+        for (auto &c : b->stages)
+            for (auto &g : c.hist) g.variant = v;
+    };
+    auto tune = [&](int stage, int n_variants, const std::function<void(int)> &apply) {
+        const auto key = std::make_tuple(stage, b->overlap, log2_bucket((double)total), log2_bucket(max_n));
         {
             std::lock_guard<std::mutex> lk(g_tiles_mu);
             auto it = g_tiles.find(key);
             if (it != g_tiles.end()) {
-                g.variant = it->second;
-                continue;
+                apply(it->second);
+                return;
             }
         }
         float best = 1e30f;
-        for (int v = 0; v < 3; ++v) {
-            const float ms = time_launches(
-                [&] { return launch_hist(g.K, b->d_descs, g.d_jobs, g.n_jobs, st, v); }, st);
-            if (ms < 0.0f) { s = QC_E_DEVICE; break; }
-            if (ms < best) { best = ms; g.variant = v; }
+        int chosen = 0;
+        for (int v = 0; v < n_variants && s == QC_OK; ++v) {
+            apply(v);
+            const float ms = time_launches(step, st);
+            if (ms < 0.0f) s = QC_E_DEVICE;
+            else if (ms < best) { best = ms; chosen = v; }
         }
+        apply(chosen);
         std::lock_guard<std::mutex> lk(g_tiles_mu);
-        if (s == QC_OK) g_tiles[key] = g.variant;
-    }
-    if (s == QC_OK && max_n <= 40704) {
-        const auto key = std::make_tuple(1, 0, log2_bucket((double)total * S), log2_bucket(max_n));
-        bool cached = false;
-        {
-            std::lock_guard<std::mutex> lk(g_tiles_mu);
-            auto it = g_tiles.find(key);
-            if (it != g_tiles.end()) {
-                b->jump_variant = it->second;
-                cached = true;
-            }
-        }
-        if (!cached) {
-            float best = 1e30f;
-            for (int v = 0; v < 2 && s == QC_OK; ++v) {
-                const float ms = time_launches(
-                    [&] {
-                        return launch_pointer_jump(b->d_descs, b->d_jump_jobs, (int)b->graphs.size(), 0,
-                                                   S, labels, total, max_n, st, v);
-                    },
-                    st);
-                if (ms < 0.0f) s = QC_E_DEVICE;
-                else if (ms < best) { best = ms; b->jump_variant = v; }
-            }
-            std::lock_guard<std::mutex> lk(g_tiles_mu);
-            if (s == QC_OK) g_tiles[key] = b->jump_variant;
-        }
-    }
+        if (s == QC_OK) g_tiles[key] = chosen;
+    };
+    if (s == QC_OK) tune(0, 3, set_hist);
+    if (s == QC_OK && max_n <= 40704) tune(1, 2, [&](int v) { b->jump_variant = v; });
     (void)hipStreamSynchronize(st);
     dfree(labels);
     return s;
@@ -420,7 +466,8 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
 {
     if (!graphs || !out || n_graphs < 1 || n_graphs > 65536) return QC_E_INVAL;
     if (tie_mode > QC_TIE_MERGE) return QC_E_INVAL;
-    if (flags & ~(uint32_t)(QC_BATCH_HIPGRAPH | QC_BATCH_FP32C | QC_BATCH_AUTOTUNE)) return QC_E_INVAL;
+    if (flags & ~(uint32_t)(QC_BATCH_HIPGRAPH | QC_BATCH_FP32C | QC_BATCH_AUTOTUNE | QC_BATCH_SERIAL))
+        return QC_E_INVAL;
     QC_TRY(validate_sigmas(sigmas, n_sigmas));
     std::set<qc_graph> seen;
     for (int i = 0; i < n_graphs; ++i) {
@@ -477,36 +524,116 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     if ((flags & QC_BATCH_AUTOTUNE) && (s = autotune_bfs_batch(b, st, &b->bfs_policy)))
         return fail(s);
     if ((s = build_bfs_groups(b->graphs, b->bfs))) return fail(s);
-    // Histogram and potential jobs grouped by bin count.
-    std::map<int, std::vector<int>> by_k;
-    for (int i = 0; i < n_graphs; ++i) by_k[graphs[i]->K].push_back(i);
-    for (auto &kv : by_k) {
-        const int K = kv.first;
-        std::vector<NodeJob> hj, pj;
-        for (int gi : kv.second) {
-            const int n = graphs[gi]->n;
-            for (int r = 0; r < n; r += hist_rows_per_job(K)) hj.push_back(NodeJob{gi, r, 0});
-            for (int r = 0; r < n; r += kNodesPerJob) pj.push_back(NodeJob{gi, r, b->offsets[gi]});
+    // The histograms overlap the searches when the searches take more than
+    // one launch (QC_BATCH_OVERLAP=2: every stage after the search, per
+    // search launch; 0: none; switches for measurements and tests). Every
+    // stage overlapped measured slower: the descent and jumping of one
+    // launch's few graphs are latency-bound chains that, queued behind one
+    // another on the side stream, outlast the searches.
+    {
+        const char *ov = getenv("QC_BATCH_OVERLAP");
+        const int want = (ov && atoi(ov) >= 0 && atoi(ov) <= 2) ? atoi(ov) : 1;
+        b->overlap = (b->bfs.size() > 1 && !(flags & QC_BATCH_SERIAL)) ? want : 0;
+    }
+    if (b->overlap) {
+        // the launch with the fewest matrix bytes last: its stages are the
+        // only ones no search runs beside
+        std::stable_sort(b->bfs.begin(), b->bfs.end(), [](const BfsGroup &x, const BfsGroup &y) {
+            return x.rows_bytes > y.rows_bytes;
+        });
+        if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) {
+            b->side = nullptr;
+            return fail(QC_E_DEVICE);
         }
-        KGroup h, p;
-        h.K = p.K = K;
-        h.n_jobs = (int)hj.size();
-        p.n_jobs = (int)pj.size();
-        b->hist.push_back(h);
-        b->pot.push_back(p);
-        if ((s = upload_jobs(&b->hist.back().d_jobs, hj)) || (s = upload_jobs(&b->pot.back().d_jobs, pj)))
-            return fail(s);
+        for (size_t i = 0; i <= b->bfs.size(); ++i) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(QC_E_DEVICE);
+            if (i < b->bfs.size()) b->ev_bfs.push_back(e);
+            else b->ev_join = e;
+        }
     }
-    std::vector<qc_graph> gv(graphs, graphs + n_graphs);
-    std::vector<NodeJob> gj = xcd_pinned_node_jobs(gv), jj;
-    const bool pinned = !gj.empty();
-    for (int gi = 0; gi < n_graphs; ++gi) {
-        if (!pinned)
-            for (int r = 0; r < graphs[gi]->n; r += kNodesPerJob) gj.push_back(NodeJob{gi, r, 0});
-        jj.push_back(NodeJob{gi, 0, b->offsets[gi]});
+    // One stage set over graphs `gis`: histogram and potential jobs grouped
+    // by bin count, descent jobs (pinned to XCDs when the graphs allow it),
+    // one jumping job per graph. Appended before its tables are allocated,
+    // so a failure leaves nothing unowned.
+    auto add_stages = [&](const std::vector<int> &gis, int bfs_group, bool with_hist, bool rest) -> qc_status {
+        b->stages.emplace_back();
+        Stages &c = b->stages.back();
+        c.bfs_group = bfs_group;
+        c.rest = rest;
+        std::map<int, std::vector<int>> by_k;
+        for (int gi : gis) {
+            by_k[graphs[gi]->K].push_back(gi);
+            c.max_n = std::max(c.max_n, (int)graphs[gi]->n);
+        }
+        for (auto &kv : by_k) {
+            const int K = kv.first;
+            std::vector<NodeJob> hj, pj;
+            for (int gi : kv.second) {
+                const int n = graphs[gi]->n;
+                if (with_hist)
+                    for (int r = 0; r < n; r += hist_rows_per_job(K)) hj.push_back(NodeJob{gi, r, 0});
+                if (rest)
+                    for (int r = 0; r < n; r += kNodesPerJob) pj.push_back(NodeJob{gi, r, b->offsets[gi]});
+            }
+            if (with_hist) {
+                KGroup h;
+                h.K = K;
+                h.n_jobs = (int)hj.size();
+                // sixteen wavefronts per 32 rows where the searches run beside:
+                // their LDS keeps searches off a histogram's CU (measured faster)
+                h.variant = b->overlap ? 2 : 0;
+                c.hist.push_back(h);
+                QC_TRY(upload_jobs(&c.hist.back().d_jobs, hj));
+            }
+            if (rest) {
+                KGroup pg;
+                pg.K = K;
+                pg.n_jobs = (int)pj.size();
+                c.pot.push_back(pg);
+                QC_TRY(upload_jobs(&c.pot.back().d_jobs, pj));
+            }
+        }
+        if (!rest) return QC_OK;
+        std::vector<qc_graph> gv;
+        for (int gi : gis) gv.push_back(graphs[gi]);
+        std::vector<NodeJob> gj = xcd_pinned_node_jobs(gv), jj;
+        // pinned jobs index gv; the kernels index the batch's descriptors
+        for (auto &j : gj) j.g = gis[j.g];
+        const bool pinned = !gj.empty();
+        for (int gi : gis) {
+            if (!pinned)
+                for (int r = 0; r < graphs[gi]->n; r += kNodesPerJob) gj.push_back(NodeJob{gi, r, 0});
+            jj.push_back(NodeJob{gi, 0, b->offsets[gi]});
+        }
+        c.n_ggd_jobs = (int)gj.size();
+        c.n_jump_jobs = (int)jj.size();
+        QC_TRY(upload_jobs(&c.d_ggd_jobs, gj));
+        return upload_jobs(&c.d_jump_jobs, jj);
+    };
+    std::vector<int> all(n_graphs);
+    for (int i = 0; i < n_graphs; ++i) all[i] = i;
+    {
+        std::map<int, std::vector<int>> by_k;
+        for (int gi : all) by_k[graphs[gi]->K].push_back(gi);
+        for (auto &kv : by_k) {
+            std::vector<NodeJob> pj;
+            for (int gi : kv.second)
+                for (int r = 0; r < graphs[gi]->n; r += kNodesPerJob) pj.push_back(NodeJob{gi, r, b->offsets[gi]});
+            KGroup pg;
+            pg.K = kv.first;
+            pg.n_jobs = (int)pj.size();
+            b->pot_all.push_back(pg);
+            if ((s = upload_jobs(&b->pot_all.back().d_jobs, pj))) return fail(s);
+        }
     }
-    b->n_ggd_jobs = (int)gj.size();
-    if ((s = upload_jobs(&b->d_ggd_jobs, gj)) || (s = upload_jobs(&b->d_jump_jobs, jj))) return fail(s);
+    if (b->overlap == 0) {
+        if ((s = add_stages(all, -1, true, true))) return fail(s);
+    } else {
+        for (size_t i = 0; i < b->bfs.size(); ++i)
+            if ((s = add_stages(b->bfs[i].graphs, (int)i, true, b->overlap == 2))) return fail(s);
+        if (b->overlap == 1 && (s = add_stages(all, -1, false, true))) return fail(s);
+    }
     // Each graph's own descriptor now reflects the batch's sigma list.
     for (int i = 0; i < n_graphs; ++i)
         if ((s = push_desc(graphs[i], st))) return fail(s);
@@ -518,7 +645,8 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         // tests): a fixed histogram shape (0-2) and jumping variant (0-1)
         const char *hv = getenv("QC_HIST_VARIANT"), *jv = getenv("QC_JUMP_VARIANT");
         if (hv && atoi(hv) >= 0 && atoi(hv) <= 2)
-            for (auto &g : b->hist) g.variant = atoi(hv);
+            for (auto &c : b->stages)
+                for (auto &g : c.hist) g.variant = atoi(hv);
         if (jv && (atoi(jv) == 0 || atoi(jv) == 1)) b->jump_variant = atoi(jv);
     }
     *out = b;
@@ -526,19 +654,21 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
 }
 
 qc_status qc_batch_stage_tiles(qc_batch b, int32_t *bfs_widest_out, int32_t *bfs_front_first_out,
-                               int32_t *hist_waves_out, int32_t *jump_global_out)
+                               int32_t *hist_waves_out, int32_t *jump_global_out, int32_t *overlap_out)
 {
     if (!b) return QC_E_INVAL;
     if (bfs_widest_out) *bfs_widest_out = kBfsPolicies[b->bfs_policy].max_bw;
     if (bfs_front_first_out) *bfs_front_first_out = kBfsPolicies[b->bfs_policy].front_first ? 1 : 0;
     if (hist_waves_out) {
         for (int i = 0; i < 3; ++i) hist_waves_out[i] = 0;
-        for (auto &g : b->hist) {
-            const int slot = g.K == 32 ? 0 : g.K == 64 ? 1 : 2;
-            hist_waves_out[slot] = hist_waves(g.K, g.variant);
-        }
+        for (auto &c : b->stages)
+            for (auto &g : c.hist) {
+                const int slot = g.K == 32 ? 0 : g.K == 64 ? 1 : 2;
+                hist_waves_out[slot] = hist_waves(g.K, g.variant);
+            }
     }
     if (jump_global_out) *jump_global_out = (b->jump_variant == 1 || batch_max_n(b) > 40704) ? 1 : 0;
+    if (overlap_out) *overlap_out = b->overlap;
     return QC_OK;
 }
 
@@ -588,7 +718,7 @@ qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *st
     if (!b || !psi_out || !v_out) return QC_E_INVAL;
     hipStream_t st = as_stream(stream);
     const int64_t total = b->offsets.back();
-    for (auto &g : b->pot) {
+    for (auto &g : b->pot_all) {
         StageTimer t(QC_STAGE_POTENTIAL, st);
         QC_HIP(launch_potential(QC_PREC_BF16, g.K, b->d_descs, g.d_jobs, g.n_jobs, psi_out, v_out,
                                 total, st));

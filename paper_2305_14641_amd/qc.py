@@ -55,6 +55,7 @@ EXPORTED = [
 BATCH_HIPGRAPH = 1
 BATCH_FP32C = 2
 BATCH_AUTOTUNE = 4
+BATCH_SERIAL = 8
 
 EXPORTED += ["qc_request_footprint", "qc_server_create", "qc_server_submit", "qc_server_poll",
              "qc_server_wait", "qc_server_cancel", "qc_server_stats", "qc_server_destroy"]
@@ -129,7 +130,7 @@ def lib():
         L.qc_batch_node_offsets.argtypes = [P, P]
         L.qc_batch_run.argtypes = [P, P, P, P, P]
         L.qc_batch_sweep_bf16.argtypes = [P, P, P, P]
-        L.qc_batch_stage_tiles.argtypes = [P, P, P, P, P]
+        L.qc_batch_stage_tiles.argtypes = [P, P, P, P, P, P]
         L.qc_batch_recheck_count.argtypes = [P, P]
         L.qc_batch_search_stats.argtypes = [P, P, P]
         L.qc_batch_destroy.argtypes = [P]
@@ -348,12 +349,12 @@ class Batch:
     """Many graphs x one sigma list in grouped launches (include/qc_batch.h)."""
 
     def __init__(self, graphs, sigmas, tie_mode=TIE_STRICT, hipgraph=True, fp32c=False,
-                 autotune=False, stream=None):
+                 autotune=False, serial=False, stream=None):
         self.graphs = list(graphs)          # keeps the Graph handles alive
         arr = (ctypes.c_void_p * len(self.graphs))(*[G.handle.value for G in self.graphs])
         sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).reshape(-1))
         flags = ((BATCH_HIPGRAPH if hipgraph else 0) | (BATCH_FP32C if fp32c else 0)
-                 | (BATCH_AUTOTUNE if autotune else 0))
+                 | (BATCH_AUTOTUNE if autotune else 0) | (BATCH_SERIAL if serial else 0))
         h = ctypes.c_void_p()
         _check(lib().qc_batch_create(arr, len(self.graphs), sig.ctypes.data_as(ctypes.c_void_p),
                                      sig.shape[0], int(tie_mode), flags, _stream_ptr(stream),
@@ -402,13 +403,15 @@ class Batch:
     def stage_tiles(self) -> dict:
         """Launch shapes of the stages: the BFS planning policy (widest batch,
         seen-in-registers shape first), the histogram pass (wavefronts per
-        workgroup by row length) and the pointer jumping (LDS or global)."""
-        bw, ff, j = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        workgroup by row length), the pointer jumping (LDS or global) and
+        which stages run beside the searches ("all", "histograms", "none")."""
+        bw, ff, j, ov = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         w = (ctypes.c_int32 * 3)()
         _check(lib().qc_batch_stage_tiles(self._h, ctypes.byref(bw), ctypes.byref(ff), w,
-                                          ctypes.byref(j)), "qc_batch_stage_tiles")
+                                          ctypes.byref(j), ctypes.byref(ov)), "qc_batch_stage_tiles")
         return {"bfs_widest": bw.value, "bfs_front_first": bool(ff.value),
-                "hist_waves": {32: w[0], 64: w[1], 128: w[2]}, "jump": "global" if j.value else "lds"}
+                "hist_waves": {32: w[0], 64: w[1], 128: w[2]}, "jump": "global" if j.value else "lds",
+                "overlap": {0: "none", 1: "histograms", 2: "all"}[ov.value]}
 
     def search_stats(self) -> tuple:
         """(edge visits, LDS bytes gathered) of the last run's searches."""

@@ -274,7 +274,7 @@ def test_hooks_and_new_entry_points_reject_bad_handles():
     assert L.qc_get_potential64(None, ctypes.c_void_p(64), None) == qc.QC_E_INVAL
     assert L.qc_batch_search_stats(None, None, None) == qc.QC_E_INVAL
     assert L.qc_batch_sweep_bf16(None, ctypes.c_void_p(64), ctypes.c_void_p(64), None) == qc.QC_E_INVAL
-    assert L.qc_batch_stage_tiles(None, None, None, None, None) == qc.QC_E_INVAL
+    assert L.qc_batch_stage_tiles(None, None, None, None, None, None) == qc.QC_E_INVAL
     assert L.qc_server_cancel(None, 1) == qc.QC_E_INVAL
 
 

@@ -175,6 +175,50 @@ def test_batch_stage_shapes_change_no_output(setup, monkeypatch, env):
     bb.close()
 
 
+@pytest.mark.parametrize("form", ["histograms", "all", "histograms-eager"])
+def test_batch_overlapped_stages_change_no_output(setup, monkeypatch, form):
+    """The histograms (by default) or every stage after the search on the
+    batch's second stream, beside the searches (replayed as a HIP graph
+    several times with other work in between, or run eagerly), give the
+    bytes of the serial form, and the serial form matches the oracle."""
+    torch, qc, graphs, sigmas = setup
+    hs = [qc.Graph.from_graph(g) for g in graphs]
+    bs = qc.Batch(hs, sigmas, hipgraph=True, serial=True)
+    assert bs.stage_tiles()["overlap"] == "none"
+    if form == "all":
+        monkeypatch.setenv("QC_BATCH_OVERLAP", "2")
+    ho = [qc.Graph.from_graph(g) for g in graphs]
+    bo = qc.Batch(ho, sigmas, hipgraph=(form != "histograms-eager"))
+    assert bo.stage_tiles()["overlap"] == ("all" if form == "all" else "histograms")
+    os_, oo = bs.outputs(), bo.outputs()
+    bs.run(*os_)
+    torch.cuda.synchronize()
+    ref = [x.cpu().numpy().copy() for x in os_]
+    for r in range(3):
+        for x in oo:
+            x.fill_(-7)
+        bo.run(*oo)
+        torch.cuda.synchronize()
+        for x, y in zip(oo, ref):
+            assert x.cpu().numpy().tobytes() == y.tobytes(), f"run {r}"
+        _ = torch.ones(1000, device="cuda").sum().item()
+    for G, H in zip(hs, ho):
+        assert torch.equal(G.histograms(), H.histograms())
+    for i, g in enumerate(graphs):
+        if g.n > 3000:
+            continue
+        o0, o1 = bs.offsets[i], bs.offsets[i + 1]
+        dist, dmax = oracle.distances(g.n, g.row_ptr, g.col)
+        hist = oracle.hist_rows(dist, dmax + 1)
+        for s, sigma in enumerate(sigmas):
+            psi_c, v_c = oracle.potential_canonical(hist, sigma)
+            np.testing.assert_allclose(ref[1][s, o0:o1], v_c, rtol=1e-6, atol=0)
+            lab = oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v_c, 0))
+            np.testing.assert_array_equal(ref[2][s, o0:o1], lab)
+    bs.close()
+    bo.close()
+
+
 def test_batch_rejects_bad_arguments(setup):
     torch, qc, graphs, sigmas = setup
     G = qc.Graph.from_graph(graphs[-1])
