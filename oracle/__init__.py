@@ -76,6 +76,8 @@ def lib():
         L.qco_potential_dense.restype = None
         L.qco_dijkstra_rows.argtypes = [I, P, P, P, I, P, P, P]
         L.qco_dijkstra_rows.restype = I
+        L.qco_sssp_f32_rows.argtypes = [I, P, P, P, I, P, P]
+        L.qco_sssp_f32_rows.restype = I
         L.qco_num_threads.argtypes = []
         L.qco_num_threads.restype = I
         L.qco_set_num_threads.argtypes = [I]
@@ -139,6 +141,24 @@ def weighted_rows(n, row_ptr, col, weight, sources) -> tuple:
 
 def weighted_distances(n, row_ptr, col, weight) -> tuple:
     return weighted_rows(n, row_ptr, col, weight, np.arange(n, dtype=np.int32))
+
+
+def real_rows(n, row_ptr, col, weight, sources) -> np.ndarray:
+    """Shortest-path lengths with positive real edge weights (float32, one per
+    CSR entry) from the given sources: float32 rows, each a path's binary32
+    sum from the source outward minimised over paths; +inf unreachable."""
+    rp, c = _csr(row_ptr, col)
+    w = np.ascontiguousarray(weight, dtype=np.float32)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    out = np.empty((src.shape[0], n), dtype=np.float32)
+    st = lib().qco_sssp_f32_rows(n, _p(rp), _p(c), _p(w), src.shape[0], _p(src), _p(out))
+    if st != 0:
+        raise OracleError(f"sssp status {st} (a weight not finite and > 0)")
+    return out
+
+
+def real_distances(n, row_ptr, col, weight) -> np.ndarray:
+    return real_rows(n, row_ptr, col, weight, np.arange(n, dtype=np.int32))
 
 
 def hist_rows(dist_rows: np.ndarray, K: int) -> np.ndarray:

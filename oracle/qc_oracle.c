@@ -181,6 +181,98 @@ int qco_dijkstra_rows(int n, const int32_t *row_ptr, const int32_t *col, const u
     return status;
 }
 
+/* Shortest-path lengths from s along CSR rows with positive real edge
+ * weights w[e] (Section 3.1: a path's length is the sum of its edges'
+ * weights). A path's length is summed in binary32 from the source outward,
+ * every partial sum rounded to nearest; d(s, v) is the least such sum over
+ * all paths (+infinity when v is unreachable). Dijkstra's algorithm with a
+ * binary min-heap of (tentative length, node) entries; an entry popped after
+ * its node's length has dropped below it is skipped. The order Dijkstra
+ * relies on holds in binary32: a partial sum never decreases along a path,
+ * since the weights are positive and rounding is monotone. */
+static void sssp_f32_one(int n, const int32_t *row_ptr, const int32_t *col, const float *w, int s,
+                         float *row, unsigned char *done, float *hkey, int32_t *hnode)
+{
+    for (int v = 0; v < n; ++v) {
+        row[v] = INFINITY;
+        done[v] = 0;
+    }
+    int size = 0;
+    /* push (key, node): sift the new entry up */
+#define QCO_HEAP_PUSH(KEY, NODE)                                   \
+    do {                                                           \
+        int i_ = size++;                                           \
+        while (i_ > 0) {                                           \
+            int p_ = (i_ - 1) / 2;                                 \
+            if (!(hkey[p_] > (KEY))) break;                        \
+            hkey[i_] = hkey[p_];                                   \
+            hnode[i_] = hnode[p_];                                 \
+            i_ = p_;                                               \
+        }                                                          \
+        hkey[i_] = (KEY);                                          \
+        hnode[i_] = (NODE);                                        \
+    } while (0)
+    row[s] = 0.0f;
+    QCO_HEAP_PUSH(0.0f, s);
+    while (size > 0) {
+        const float key = hkey[0];
+        const int u = hnode[0];
+        /* pop: move the last entry to the root and sift it down */
+        --size;
+        if (size > 0) {
+            const float lk = hkey[size];
+            const int32_t ln = hnode[size];
+            int i = 0;
+            for (;;) {
+                int c = 2 * i + 1;
+                if (c >= size) break;
+                if (c + 1 < size && hkey[c + 1] < hkey[c]) ++c;
+                if (!(hkey[c] < lk)) break;
+                hkey[i] = hkey[c];
+                hnode[i] = hnode[c];
+                i = c;
+            }
+            hkey[i] = lk;
+            hnode[i] = ln;
+        }
+        if (done[u] || key > row[u]) continue;
+        done[u] = 1;
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int v = col[e];
+            const float nd = key + w[e];   /* binary32 sum, rounded to nearest */
+            if (!done[v] && nd < row[v]) {
+                row[v] = nd;
+                QCO_HEAP_PUSH(nd, v);
+            }
+        }
+    }
+#undef QCO_HEAP_PUSH
+}
+
+/* Real-weighted shortest-path lengths (binary32) for the listed sources;
+ * every weight must be finite and > 0. */
+int qco_sssp_f32_rows(int n, const int32_t *row_ptr, const int32_t *col, const float *w,
+                      int nsrc, const int32_t *srcs, float *dist)
+{
+    if (n <= 0 || nsrc < 0) return QCO_E_ARG;
+    const int32_t m = row_ptr[n];
+    for (int32_t e = 0; e < m; ++e)
+        if (!(w[e] > 0.0f) || !isfinite(w[e])) return QCO_E_ARG;
+#pragma omp parallel
+    {
+        unsigned char *done = (unsigned char *)malloc((size_t)n);
+        float *hk = (float *)malloc(sizeof(float) * ((size_t)m + 1));
+        int32_t *hn = (int32_t *)malloc(sizeof(int32_t) * ((size_t)m + 1));
+#pragma omp for schedule(dynamic, 8)
+        for (int r = 0; r < nsrc; ++r)
+            sssp_f32_one(n, row_ptr, col, w, srcs[r], dist + (size_t)r * n, done, hk, hn);
+        free(done);
+        free(hk);
+        free(hn);
+    }
+    return QCO_OK;
+}
+
 /* Histogram of each listed distance row: hist[r*K + k] = #{v : row_r[v] == k}.
  * Unreachable entries (-1) are not counted. Distances >= K are an error. */
 int qco_hist_rows(int n, int nrows, const int8_t *dist, int K, int32_t *hist)

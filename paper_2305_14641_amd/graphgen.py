@@ -240,6 +240,28 @@ def edge_weights(g: Graph, max_weight: int, seed: int, directed: bool = False) -
     return w[inv]
 
 
+def real_edge_weights(g: Graph, seed: int, lo: float = 0.5, hi: float = 4.0,
+                      directed: bool = False, dyadic: bool = False) -> np.ndarray:
+    """Seeded positive real weights, one per CSR entry (float32): uniform in
+    [lo, hi), or with dyadic=True multiples of 1/8 in [1/8, 4] (every path
+    sum below 2^20 is then exact in float32). For an undirected graph both
+    directions of an edge get the same weight."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    cols = g.col.astype(np.int64)
+
+    def draw(k):
+        if dyadic:
+            return (rng.integers(1, 33, k) / 8.0).astype(np.float32)
+        return rng.uniform(lo, hi, k).astype(np.float32)
+
+    if directed:
+        return draw(g.nnz)
+    lo_, hi_ = np.minimum(rows, cols), np.maximum(rows, cols)
+    uniq, inv = np.unique(lo_ * g.n + hi_, return_inverse=True)
+    return draw(uniq.shape[0])[inv]
+
+
 def random_digraph(n: int, p: float, seed: int) -> Graph:
     """Directed Erdos-Renyi graph: each ordered pair an arc with probability p."""
     rng = np.random.default_rng(seed)

@@ -231,3 +231,110 @@ def test_weighted_overflow_and_zero_weight():
         oracle.weighted_distances(g.n, g.row_ptr, g.col, np.full(g.nnz, 50, dtype=np.uint8))
     with pytest.raises(oracle.OracleError):
         oracle.weighted_distances(g.n, g.row_ptr, g.col, np.zeros(g.nnz, dtype=np.uint8))
+
+
+# --- real edge weights: binary32 path sums (Dijkstra with a binary heap) -----
+
+REAL = [gg.random_graph(40, 0.1, seed=s) for s in range(3)] + [
+    gg.config2(), gg.dcsbm_directed(300, [0.5, 0.5], 2.0, seed=8),
+    gg.disjoint_union(gg.path_graph(5), gg.star_graph(6), gg.empty_graph(3))]
+
+
+def _is_directed(g):
+    return g.name.startswith("dcsbm_directed")
+
+
+@pytest.mark.parametrize("case", range(len(REAL)))
+def test_real_rows_equal_scipy_when_sums_are_exact(case):
+    """Weights that are multiples of 1/8: every path sum is exact in float32,
+    so the binary32 Dijkstra must equal scipy's float64 shortest paths bit
+    for bit (unreachable = +inf in both)."""
+    g = REAL[case]
+    directed = _is_directed(g)
+    w = gg.real_edge_weights(g, seed=case, directed=directed, dyadic=True)
+    d = oracle.real_distances(g.n, g.row_ptr, g.col, w)
+    a = sp.csr_matrix((w.astype(np.float64), g.col, g.row_ptr), shape=(g.n, g.n))
+    ref = csg.shortest_path(a, method="D", directed=directed)
+    np.testing.assert_array_equal(d, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("case", range(len(REAL)))
+def test_real_rows_close_to_float64_shortest_paths(case):
+    """Uniform real weights: within binary32 rounding of each path's length
+    (relative 2^-24 per edge) of scipy's float64 shortest paths, and the same
+    reachability."""
+    g = REAL[case]
+    directed = _is_directed(g)
+    w = gg.real_edge_weights(g, seed=10 + case, directed=directed)
+    d = oracle.real_distances(g.n, g.row_ptr, g.col, w)
+    a = sp.csr_matrix((w.astype(np.float64), g.col, g.row_ptr), shape=(g.n, g.n))
+    ref = csg.shortest_path(a, method="D", directed=directed)
+    assert (np.isinf(d) == np.isinf(ref)).all()
+    fin = np.isfinite(ref)
+    np.testing.assert_allclose(d[fin], ref[fin], rtol=64 * 2.0 ** -24, atol=0)
+    assert (np.diag(d) == 0).all()
+
+
+def _brute_force_f32(n, row_ptr, col, w):
+    """Least binary32 left-to-right path sum over all simple paths (tiny n)."""
+    out = np.full((n, n), np.inf, dtype=np.float32)
+    def walk(s, u, acc, seen):
+        if acc < out[s, u]:
+            out[s, u] = acc
+        for e in range(row_ptr[u], row_ptr[u + 1]):
+            v = int(col[e])
+            if v not in seen:
+                seen.add(v)
+                walk(s, v, np.float32(acc + w[e]), seen)
+                seen.remove(v)
+    for s in range(n):
+        walk(s, s, np.float32(0.0), {s})
+    return out
+
+
+def test_real_rows_brute_force_binary32():
+    """Every simple path enumerated, its length summed in binary32 from the
+    source outward: the oracle's least sums equal these bit for bit, on tiny
+    random graphs whose weights mix magnitudes so that rounding decides."""
+    rng = np.random.default_rng(5)
+    scales = np.array([1.0, 2.0 ** -24, 3 * 2.0 ** -25, 0.1, 1e-3, 7.0], dtype=np.float32)
+    for trial in range(40):
+        g = gg.random_graph(7, 0.45, seed=100 + trial)
+        directed = trial % 3 == 2
+        if directed:
+            g = gg.random_digraph(7, 0.35, seed=200 + trial)
+        rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        key = np.minimum(rows, g.col) * g.n + np.maximum(rows, g.col) if not directed else \
+            np.arange(g.nnz)
+        uniq, inv = np.unique(key, return_inverse=True)
+        w = (rng.choice(scales, uniq.shape[0]) *
+             rng.uniform(1.0, 1.5, uniq.shape[0]).astype(np.float32)).astype(np.float32)[inv]
+        d = oracle.real_distances(g.n, g.row_ptr, g.col, w)
+        np.testing.assert_array_equal(d, _brute_force_f32(g.n, g.row_ptr, g.col, w),
+                                      err_msg=f"trial {trial}")
+
+
+def test_real_rows_rounding_decides():
+    """A path 1 + 2^-24 + 2^-24 sums to 1.0 in binary32 (each partial sum
+    rounds to even), below a direct edge of 1 + 2^-23, although its exact
+    length equals that edge: the least binary32 sum is 1.0, not the rounded
+    exact minimum. Path s=0 - 1 - 2 - 3 and the edge 0 - 3."""
+    rp, col = gg.csr_from_edges(4, np.array([0, 1, 2, 0]), np.array([1, 2, 3, 3]))
+    g = gg.Graph(4, rp, col, np.zeros(4, dtype=np.int32), "rounding")
+    eps = np.float32(2.0 ** -24)
+    wt = {(0, 1): np.float32(1.0), (1, 2): eps, (2, 3): eps, (0, 3): np.float32(1.0 + 2.0 ** -23)}
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    w = np.array([wt[(min(a, b), max(a, b))] for a, b in zip(rows, g.col)], dtype=np.float32)
+    d = oracle.real_distances(g.n, g.row_ptr, g.col, w)
+    # from 3 the same path sums 2^-24 + 2^-24 first, exactly, then 1 + 2^-23
+    assert d[0, 3] == np.float32(1.0) and d[3, 0] == np.float32(1.0 + 2.0 ** -23)
+    np.testing.assert_array_equal(d, _brute_force_f32(g.n, g.row_ptr, g.col, w))
+
+
+def test_real_rows_reject_bad_weights():
+    g = gg.path_graph(4)
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        w = np.ones(g.nnz, dtype=np.float32)
+        w[1] = bad
+        with pytest.raises(oracle.OracleError):
+            oracle.real_distances(g.n, g.row_ptr, g.col, w)
