@@ -250,6 +250,61 @@ qc_status qc_potential_dense(const float *dist, int64_t n_rows, int64_t n_cols, 
 qc_status qc_get_potential64(qc_graph g, double *v64_out, void *stream);
 
 /*
+ * Shortest-path lengths of every ordered pair under positive real edge
+ * weights (Section 3.1: a path's length is the sum of its edges' weights).
+ * A path's length is summed in binary32 from its source outward, every
+ * partial sum rounded to nearest, and d(i, j) is the least such sum over the
+ * paths from i to j; +infinity when j is unreachable. (Row i holds the sums
+ * from i, so under rounding d(i, j) and d(j, i) of an undirected graph can
+ * differ in the last bit.)
+ *   n, nnz, row_ptr, col_idx  host CSR as for qc_graph_create, canonical
+ *             (sorted rows, no duplicates or self-loops; undirected:
+ *             symmetric); 1 <= n <= 32768
+ *   weights   host, float[nnz], one per CSR entry, each finite and at least
+ *             FLT_MIN (normal, > 0); for an undirected graph both entries of
+ *             an edge must carry the same weight
+ *   flags     0 or QC_GRAPH_DIRECTED (row i lists i's out-neighbours and
+ *             d(i, j) follows the edge directions)
+ *   dist_out  device, float[n * ld] row-major
+ *   ld        row stride in floats, ld >= n
+ * One workgroup per source keeps that source's tentative lengths in LDS and
+ * relaxes them in rounds from the nodes whose length dropped. The call waits
+ * for `stream` and returns when the matrix is written; the caller keeps
+ * ownership of every array.
+ * Errors: QC_E_INVAL (NULL pointers, sizes, n > 32768, ld < n, a weight that
+ * is not a normal positive float, unknown flags), QC_E_NOT_SYMMETRIC (CSR
+ * not canonical, or the two weights of an undirected edge differ), QC_E_OOM,
+ * QC_E_DEVICE.
+ */
+qc_status qc_distances_real(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                            const float *weights, uint32_t flags, float *dist_out, int64_t ld,
+                            void *stream);
+
+/*
+ * Algorithm 4 on a graph with real edge weights, in one call: the distances
+ * of qc_distances_real, psi and V of every width by Algorithm 1 on them (as
+ * qc_potential_dense: FP64 sums, every exponential to about one FP32 ulp),
+ * then the descent along the graph's own edges (Algorithms 2-3, as
+ * qc_ggd_labels: FP32 comparisons, near ties re-decided on these FP64 V) and
+ * pointer jumping.
+ *   n, nnz, row_ptr, col_idx, weights, flags  as qc_distances_real
+ *   sigmas, n_sigmas  host, as for qc_potential_dense (each finite and
+ *                >= 1e-100, 1..1024 of them)
+ *   tie_mode     QC_TIE_STRICT or QC_TIE_MERGE
+ *   dist_out     device, float[n*n] row-major, or NULL (the library then
+ *                uses a matrix of its own for the call)
+ *   psi_out, v_out  device, double[n_sigmas][n], or NULL: the potentials the
+ *                labels were decided on
+ *   labels_out   device, int32[n_sigmas][n] (sigma-major), required
+ * The call waits for `stream`. Errors as qc_distances_real, plus QC_E_INVAL
+ * for a bad sigma list, tie mode or a NULL labels_out.
+ */
+qc_status qc_cluster_real(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                          const float *weights, uint32_t flags, const double *sigmas,
+                          int32_t n_sigmas, uint32_t tie_mode, float *dist_out, double *psi_out,
+                          double *v_out, int32_t *labels_out, void *stream);
+
+/*
  * Algorithm 4 in one call, on a temporary handle released before the call
  * returns (the call waits for `stream`): hop distances, psi and V (Eq. 2,
  * Algorithm 1) for every width, and the descent's labels (Algorithms 2-3)
@@ -337,7 +392,8 @@ enum {
     QC_STAGE_GGD = 3,        /* descent parents (with FP64 re-check) */
     QC_STAGE_JUMP = 4,       /* pointer jumping to labels */
     QC_STAGE_DENSE = 5,      /* qc_potential_dense */
-    QC_N_STAGES = 6
+    QC_STAGE_SSSP = 6,       /* real-weighted shortest paths (qc_distances_real) */
+    QC_N_STAGES = 7
 };
 qc_status qc_timing_enable(int32_t on);  /* on = 1 also clears earlier records */
 qc_status qc_timing_read(int32_t stage, double *total_ms, int64_t *launches);

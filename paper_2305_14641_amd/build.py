@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libqc_hip.so")
 
 SOURCES = ["qc_kernels.hip", "qc_dense.hip", "qc_bfs_4.hip", "qc_bfs_8.hip", "qc_bfs_16.hip", "qc_bfs_32.hip",
            "qc_bfs_64.hip", "qc_api.cpp", "qc_host.cpp", "qc_timing.cpp", "qc_batch.cpp",
-           "qc_server.cpp", "qc_noalloc.hip"]
+           "qc_server.cpp", "qc_noalloc.hip", "qc_sssp.hip", "qc_real.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -210,6 +210,17 @@ hipError_t launch_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64
                         const double *sigmas, int n_sigmas, double *psi, double *v,
                         hipStream_t stream);
 
+// Shortest paths under real edge weights (qc_sssp.hip): one workgroup per
+// source s0 .. s0+count-1 over an n-node CSR (device row_ptr / col, float
+// weights w, each normal and > 0); row s of `dist` (stride ld >= n) receives
+// the least binary32 path sums from s (+inf unreached). n <= kSsspMaxNodes
+// (the row lives in LDS).
+constexpr int kSsspMaxNodes = 32768;
+hipError_t launch_sssp(int n, const int32_t *row_ptr, const int32_t *col, const float *w, float *dist,
+                       int64_t ld, int src0, int count, hipStream_t stream);
+// FP32 resident copy of an FP64 potential [n_sigmas][n] (v_index layout).
+hipError_t launch_v_resident(const double *v64, int n, int n_sigmas, float *v32, hipStream_t stream);
+
 // Fill kernel (used instead of hipMemsetAsync so work can be graph-captured).
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t count, hipStream_t stream);

@@ -47,7 +47,7 @@ EXPORTED = [
     "qc_graph_info", "qc_graph_bfs_plan", "qc_distances", "qc_get_histograms", "qc_potential",
     "qc_ggd_labels", "qc_last_recheck_count", "qc_graph_sync", "qc_timing_enable",
     "qc_timing_read", "qc_potential_dense", "qc_debug_alloc_fault", "qc_get_potential64",
-    "qc_cluster", "qc_cluster_noalloc",
+    "qc_cluster", "qc_cluster_noalloc", "qc_distances_real", "qc_cluster_real",
     "qc_batch_create", "qc_batch_node_offsets", "qc_batch_run", "qc_batch_recheck_count",
     "qc_batch_search_stats", "qc_batch_sweep_bf16", "qc_batch_stage_tiles", "qc_batch_destroy",
 ]
@@ -80,7 +80,8 @@ STAGE_POTENTIAL = 2
 STAGE_GGD = 3
 STAGE_JUMP = 4
 STAGE_DENSE = 5
-STAGE_NAMES = ["bfs", "hist", "potential", "ggd_parent", "pointer_jump", "dense"]
+STAGE_SSSP = 6
+STAGE_NAMES = ["bfs", "hist", "potential", "ggd_parent", "pointer_jump", "dense", "sssp"]
 
 
 class QCError(RuntimeError):
@@ -126,6 +127,8 @@ def lib():
         L.qc_get_potential64.argtypes = [P, P, P]
         L.qc_cluster.argtypes = [I32, I64, P, P, P, I32, U32, P, P, P, P, P]
         L.qc_cluster_noalloc.argtypes = [I32, I64, P, P, P, I32, U32, P, P, P, P, P]
+        L.qc_distances_real.argtypes = [I32, I64, P, P, P, U32, P, I64, P]
+        L.qc_cluster_real.argtypes = [I32, I64, P, P, P, U32, P, I32, U32, P, P, P, P, P]
         L.qc_batch_create.argtypes = [P, I32, P, I32, U32, U32, P, P]
         L.qc_batch_node_offsets.argtypes = [P, P]
         L.qc_batch_run.argtypes = [P, P, P, P, P]
@@ -574,4 +577,57 @@ def cluster_noalloc(n, row_ptr, col, sigmas, tie_mode=TIE_STRICT, dist=None, psi
                                     sig.ctypes.data_as(ctypes.c_void_p), sig.shape[0],
                                     int(tie_mode), _dptr(dist), _dptr(psi), _dptr(v),
                                     _dptr(labels), _stream_ptr(stream)), "qc_cluster_noalloc")
+    return labels
+
+
+def _real_args(n, row_ptr, col, weights):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    if w.shape != c.shape:
+        raise ValueError("one weight per CSR entry")
+    return rp, c, w
+
+
+def distances_real(n, row_ptr, col, weights, directed=False, out=None, stream=None):
+    """qc_distances_real: float32 [n, n] shortest-path lengths under positive
+    real edge weights (one per CSR entry), +inf where unreachable."""
+    import torch
+    rp, c, w = _real_args(n, row_ptr, col, weights)
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    if not out.is_cuda or out.dtype != torch.float32 or out.dim() != 2 or out.stride(1) != 1 \
+            or out.shape[0] != n or out.shape[1] < n:
+        raise ValueError("expected a CUDA float32 [n, >= n] matrix with unit column stride")
+    ld = out.stride(0) if n > 1 else max(out.shape[1], 1)
+    _check(lib().qc_distances_real(int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+                                   c.ctypes.data_as(ctypes.c_void_p),
+                                   w.ctypes.data_as(ctypes.c_void_p),
+                                   GRAPH_DIRECTED if directed else 0, _dptr(out), int(ld),
+                                   _stream_ptr(stream)), "qc_distances_real")
+    return out
+
+
+def cluster_real(n, row_ptr, col, weights, sigmas, tie_mode=TIE_STRICT, directed=False, dist=None,
+                 psi=None, v=None, labels=None, stream=None):
+    """qc_cluster_real: labels [S, n] int32 of a graph with real edge weights
+    (and the optional float32 dist [n, n], FP64 psi / v [S, n] filled)."""
+    import torch
+    rp, c, w = _real_args(n, row_ptr, col, weights)
+    sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).reshape(-1))
+    S = sig.shape[0]
+    if labels is None:
+        labels = torch.empty((S, n), dtype=torch.int32, device="cuda")
+    Graph._check_tensor(labels, (S, n), "int32")
+    if dist is not None:
+        Graph._check_tensor(dist, (n, n), "float32")
+    for t in (psi, v):
+        if t is not None:
+            Graph._check_tensor(t, (S, n), "float64")
+    _check(lib().qc_cluster_real(int(n), int(c.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+                                 c.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
+                                 GRAPH_DIRECTED if directed else 0,
+                                 sig.ctypes.data_as(ctypes.c_void_p), S, int(tie_mode), _dptr(dist),
+                                 _dptr(psi), _dptr(v), _dptr(labels), _stream_ptr(stream)),
+           "qc_cluster_real")
     return labels

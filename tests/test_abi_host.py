@@ -237,6 +237,52 @@ def test_cluster_arguments_checked_on_host():
         assert call() == qc.QC_E_DEVICE
 
 
+def test_real_weight_arguments_checked_on_host():
+    """qc_distances_real and qc_cluster_real check the CSR, the weights and
+    their own arguments before any device work."""
+    L = qc.lib()
+    P = ctypes.c_void_p
+    path = (3, np.array([0, 1, 3, 4], dtype=np.int32), np.array([1, 0, 2, 1], dtype=np.int32))
+
+    def dist(n, rp, col, w, flags=0, out=P(256), ld=None):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        return L.qc_distances_real(n, col.shape[0], rp.ctypes.data_as(P), col.ctypes.data_as(P),
+                                   w.ctypes.data_as(P) if w.size else None, flags, out,
+                                   n if ld is None else ld, None)
+
+    def clus(n, rp, col, w, sig=(1.0,), tie=0, labels=P(256), flags=0):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        s_ = np.ascontiguousarray(sig, dtype=np.float64)
+        return L.qc_cluster_real(n, col.shape[0], rp.ctypes.data_as(P), col.ctypes.data_as(P),
+                                 w.ctypes.data_as(P) if w.size else None, flags,
+                                 s_.ctypes.data_as(P), s_.shape[0], tie, None, None, None, labels,
+                                 None)
+
+    good = [0.5, 0.5, 2.25, 2.25]
+    if qc.device_count() == 0:
+        assert dist(*path, good) == qc.QC_E_DEVICE
+        assert clus(*path, good) == qc.QC_E_DEVICE
+    assert dist(*path, good, out=None) == qc.QC_E_INVAL               # no output
+    assert dist(*path, good, ld=2) == qc.QC_E_INVAL                   # ld < n
+    assert dist(*path, [0.5, 0.75, 2.25, 2.25]) == qc.QC_E_NOT_SYMMETRIC
+    for bad in (0.0, -1.0, np.nan, np.inf, 1e-40):                    # 1e-40: subnormal
+        assert dist(*path, [bad, bad, 2.25, 2.25]) == qc.QC_E_INVAL, bad
+    assert dist(*path, good, flags=qc.GRAPH_CANONICALIZE) == qc.QC_E_INVAL
+    assert dist(3, path[1], np.array([1, 0, 1, 2], dtype=np.int32), good) == qc.QC_E_NOT_SYMMETRIC
+    big = 32769                                                       # above the LDS row
+    assert dist(big, np.zeros(big + 1, dtype=np.int32), np.zeros(0, dtype=np.int32), []) \
+        == qc.QC_E_INVAL
+    assert clus(*path, good, labels=None) == qc.QC_E_INVAL
+    assert clus(*path, good, tie=2) == qc.QC_E_INVAL
+    assert clus(*path, good, sig=(1.0, 0.0)) == qc.QC_E_INVAL
+    assert clus(*path, good, sig=(1e-200,)) == qc.QC_E_INVAL
+    assert clus(*path, [0.5, 0.75, 2.25, 2.25]) == qc.QC_E_NOT_SYMMETRIC
+    if qc.device_count() == 0:
+        # directed: the weights need not match across directions
+        assert dist(3, np.array([0, 1, 2, 2], dtype=np.int32), np.array([1, 2], dtype=np.int32),
+                    [0.5, 3.0], flags=qc.GRAPH_DIRECTED) == qc.QC_E_DEVICE
+
+
 def test_noalloc_arguments_and_size_checked_on_host():
     """qc_cluster_noalloc validates its arguments and refuses a problem beyond
     its fixed scratch (QC_E_TOO_LARGE) before touching any device."""
