@@ -19,7 +19,8 @@ smaller workloads (one 200-node graph's latency, the 2,708- and 19,717-node
 graphs end to end, psi/V from a resident matrix), the serving form on the
 whole 1,024-request stream (p50/p99 latency and graphs/s at several arrival
 rates, against one request at a time), the fully connected dense workload,
-and the CPU oracle on bounded samples (every core and one thread), whose
+real edge weights (shortest paths and the whole path on the 2,708- and
+19,717-node graphs), and the CPU oracle on bounded samples (every core and one thread), whose
 labels are compared with the GPU's.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -362,6 +363,58 @@ def bfs_alu(stages):
             "lds_wave_instructions_per_step": prof.get("lds_wave_instructions_per_step")}
 
 
+def real_leg(args, qc, torch) -> dict:
+    """Shortest paths under real edge weights (qc_distances_real: one
+    workgroup per source, binary32 path sums) and the whole real-weighted
+    path (qc_cluster_real) on the 2,708- and 19,717-node graphs with seeded
+    uniform weights in [0.5, 4). Kernel times from the library's stage
+    events; call times include the CSR upload and the final wait."""
+    from paper_2305_14641_amd import graphgen as gg
+    out = {"workload": "config-2 and config-3 graphs, edge weights uniform in [0.5, 4) (seeded)"}
+    for name, g, S in (("c2", gg.config2(), 4), ("c3", gg.config3(), 1)):
+        w = gg.real_edge_weights(g, seed=5)
+        n = g.n
+        d = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        qc.distances_real(n, g.row_ptr, g.col, w, out=d)
+        torch.cuda.synchronize()
+        reps = 3
+        qc.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            qc.distances_real(n, g.row_ptr, g.col, w, out=d)
+        call_ms = (time.perf_counter() - t0) / reps * 1e3
+        k_ms, k_n = qc.timing_read(qc.STAGE_SSSP)
+        qc.timing_enable(False)
+        k_ms /= max(k_n, 1)
+        sig = list(np.geomspace(0.5, 4.0, S)) if S > 1 else [1.0]
+        lab = torch.empty((S, n), dtype=torch.int32, device="cuda")
+        qc.cluster_real(n, g.row_ptr, g.col, w, sig, dist=d, labels=lab)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            qc.cluster_real(n, g.row_ptr, g.col, w, sig, dist=d, labels=lab)
+        cl_ms = (time.perf_counter() - t0) / reps * 1e3
+        out[name] = {"n": n, "nnz": g.nnz, "sssp_kernel_ms": k_ms, "distances_call_ms": call_ms,
+                     "sources_per_s": n / (k_ms * 1e-3),
+                     "pair_lengths_per_s": float(n) * n / (k_ms * 1e-3),
+                     "output_gbs": 4.0 * n * n / (k_ms * 1e-3) / 1e9,
+                     "cluster_call_ms": cl_ms, "n_sigmas": S,
+                     "pair_terms_per_s_end_to_end": float(n) * n * S / (cl_ms * 1e-3)}
+        log(f"real {name}: sssp {k_ms:.2f} ms ({n / (k_ms * 1e-3):.3e} sources/s), "
+            f"distances call {call_ms:.2f} ms, cluster ({S} sigma) {cl_ms:.2f} ms")
+        if name == "c3" and not args.no_cpu_baseline:
+            import oracle
+            src = np.arange(0, n, max(1, n // 256), dtype=np.int32)[:256]
+            t0 = time.perf_counter()
+            oracle.real_rows(n, g.row_ptr, g.col, w, src)
+            dt = time.perf_counter() - t0
+            out[name]["cpu_oracle"] = {"sources_per_s": src.shape[0] / dt,
+                                       "cores": oracle.num_threads(),
+                                       "sample": f"{src.shape[0]} sources, binary32 Dijkstra"}
+        del d, lab
+    torch.cuda.empty_cache()
+    return out
+
+
 def dense_leg(args, qc, torch) -> dict:
     """Algorithm 1 on a fully connected graph with float distances (the
     paper's GPU experiment shape): one pass for one width (HBM-bound) and for
@@ -439,6 +492,8 @@ def main():
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the fully connected (dense float distance) leg")
     ap.add_argument("--dense-n", type=int, default=20000)
+    ap.add_argument("--no-real", action="store_true",
+                    help="skip the real edge weight leg (shortest paths, whole path)")
     ap.add_argument("--quality", action="store_true",
                     help="sigma-sweep quality study: label quality vs the planted blocks")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -628,6 +683,7 @@ def main():
             f"max rel err psi {worst_psi:.2e} V {worst_v:.2e}")
 
     dense = None if args.no_dense else dense_leg(args, qc, torch)
+    real = None if args.no_real else real_leg(args, qc, torch)
     configs = None if args.no_configs else configs_leg(args, qc, gg, torch)
     serving = serve(args, reqs) if reqs else None
 
@@ -696,6 +752,7 @@ def main():
         "plain": plain,
         "bf16_sweep": bf16,
         "dense": dense,
+        "real_weights": real,
         "configs": configs,
         "serving": serving,
         "cpu_baseline": cpu,

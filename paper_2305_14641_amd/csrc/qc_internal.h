@@ -211,13 +211,14 @@ hipError_t launch_dense(const float *dist, int64_t n_rows, int64_t n_cols, int64
                         hipStream_t stream);
 
 // Shortest paths under real edge weights (qc_sssp.hip): one workgroup per
-// source s0 .. s0+count-1 over an n-node CSR (device row_ptr / col, float
-// weights w, each normal and > 0); row s of `dist` (stride ld >= n) receives
-// the least binary32 path sums from s (+inf unreached). n <= kSsspMaxNodes
-// (the row lives in LDS).
+// source s0 .. s0+count-1 over an n-node CSR (device row_ptr; col_w holds
+// each entry's column and the bits of its float weight, normal and > 0, as
+// consecutive 32-bit words, 8-byte aligned); row s of `dist` (stride
+// ld >= n) receives the least binary32 path sums from s (+inf unreached).
+// n <= kSsspMaxNodes (the row lives in LDS).
 constexpr int kSsspMaxNodes = 32768;
-hipError_t launch_sssp(int n, const int32_t *row_ptr, const int32_t *col, const float *w, float *dist,
-                       int64_t ld, int src0, int count, hipStream_t stream);
+hipError_t launch_sssp(int n, const int32_t *row_ptr, const uint32_t *col_w, float *dist, int64_t ld,
+                       int src0, int count, hipStream_t stream);
 // FP32 resident copy of an FP64 potential [n_sigmas][n] (v_index layout).
 hipError_t launch_v_resident(const double *v64, int n, int n_sigmas, float *v32, hipStream_t stream);
 

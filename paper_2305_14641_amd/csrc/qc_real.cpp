@@ -4,6 +4,7 @@
 #include <float.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -46,23 +47,25 @@ qc_status validate_real(int32_t n, int64_t nnz, const int32_t *row_ptr, const in
 qc_status real_distances(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
                          const float *weights, float *dist, int64_t ld, hipStream_t st)
 {
-    int32_t *d_rp = nullptr, *d_col = nullptr;
-    float *d_w = nullptr;
-    const std::vector<float> w(weights, weights + col.size());
+    // each entry's column and weight bits side by side: one 8-byte load per edge
+    std::vector<uint32_t> cw(2 * col.size());
+    for (size_t e = 0; e < col.size(); ++e) {
+        cw[2 * e] = (uint32_t)col[e];
+        memcpy(&cw[2 * e + 1], &weights[e], sizeof(float));
+    }
+    int32_t *d_rp = nullptr;
+    uint32_t *d_cw = nullptr;
     qc_status s = dalloc(&d_rp, rp.size());
-    if (s == QC_OK) s = dalloc(&d_col, col.size());
-    if (s == QC_OK) s = dalloc(&d_w, w.size());
+    if (s == QC_OK) s = dalloc(&d_cw, cw.size());
     if (s == QC_OK) s = upload(d_rp, rp);
-    if (s == QC_OK) s = upload(d_col, col);
-    if (s == QC_OK) s = upload(d_w, w);
+    if (s == QC_OK) s = upload(d_cw, cw);
     if (s == QC_OK) {
         StageTimer t(QC_STAGE_SSSP, st);
-        s = from_hip(launch_sssp(n, d_rp, d_col, d_w, dist, ld, 0, n, st));
+        s = from_hip(launch_sssp(n, d_rp, d_cw, dist, ld, 0, n, st));
     }
     if (s == QC_OK) s = from_hip(hipStreamSynchronize(st));
     dfree(d_rp);
-    dfree(d_col);
-    dfree(d_w);
+    dfree(d_cw);
     return s;
 }
 
