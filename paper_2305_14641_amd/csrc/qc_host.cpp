@@ -386,6 +386,10 @@ BfsPlan plan_bfs_shape(int32_t n, int32_t dmax, int shape, int max_bw)
             if (bw == 64 && (nw % 2)) continue;
             if (bw == 64 && shape == kBfsNarrow && planes >= 7 && nw > 10) continue;
             if (shape == kBfsWide1024 && planes == 5 && nw > 16 && bw != 32) continue;
+            // seen in registers with 4 planes: 16 words rather than 14, so a
+            // thread owns its words four at a time (16-byte LDS accesses,
+            // the decode's register transpose); measured faster on the sweep
+            if (shape == kBfsFront && planes <= 4 && nw == 14) continue;
             if (nw >= need) {
                 BfsPlan p;
                 p.bw = bw;

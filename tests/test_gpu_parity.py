@@ -288,7 +288,8 @@ def test_search_order_changes_nothing(torch_cuda, monkeypatch, g, env):
 def front_plan(n, dmax):
     """Batch width and words per thread of the seen-in-registers shape: the
     widest batch whose bit fields fit 16 words per thread (4 planes, largest
-    distance <= 15) or 14 (5 planes) at 1024 threads."""
+    distance <= 15; 14 words are then taken as 16) or 14 (5 planes) at 1024
+    threads."""
     max_nw = 16 if dmax <= 15 else 14
     for bw in (64, 32, 16, 8):
         need = -(-(-(-n * bw // 32)) // 1024)
@@ -296,6 +297,8 @@ def front_plan(n, dmax):
             if nw > max_nw:
                 break
             if bw == 64 and nw % 2:
+                continue
+            if nw == 14 and dmax <= 15:
                 continue
             if nw >= need:
                 return bw, nw
@@ -307,6 +310,7 @@ def front_plan(n, dmax):
     (9000, 4.0, 22),    # 64 sources would need 18 words: 32 sources
     (6000, 5.0, 21),    # 64 sources (64-bit fields)
     (16500, 4.0, 27),   # beyond 16 words at 32 sources: 16 sources
+    (13500, 2.5, 33),   # largest distance above 15: 5 planes, 14 words
 ])
 def test_seen_in_registers_shape(torch_cuda, monkeypatch, n, deg, seed):
     """The search shape that keeps `seen` in its owners' registers (two LDS
