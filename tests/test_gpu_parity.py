@@ -158,6 +158,7 @@ def test_config3_fp32c(torch_cuda):
     (50003, 3.0, 25),    # 4, then 8 (two fields, 1024 threads, 14 words, 5 planes)
     (13000, 0.0, 7),     # sparse SBM, largest distance 20: 32 (two fields, 1024 threads, 5 planes)
     (17000, 0.0, 8),     # sparse SBM, largest distance 19: 16, then 32 (1024 threads, 18 words, 5 planes)
+    (15500, 2.5, 35),    # largest distance 17: 32 (two fields, 1024 threads, 16 words, 5 planes)
 ])
 def test_batch_width_classes_sampled(torch_cuda, n, deg, seed):
     """Every BFS launch shape, ragged last batch: the first run (7 planes)
