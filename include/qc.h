@@ -308,7 +308,10 @@ qc_status qc_cluster_real(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
  * Algorithm 4 in one call, on a temporary handle released before the call
  * returns (the call waits for `stream`): hop distances, psi and V (Eq. 2,
  * Algorithm 1) for every width, and the descent's labels (Algorithms 2-3)
- * for every width.
+ * for every width. A problem that fits QC_NOALLOC_SCRATCH_BYTES runs in the
+ * library's fixed device scratch, as qc_cluster_noalloc (no device
+ * allocation; such calls on one device take turns), a larger one on
+ * buffers allocated for the call.
  *   n, nnz, row_ptr, col_idx  host CSR as for qc_graph_create with flags 0
  *                (canonical and undirected, else QC_E_NOT_SYMMETRIC)
  *   sigmas, n_sigmas          host, as for qc_potential

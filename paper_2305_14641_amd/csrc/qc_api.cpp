@@ -764,6 +764,11 @@ qc_status qc_cluster(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32
     if (dist_out && ((uintptr_t)dist_out) % 16) return QC_E_INVAL;
     QC_TRY(validate_sigmas(sigmas, n_sigmas));
     hipStream_t st = as_stream(stream);
+    // a problem that fits the fixed scratch runs there, without the device
+    // allocations (and frees) of a temporary handle
+    const qc_status fit = cluster_scratch(n, nnz, row_ptr, col_idx, sigmas, n_sigmas, tie_mode, dist_out,
+                                          psi_out, v_out, labels_out, st, true);
+    if (fit != QC_E_TOO_LARGE) return fit;
     qc_graph g = nullptr;
     QC_TRY(create_graph(n, nnz, row_ptr, col_idx, 0, st, nullptr, 0, &g));
     const qc_status s =

@@ -231,6 +231,14 @@ int64_t handle_footprint(int32_t n, int64_t nnz, int32_t n_sigmas, bool with_dis
 qc_status cluster_on_handle(qc_graph g, const double *sigmas, int32_t n_sigmas,
                             uint32_t tie_mode, int8_t *dist_out, float *psi_out, float *v_out,
                             int32_t *labels_out, hipStream_t st);
+// Algorithm 4 in one call with every device buffer carved from the library's
+// fixed per-device scratch (qc_noalloc.hip; one call per device at a time):
+// QC_E_TOO_LARGE when the problem does not fit it. `stage_events`: let the
+// stage timers record (they create HIP events, an allocation).
+qc_status cluster_scratch(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                          const double *sigmas, int32_t n_sigmas, uint32_t tie_mode, int8_t *dist_out,
+                          float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st,
+                          bool stage_events);
 // Release a handle; `sync` waits for the whole device first (handles that
 // live in an arena region are released after their own stream has drained).
 void destroy(qc_graph g, bool sync = true);

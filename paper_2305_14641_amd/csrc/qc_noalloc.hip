@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <optional>
+#include <vector>
 
 #include "qc.h"
 #include "qc_handle.h"
@@ -45,11 +47,12 @@ qc_status scratch_ptr(int dev, char **out)
 
 }  // namespace
 
-extern "C" qc_status qc_cluster_noalloc(int32_t n, int64_t nnz, const int32_t *row_ptr,
-                                        const int32_t *col_idx, const double *sigmas,
-                                        int32_t n_sigmas, uint32_t tie_mode, int8_t *dist_out,
-                                        float *psi_out, float *v_out, int32_t *labels_out,
-                                        void *stream)
+namespace qc {
+
+qc_status cluster_scratch(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                          const double *sigmas, int32_t n_sigmas, uint32_t tie_mode, int8_t *dist_out,
+                          float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st,
+                          bool stage_events)
 {
     if (!labels_out || tie_mode > QC_TIE_MERGE) return QC_E_INVAL;
     if (dist_out && ((uintptr_t)dist_out) % 16) return QC_E_INVAL;
@@ -59,14 +62,20 @@ extern "C" qc_status qc_cluster_noalloc(int32_t n, int64_t nnz, const int32_t *r
     const int64_t need = handle_footprint(n, nnz, n_sigmas, dist_out == nullptr, false);
     if (need < 0) return QC_E_INVAL;
     if (need > (int64_t)kScratchBytes) return QC_E_TOO_LARGE;
+    {
+        // the CSR is checked on the host before any device work
+        std::vector<int32_t> rp, col;
+        QC_TRY(validate_csr(n, nnz, row_ptr, col_idx, false, rp, col));
+    }
     int dev = 0;
     QC_TRY(check_device(&dev));
     if (dev >= kMaxDevices) return QC_E_DEVICE;
     std::lock_guard<std::mutex> lk(g_dev_mu[dev]);
     char *base = nullptr;
     QC_TRY(scratch_ptr(dev, &base));
-    hipStream_t st = as_stream(stream);
-    StageTimingOff no_events;   // the stage timers would create HIP events
+    // without allocation no stage timer may run (each creates HIP events)
+    std::optional<StageTimingOff> no_events;
+    if (!stage_events) no_events.emplace();
     qc_graph g = nullptr;
     QC_TRY(create_graph(n, nnz, row_ptr, col_idx, 0, st, base, kScratchBytes, &g));
     const qc_status s =
@@ -76,4 +85,16 @@ extern "C" qc_status qc_cluster_noalloc(int32_t n, int64_t nnz, const int32_t *r
     (void)hipStreamSynchronize(st);
     destroy(g, false);
     return s;
+}
+
+}  // namespace qc
+
+extern "C" qc_status qc_cluster_noalloc(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                                        const int32_t *col_idx, const double *sigmas,
+                                        int32_t n_sigmas, uint32_t tie_mode, int8_t *dist_out,
+                                        float *psi_out, float *v_out, int32_t *labels_out,
+                                        void *stream)
+{
+    return cluster_scratch(n, nnz, row_ptr, col_idx, sigmas, n_sigmas, tie_mode, dist_out, psi_out,
+                           v_out, labels_out, as_stream(stream), false);
 }

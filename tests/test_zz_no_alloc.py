@@ -1,13 +1,16 @@
-"""The no-allocation entry point qc_cluster_noalloc against qc_cluster.
+"""The no-allocation entry point qc_cluster_noalloc against qc_cluster and
+against the per-step calls on a graph handle.
 
-Both run Algorithm 4 (distances, psi/V of Eq. 2 / Algorithm 1, the descent
+All run Algorithm 4 (distances, psi/V of Eq. 2 / Algorithm 1, the descent
 of Algorithms 2-3) on the same graphs; the no-allocation call carves all its
-device buffers from the library's fixed device scratch. Checked: outputs
-equal to qc_cluster's (distances, labels bit for bit, psi/V within 1e-6 and
-in fact equal) on consecutive calls that reuse the scratch, the second one
-smaller; no device memory is taken from the driver or the library's
-allocator during a call; a problem beyond the scratch is refused before any
-device work.
+device buffers from the library's fixed device scratch (as qc_cluster does
+for a problem that fits it), the handle's calls use buffers of their own.
+Checked: outputs equal to the handle's and to qc_cluster's (distances,
+labels bit for bit, psi/V within 1e-6 and in fact equal) on consecutive
+calls that reuse the scratch, the second one smaller; no device memory is
+taken from the driver or the library's allocator during a call; a problem
+beyond the scratch is refused before any device work, and qc_cluster runs
+it on buffers of its own.
 """
 import gc
 
@@ -30,13 +33,28 @@ def env():
     return torch, qc
 
 
+def handle_path(qc, n, row_ptr, col, sigmas, tie_mode, labels, psi, v, dist):
+    """Algorithm 4 through the per-step calls on a graph handle."""
+    G = qc.Graph(n, row_ptr, col)
+    G.distances(dist)
+    p_, v_ = G.potential(sigmas)
+    psi.copy_(p_)
+    v.copy_(v_)
+    for k in range(len(sigmas)):
+        labels[k].copy_(G.labels(k, tie_mode))
+    G.sync()
+    G.close()
+
+
 def run_both(torch, qc, g, sigmas, with_dist, tie=0):
-    """qc_cluster and qc_cluster_noalloc on g with preallocated outputs;
-    returns both output sets and the device memory the no-allocation call
-    took (driver free-memory drop, library allocator blocks, torch bytes)."""
+    """The handle's calls, qc_cluster and qc_cluster_noalloc on g with
+    preallocated outputs; returns the handle's outputs and, for the last
+    call, its outputs and the device memory it took (driver free-memory
+    drop, library allocator blocks, torch bytes), after checking that
+    qc_cluster's outputs equal the handle's."""
     S, n = len(sigmas), g.n
     outs = []
-    for fn in (qc.cluster, qc.cluster_noalloc):
+    for fn in (handle_path, qc.cluster, qc.cluster_noalloc):
         o = dict(labels=torch.full((S, n), -7, dtype=torch.int32, device="cuda"),
                  psi=torch.full((S, n), -1.0, dtype=torch.float32, device="cuda"),
                  v=torch.full((S, n), -1.0, dtype=torch.float32, device="cuda"),
@@ -47,12 +65,16 @@ def run_both(torch, qc, g, sigmas, with_dist, tie=0):
         blocks0 = qc.debug_alloc_fault(0)
         torch0 = torch.cuda.memory_allocated()
         print(f"[gpu] {fn.__name__} n={n} S={S} dist={with_dist} tie={tie}", flush=True)
-        fn(n, g.row_ptr, g.col, sigmas, tie_mode=tie, **o)
+        if fn is handle_path:
+            fn(qc, n, g.row_ptr, g.col, sigmas, tie, **o)
+        else:
+            fn(n, g.row_ptr, g.col, sigmas, tie_mode=tie, **o)
         torch.cuda.synchronize()
         took = (free0 - torch.cuda.mem_get_info()[0], qc.debug_alloc_fault(0) - blocks0,
                 torch.cuda.memory_allocated() - torch0)
         outs.append(({k: (t.cpu().numpy() if t is not None else None) for k, t in o.items()}, took))
-    return outs
+    check_equal(outs[0][0], outs[1][0])   # qc_cluster
+    return outs[0], outs[2]
 
 
 def check_equal(a, b):
@@ -104,3 +126,7 @@ def test_noalloc_refuses_a_problem_beyond_its_scratch(env):
     assert (labels.cpu().numpy() == -7).all()   # nothing written
     (ref, _), (got, _) = run_both(torch, qc, g, [0.5], True)
     check_equal(ref, got)
+    # qc_cluster takes the same problem on buffers of its own
+    lab = qc.cluster(g.n, g.row_ptr, g.col, [0.5])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(lab.cpu().numpy(), got["labels"])
