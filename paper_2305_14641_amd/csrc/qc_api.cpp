@@ -69,6 +69,40 @@ qc_status check_device(int *dev_out)
     return QC_OK;
 }
 
+qc_status upload_group(qc_graph g, std::vector<HostSpan> spans)
+{
+    // large arrays go straight (a staging copy would only add host work);
+    // the small ones are what costs a copy call each
+    constexpr size_t kLarge = 64 * 1024;
+    for (const HostSpan &x : spans)
+        if (x.bytes >= kLarge) QC_HIP(hipMemcpy(x.dst, x.src, x.bytes, hipMemcpyHostToDevice));
+    spans.erase(std::remove_if(spans.begin(), spans.end(),
+                               [](const HostSpan &x) { return x.bytes == 0 || x.bytes >= kLarge; }),
+                spans.end());
+    std::sort(spans.begin(), spans.end(),
+              [](const HostSpan &a, const HostSpan &b) { return (char *)a.dst < (char *)b.dst; });
+    for (size_t i = 0; i < spans.size();) {
+        char *const lo = (char *)spans[i].dst;
+        char *hi = lo + spans[i].bytes;
+        size_t j = i + 1;
+        while (g->bump_base && j < spans.size() && (char *)spans[j].dst >= hi &&
+               (char *)spans[j].dst - hi < 256) {
+            hi = (char *)spans[j].dst + spans[j].bytes;
+            ++j;
+        }
+        if (j == i + 1) {
+            QC_HIP(hipMemcpy(spans[i].dst, spans[i].src, spans[i].bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<char> stage((size_t)(hi - lo), 0);
+            for (size_t k = i; k < j; ++k)
+                memcpy(stage.data() + ((char *)spans[k].dst - lo), spans[k].src, spans[k].bytes);
+            QC_HIP(hipMemcpy(lo, stage.data(), stage.size(), hipMemcpyHostToDevice));
+        }
+        i = j;
+    }
+    return QC_OK;
+}
+
 qc_status push_desc(qc_graph g, hipStream_t st)
 {
     return from_hip(launch_set_desc(g->d_desc, g->desc(), st));
@@ -304,11 +338,8 @@ qc_status load_sigmas(qc_graph g, const double *sigmas, int32_t n_sigmas, hipStr
         // The weight tables are tiny; a synchronous upload keeps host buffers
         // safe. A repeated sigma list reuses the tables already on the device.
         QC_HIP(hipStreamSynchronize(st));
-        QC_TRY(upload(g->d_w64, w64));
-        QC_TRY(upload(g->d_u64, u64));
-        QC_TRY(upload(g->d_inv_a, inv_a));
-        QC_TRY(upload(g->d_w32c, w32c));
-        QC_TRY(upload(g->d_wbf16, wbf16));
+        QC_TRY(upload_group(g, {span_of(g->d_w64, w64), span_of(g->d_u64, u64), span_of(g->d_inv_a, inv_a),
+                                span_of(g->d_w32c, w32c), span_of(g->d_wbf16, wbf16)}));
         g->sigmas_loaded = sig;
         g->n_sigmas = n_sigmas;
         QC_TRY(push_desc(g, st));
@@ -583,13 +614,16 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
         (st_ = galloc(g, &g->d_recheck, 1)) || (st_ = galloc(g, &g->d_desc, 1)) ||
         (st_ = galloc(g, &g->d_node_jobs, njobs.size())))
         return fail(st_);
-    if ((st_ = upload(g->d_row_ptr, rp)) || (st_ = upload(g->d_col, col)) ||
-        (st_ = upload(g->d_order, order)) || (st_ = upload(g->d_src, g->src_order)) ||
-        (st_ = upload(g->d_sell_col, sell_col)) || (st_ = upload(g->d_sell_off, sell_off)) ||
-        (st_ = upload(g->d_sell_deg, sell_deg)) ||
-        (weights && ((st_ = upload(g->d_bfs_row_ptr, brp)) || (st_ = upload(g->d_bfs_col, bcol)))) ||
-        (st_ = upload(g->d_edges, edges)) || (st_ = upload(g->d_node_jobs, njobs)) ||
-        (st_ = set_plan(g, plan_bfs(n_bfs, bound))))
+    std::vector<HostSpan> spans = {span_of(g->d_row_ptr, rp),        span_of(g->d_col, col),
+                                   span_of(g->d_order, order),        span_of(g->d_src, g->src_order),
+                                   span_of(g->d_sell_col, sell_col),  span_of(g->d_sell_off, sell_off),
+                                   span_of(g->d_sell_deg, sell_deg),  span_of(g->d_edges, edges),
+                                   span_of(g->d_node_jobs, njobs)};
+    if (weights) {
+        spans.push_back(span_of(g->d_bfs_row_ptr, brp));
+        spans.push_back(span_of(g->d_bfs_col, bcol));
+    }
+    if ((st_ = upload_group(g, spans)) || (st_ = set_plan(g, plan_bfs(n_bfs, bound))))
         return fail(st_);
     if ((st_ = from_hip(launch_fill_u64(g->d_recheck, 1, st))) || (st_ = push_desc(g, st)))
         return fail(st_);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "qc.h"
@@ -201,6 +202,24 @@ qc_status upload(T *dst, const std::vector<T> &src)
     if (src.empty()) return QC_OK;
     return from_hip(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
 }
+
+// One host array bound for the device.
+struct HostSpan {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+template <class T>
+HostSpan span_of(T *dst, const std::vector<T> &src)
+{
+    return HostSpan{(void *)dst, (const void *)src.data(), src.size() * sizeof(T)};
+}
+// Upload several host arrays (set-up only). In a handle's arena region,
+// small arrays whose buffers follow one another (separated only by the
+// region's 256-byte alignment padding, which no buffer uses) go as one copy
+// from a staging buffer; large arrays, and every array outside a region,
+// are copies of their own.
+qc_status upload_group(qc_graph g, std::vector<HostSpan> spans);
 
 inline hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
