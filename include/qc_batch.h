@@ -70,9 +70,10 @@ qc_status qc_batch_node_offsets(qc_batch b, int64_t *offsets);
  * With QC_BATCH_HIPGRAPH the first run captures the launches on `stream`
  * and every later run with the same output pointers replays that graph.
  * When the searches take more than one launch (graphs of different launch
- * shapes), the distance histograms of the graphs one search launch covers
- * run on a second stream the batch owns as soon as that launch has
- * finished, beside the following searches; `stream` waits for them before
+ * shapes), the launches take turns on `stream` and a stream the batch owns,
+ * and the distance histograms of the graphs one search launch covers run on
+ * another stream the batch owns as soon as that launch has finished, beside
+ * the following searches; `stream` waits for all of them before
  * the potentials (Eq. 2 / Eq. 7) and Algorithms 2-3, so the run is ordered
  * on `stream` like any other work (and a captured graph holds both
  * branches). QC_BATCH_SERIAL keeps every launch on `stream`, in stream order

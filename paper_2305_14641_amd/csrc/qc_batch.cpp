@@ -68,6 +68,13 @@ struct qc_batch_s {
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> ev_bfs;
     hipEvent_t ev_join = nullptr;
+    // The search launches themselves go round-robin over the caller's stream
+    // and these, forked after the counters are cleared (ev_fork) and joined
+    // back after the last search (ev_search_join), so that one launch's last
+    // workgroups run beside the next launch's first.
+    std::vector<hipStream_t> search_side;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_search_join;
     int jump_variant = 0;   // pointer jumping in LDS when it fits (0) or in global memory (1)
     int bfs_policy = 0;     // the BFS planning policy the autotuner kept (0: the planner's)
 
@@ -100,6 +107,9 @@ void free_batch(qc_batch b)
     for (hipEvent_t e : b->ev_bfs) (void)hipEventDestroy(e);
     if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     if (b->side) (void)hipStreamDestroy(b->side);
+    for (hipEvent_t e : b->ev_search_join) (void)hipEventDestroy(e);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipStream_t x : b->search_side) (void)hipStreamDestroy(x);
     delete b;
 }
 
@@ -271,13 +281,23 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
 {
     QC_HIP(launch_fill_u64(b->d_recheck, 1, st));
     QC_HIP(launch_fill_u64(b->d_visits, 2, st));
+    const size_t k = b->search_side.size() + 1;   // streams the searches take turns on
+    if (k > 1) {
+        QC_HIP(hipEventRecord(b->ev_fork, st));
+        for (hipStream_t x : b->search_side) QC_HIP(hipStreamWaitEvent(x, b->ev_fork, 0));
+    }
     for (size_t i = 0; i < b->bfs.size(); ++i) {
         const BfsGroup &g = b->bfs[i];
+        hipStream_t bs = (i % k) ? b->search_side[i % k - 1] : st;
         {
-            StageTimer t(QC_STAGE_BFS, st);
-            QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, st));
+            StageTimer t(QC_STAGE_BFS, bs);
+            QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, bs));
         }
-        if (b->overlap) QC_HIP(hipEventRecord(b->ev_bfs[i], st));
+        if (b->overlap) QC_HIP(hipEventRecord(b->ev_bfs[i], bs));
+    }
+    for (size_t j = 0; j + 1 < k; ++j) {
+        QC_HIP(hipEventRecord(b->ev_search_join[j], b->search_side[j]));
+        QC_HIP(hipStreamWaitEvent(st, b->ev_search_join[j], 0));
     }
     bool forked = false;
     for (const Stages &c : b->stages) {
@@ -550,6 +570,23 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(QC_E_DEVICE);
             if (i < b->bfs.size()) b->ev_bfs.push_back(e);
             else b->ev_join = e;
+        }
+        // the searches on two streams (QC_BATCH_BFS_STREAMS=1..4, a switch
+        // for measurements and tests)
+        const char *ks = getenv("QC_BATCH_BFS_STREAMS");
+        int k = (ks && atoi(ks) >= 1 && atoi(ks) <= 4) ? atoi(ks) : 2;
+        k = std::min<int>(k, (int)b->bfs.size());
+        if (k > 1 && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
+            b->ev_fork = nullptr;
+            return fail(QC_E_DEVICE);
+        }
+        for (int j = 1; j < k; ++j) {
+            hipStream_t x = nullptr;
+            if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return fail(QC_E_DEVICE);
+            b->search_side.push_back(x);
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(QC_E_DEVICE);
+            b->ev_search_join.push_back(e);
         }
     }
     // One stage set over graphs `gis`: histogram and potential jobs grouped
