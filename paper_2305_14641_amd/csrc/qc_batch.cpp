@@ -617,9 +617,7 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
                 KGroup h;
                 h.K = K;
                 h.n_jobs = (int)hj.size();
-                // sixteen wavefronts per 32 rows where the searches run beside:
-                // their LDS keeps searches off a histogram's CU (measured faster)
-                h.variant = b->overlap ? 2 : 0;
+                h.variant = 0;
                 c.hist.push_back(h);
                 QC_TRY(upload_jobs(&c.hist.back().d_jobs, hj));
             }
