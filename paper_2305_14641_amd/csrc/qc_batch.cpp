@@ -53,8 +53,11 @@ struct qc_batch_s {
     int precision = QC_PREC_FP64ACC;
 
     GraphDev *d_descs = nullptr;
-    unsigned long long *d_recheck = nullptr;
-    unsigned long long *d_visits = nullptr;   // [2] the last run's BFS edge visits, bytes gathered
+    // [3] counters of the last run, cleared together at its start: the FP64
+    // re-decisions, then the BFS edge visits and LDS bytes gathered
+    unsigned long long *d_counters = nullptr;
+    unsigned long long *d_recheck = nullptr;  // d_counters
+    unsigned long long *d_visits = nullptr;   // d_counters + 1
     std::vector<BfsGroup> bfs;
     // Stage sets in launch order. Serial form: one over every graph, on the
     // caller's stream after the last search. Overlapped forms: one per BFS
@@ -94,8 +97,7 @@ void free_batch(qc_batch b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     dfree(b->d_descs);
-    dfree(b->d_recheck);
-    dfree(b->d_visits);
+    dfree(b->d_counters);
     for (auto &g : b->bfs) dfree(g.d_jobs);
     for (auto &c : b->stages) {
         for (auto &g : c.hist) dfree(g.d_jobs);
@@ -279,8 +281,7 @@ qc_status run_stages(qc_batch b, const Stages &c, float *psi_out, float *v_out, 
 
 qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out, hipStream_t st)
 {
-    QC_HIP(launch_fill_u64(b->d_recheck, 1, st));
-    QC_HIP(launch_fill_u64(b->d_visits, 2, st));
+    QC_HIP(launch_fill_u64(b->d_counters, 3, st));
     const size_t k = b->search_side.size() + 1;   // streams the searches take turns on
     if (k > 1) {
         QC_HIP(hipEventRecord(b->ev_fork, st));
@@ -528,9 +529,9 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     if (hipStreamSynchronize(st) != hipSuccess) return fail(QC_E_DEVICE);
 
     qc_status s;
-    if ((s = dalloc(&b->d_recheck, 1)) || (s = dalloc(&b->d_visits, 2)) ||
-        (s = dalloc(&b->d_descs, (size_t)n_graphs)))
-        return fail(s);
+    if ((s = dalloc(&b->d_counters, 3)) || (s = dalloc(&b->d_descs, (size_t)n_graphs))) return fail(s);
+    b->d_recheck = b->d_counters;
+    b->d_visits = b->d_counters + 1;
     std::vector<GraphDev> descs(n_graphs);
     for (int i = 0; i < n_graphs; ++i) {
         descs[i] = graphs[i]->desc();
