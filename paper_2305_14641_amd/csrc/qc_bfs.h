@@ -123,6 +123,25 @@ __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
     }
 }
 
+// Transpose the 8 x 8 bit matrix in each byte lane of a[0..7]: afterwards
+// bit 8j + p of a[k] is what bit 8j + k of a[p] was. Three rounds of swaps
+// between words 4, 2 and 1 apart (bit-field inserts of the shifted partner).
+__device__ __forceinline__ void transpose8x8_lanes(uint32_t (&a)[8])
+{
+    constexpr uint32_t kMask[3] = {0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int s = 4 >> r;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            if (p & s) continue;
+            const uint32_t x = a[p], y = a[p + s], m = kMask[r];
+            a[p] = (x & m) | ((y << s) & ~m);
+            a[p + s] = ((x >> s) & m) | (y & ~m);
+        }
+    }
+}
+
 // 16 bytes of the packed edge list at byte offset `off`; offsets at or past
 // the end read as zeros (the buffer's range check), i.e. no-op edges (0, 0).
 __device__ __forceinline__ u32x4 edge_quad(__amdgpu_buffer_rsrc_t rsrc, uint32_t off)
@@ -427,67 +446,78 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     typedef __attribute__((address_space(1))) int8_t gbyte;
     typedef uint32_t __attribute__((aligned(1))) u32_any;   // rows need not be 4-byte aligned
     typedef __attribute__((address_space(1))) u32_any gu32;
+    // With 4 consecutive nodes per thread and one node per word, the decode
+    // takes sources 8j + k (j = 0..3) together for each k, so their pointers
+    // sit side by side: source b at 4 (b % 8) + b / 8.
+    constexpr bool kLanes = V == 4 && W::kPer == 1;
     gbyte **const rows = (gbyte **)nxt;
-    if (tid < nb) rows[tid] = (gbyte *)G.dist + (int64_t)srcs[tid] * n;
+    if (tid < nb) rows[kLanes ? 4 * (tid & 7) + (tid >> 3) : tid] = (gbyte *)G.dist + (int64_t)srcs[tid] * n;
     __syncthreads();
     // words of the graph's own nodes (the first n)
     const int own_words = WEIGHTED ? (n + W::kPer - 1) / W::kPer : nwords;
     const int td = opaque(tid);
-    if constexpr (V == 4 && W::kPer == 1) {
-        // runs of 4 consecutive nodes v0..v0+3: for each group of 4 sources
-        // the 4 nodes' dwords (byte k = source b0 + k) are transposed in
-        // registers into one dword per source (byte i = node v0 + i) and
-        // stored with one 4-byte store each, so a wavefront's store covers
-        // 256 consecutive bytes of a row
+    if constexpr (kLanes) {
+        // runs of 4 consecutive nodes v0..v0+3 (BW = 32). Per node, word p of
+        // eight holds plane p (all ones past the planes) OR-ed with the
+        // unreached pairs, so an unreached pair reads 0xFF; transposing the
+        // bit matrix in each byte lane turns word k into the distance bytes
+        // of sources k, 8 + k, 16 + k, 24 + k. For each k the four nodes'
+        // words are then transposed as a 4 x 4 byte matrix into one dword per
+        // source (byte i = node v0 + i), stored with one 4-byte store, so a
+        // wavefront's store covers 256 consecutive bytes of a row.
 #pragma unroll
         for (int g = 0; g < NWW / 4; ++g) {
             const int v0 = (g * kT + td) * 4;
             if (v0 < own_words) {
-                T sw[4], lp[4][P];
+                uint32_t a[4][8];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    sw[i] = SREG ? seen_r[4 * g + i] : seen[v0 + i];
+                    const uint32_t u = ~(uint32_t)(SREG ? seen_r[4 * g + i] : seen[v0 + i]);
 #pragma unroll
-                    for (int p = 0; p < P; ++p) lp[i][p] = plane[4 * g + i][p];
+                    for (int p = 0; p < 8; ++p) a[i][p] = (p < P) ? ((uint32_t)plane[4 * g + i][p] | u) : u;
+                    transpose8x8_lanes(a[i]);
                 }
-#pragma unroll 1
-                for (int t = 0; t < BW / 4; ++t) {
-                    const int b0 = 4 * t;
-                    uint32_t d[4];
+                // the quad's 4 x 4 byte transposes for sources 8j + k, j = 0..3
+                auto quad = [&](int k, uint32_t (&o)[4]) {
+                    const uint32_t d[4] = {a[0][k], a[1][k], a[2][k], a[3][k]};
+                    const uint32_t t0 = __builtin_amdgcn_perm(d[1], d[0], 0x05010400u);
+                    const uint32_t t1 = __builtin_amdgcn_perm(d[1], d[0], 0x07030602u);
+                    const uint32_t t2 = __builtin_amdgcn_perm(d[3], d[2], 0x05010400u);
+                    const uint32_t t3 = __builtin_amdgcn_perm(d[3], d[2], 0x07030602u);
+                    o[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+                    o[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+                    o[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+                    o[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+                };
+                if (v0 + 3 < n && nb == BW) {
+                    // the common case, without branches: a whole quad, a full batch
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        d[i] = spread4((uint32_t)(~sw[i] >> (4 * t)) & 0xFu) * 0xFFu;
-#pragma unroll
-                        for (int p = 0; p < P; ++p)
-                            d[i] |= spread4((uint32_t)(lp[i][p] >> (4 * t)) & 0xFu) << p;
+                    for (int k = 0; k < 8; ++k) {
+                        uint32_t o[4];
+                        quad(k, o);
+                        const ulonglong2 r01 = *(const ulonglong2 *)(rows + 4 * k);
+                        const ulonglong2 r23 = *(const ulonglong2 *)(rows + 4 * k + 2);
+                        *(gu32 *)((gbyte *)r01.x + v0) = o[0];
+                        *(gu32 *)((gbyte *)r01.y + v0) = o[1];
+                        *(gu32 *)((gbyte *)r23.x + v0) = o[2];
+                        *(gu32 *)((gbyte *)r23.y + v0) = o[3];
                     }
-                    if (b0 + 4 <= nb && v0 + 3 < n) {
-                        // 4 x 4 byte transpose: pairs of nodes, then pairs of pairs
-                        const uint32_t t0 = __builtin_amdgcn_perm(d[1], d[0], 0x05010400u);
-                        const uint32_t t1 = __builtin_amdgcn_perm(d[1], d[0], 0x07030602u);
-                        const uint32_t t2 = __builtin_amdgcn_perm(d[3], d[2], 0x05010400u);
-                        const uint32_t t3 = __builtin_amdgcn_perm(d[3], d[2], 0x07030602u);
-                        const uint32_t o[4] = {__builtin_amdgcn_perm(t2, t0, 0x05040100u),
-                                               __builtin_amdgcn_perm(t2, t0, 0x07060302u),
-                                               __builtin_amdgcn_perm(t3, t1, 0x05040100u),
-                                               __builtin_amdgcn_perm(t3, t1, 0x07060302u)};
-                        const ulonglong2 r01 = *(const ulonglong2 *)(rows + b0);
-                        const ulonglong2 r23 = *(const ulonglong2 *)(rows + b0 + 2);
-                        gbyte *const r[4] = {(gbyte *)r01.x, (gbyte *)r01.y, (gbyte *)r23.x,
-                                             (gbyte *)r23.y};
+                } else {
+                    // the graph's last quad or a partial batch
+#pragma unroll 1
+                    for (int k = 0; k < 8; ++k) {
+                        uint32_t o[4];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) *(gu32 *)(r[k] + v0) = o[k];
-                    } else {
-                        const ulonglong2 r01 = *(const ulonglong2 *)(rows + b0);
-                        const ulonglong2 r23 = *(const ulonglong2 *)(rows + b0 + 2);
-                        gbyte *const r[4] = {(gbyte *)r01.x, (gbyte *)r01.y, (gbyte *)r23.x,
-                                             (gbyte *)r23.y};
+                        for (int kk = 0; kk < 8; ++kk)
+                            if (kk == k) quad(kk, o);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
+                        for (int j = 0; j < 4; ++j) {
+                            if (8 * j + k >= nb) continue;
+                            gbyte *const r = rows[4 * k + j];
 #pragma unroll
-                            for (int k = 0; k < 4; ++k)
-                                if (v0 + i < n && b0 + k < nb)
-                                    r[k][v0 + i] = (int8_t)((d[i] >> (8 * k)) & 0xFFu);
+                            for (int i = 0; i < 4; ++i)
+                                if (v0 + i < n) r[v0 + i] = (int8_t)((o[j] >> (8 * i)) & 0xFFu);
+                        }
                     }
                 }
             }
