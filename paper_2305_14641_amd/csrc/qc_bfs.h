@@ -446,17 +446,17 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     typedef __attribute__((address_space(1))) int8_t gbyte;
     typedef uint32_t __attribute__((aligned(1))) u32_any;   // rows need not be 4-byte aligned
     typedef __attribute__((address_space(1))) u32_any gu32;
-    // With 4 consecutive nodes per thread and one node per word, the decode
-    // takes sources 8j + k (j = 0..3) together for each k, so their pointers
-    // sit side by side: source b at 4 (b % 8) + b / 8.
-    constexpr bool kLanes = V == 4 && W::kPer == 1;
+    // With one node per 32-bit word (BW = 32) the decode takes sources 8j + k
+    // (j = 0..3) together for each k, so their pointers sit side by side:
+    // source b at 4 (b % 8) + b / 8.
+    constexpr bool kLanes = BW == 32;
     gbyte **const rows = (gbyte **)nxt;
     if (tid < nb) rows[kLanes ? 4 * (tid & 7) + (tid >> 3) : tid] = (gbyte *)G.dist + (int64_t)srcs[tid] * n;
     __syncthreads();
     // words of the graph's own nodes (the first n)
     const int own_words = WEIGHTED ? (n + W::kPer - 1) / W::kPer : nwords;
     const int td = opaque(tid);
-    if constexpr (kLanes) {
+    if constexpr (kLanes && V == 4) {
         // runs of 4 consecutive nodes v0..v0+3 (BW = 32). Per node, word p of
         // eight holds plane p (all ones past the planes) OR-ed with the
         // unreached pairs, so an unreached pair reads 0xFF; transposing the
@@ -518,6 +518,49 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
                             for (int i = 0; i < 4; ++i)
                                 if (v0 + i < n) r[v0 + i] = (int8_t)((o[j] >> (8 * i)) & 0xFFu);
                         }
+                    }
+                }
+            }
+        }
+    } else if constexpr (kLanes) {
+        // one node per lane (BW = 32, word j kT + tid): the same per-node
+        // transpose, then for each k the four lanes of a quad, which hold four
+        // consecutive nodes, transpose their words' bytes across the quad
+        // (swap 16-bit halves with lane ^ 2, then bytes with lane ^ 1), so
+        // lane q stores source 8q + k's bytes for the quad's four nodes with
+        // one 4-byte store. Taken when the whole quad is in the graph and the
+        // batch is full (the same for the quad's four lanes).
+        const int q = td & 3;
+        const uint32_t sel2 = (q >> 1) ? 0x03020706u : 0x05040100u;
+        const uint32_t sel1 = (q & 1) ? 0x03070105u : 0x06020400u;
+#pragma unroll
+        for (int j = 0; j < NWW; ++j) {
+            const int w = j * kT + td;
+            if (w < own_words) {
+                uint32_t a[8];
+                const uint32_t u = ~(uint32_t)(SREG ? seen_r[j] : seen[w]);
+#pragma unroll
+                for (int p = 0; p < 8; ++p) a[p] = (p < P) ? ((uint32_t)plane[j][p] | u) : u;
+                transpose8x8_lanes(a);
+                if (w - q + 3 < n && nb == BW) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const uint32_t d = a[k];
+                        const uint32_t p2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0x4E, 0xF, 0xF, false);
+                        const uint32_t h = __builtin_amdgcn_perm(p2, d, sel2);
+                        const uint32_t p1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)h, 0xB1, 0xF, 0xF, false);
+                        *(gu32 *)(rows[4 * k + q] + (w - q)) = __builtin_amdgcn_perm(p1, h, sel1);
+                    }
+                } else {
+#pragma unroll 1
+                    for (int k = 0; k < 8; ++k) {
+                        uint32_t d = 0;
+#pragma unroll
+                        for (int kk = 0; kk < 8; ++kk)
+                            if (kk == k) d = a[kk];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (8 * i + k < nb && w < n) rows[4 * k + i][w] = (int8_t)((d >> (8 * i)) & 0xFFu);
                     }
                 }
             }
