@@ -202,6 +202,10 @@ std::vector<NodeJob> xcd_pinned_node_jobs(const std::vector<qc_graph> &graphs)
 }
 
 constexpr int kTuneReps = 2;
+// Rounds over a stage's variants: each round times every variant once, in
+// turn, and a variant's time is its best round, so that a drift over the
+// tuning (clocks settling) does not favour the variants timed last.
+constexpr int kTuneRounds = 3;
 
 // BFS launch groups of the graphs' current plans: jobs grouped by launch
 // shape (batch width, words per thread, planes, shape), each group's jobs in
@@ -374,7 +378,8 @@ std::map<std::tuple<int, int, int, int>, int> g_tiles;
 // matrices, histograms and parents are the batch's own and re-running a
 // stage rewrites identical values), time whole steps with the histogram pass
 // in each of its three workgroup shapes, then with pointer jumping in LDS and
-// in global memory; keep the fastest, and remember it for the class. Whole
+// in global memory (interleaved rounds, each variant's best round); keep the
+// fastest, and remember it for the class. Whole
 // steps, because in the overlapped forms a stage's best shape is the one
 // that shares the GPU best with the searches beside it.
 qc_status autotune_stages(qc_batch b, hipStream_t st)
@@ -404,14 +409,15 @@ qc_status autotune_stages(qc_batch b, hipStream_t st)
                 return;
             }
         }
-        float best = 1e30f;
-        int chosen = 0;
-        for (int v = 0; v < n_variants && s == QC_OK; ++v) {
-            apply(v);
-            const float ms = time_launches(step, st);
-            if (ms < 0.0f) s = QC_E_DEVICE;
-            else if (ms < best) { best = ms; chosen = v; }
-        }
+        std::vector<float> best((size_t)n_variants, 1e30f);
+        for (int r = 0; r < kTuneRounds && s == QC_OK; ++r)
+            for (int v = 0; v < n_variants && s == QC_OK; ++v) {
+                apply(v);
+                const float ms = time_launches(step, st);
+                if (ms < 0.0f) s = QC_E_DEVICE;
+                else best[(size_t)v] = std::min(best[(size_t)v], ms);
+            }
+        const int chosen = (int)(std::min_element(best.begin(), best.end()) - best.begin());
         apply(chosen);
         std::lock_guard<std::mutex> lk(g_tiles_mu);
         if (s == QC_OK) g_tiles[key] = chosen;
