@@ -125,24 +125,49 @@ static int edge_banks()
     return (b == 0 || b == 16 || b == 32 || b == 64) ? b : 32;
 }
 
+// The packed edges with every row field raised by `bias` (bfs_row_bias).
+static std::vector<uint32_t> biased_edges(const std::vector<uint32_t> &e, int bias)
+{
+    std::vector<uint32_t> out(e);
+    if (bias)
+        for (uint32_t &x : out) x += (uint32_t)bias << 16;
+    return out;
+}
+
+// Upload the edges in the handle's current order with row bias `bias`; on a
+// failure the device copy is unknown (a launch then refuses it).
+static qc_status upload_edges(qc_graph g, int bias)
+{
+    const std::vector<uint32_t> &e = g->edges_bw ? g->edges_order : g->edges_host;
+    g->edges_bias = -1;
+    QC_TRY(bias ? upload(g->d_edges, biased_edges(e, bias)) : upload(g->d_edges, e));
+    g->edges_bias = bias;
+    return QC_OK;
+}
+
 // Upload the packed edges in the order that spreads the pull's gathers over
 // the LDS banks for batches of `bw` sources.
-static qc_status order_edges(qc_graph g, int bw)
+static qc_status order_edges(qc_graph g, int bw, int bias)
 {
     std::vector<uint32_t> e = g->edges_host;
     const int banks = edge_banks();
     if (banks > 0)
         spread_gather_banks(e, g->nnz_bfs, bw >= 32 ? 1 : 32 / bw, bw == 64 ? banks / 2 : banks);
-    QC_TRY(upload(g->d_edges, e));
+    g->edges_order = std::move(e);
     g->edges_bw = bw;
-    return QC_OK;
+    return upload_edges(g, bias);
 }
 
 qc_status plain_edges(qc_graph g)
 {
-    QC_TRY(upload(g->d_edges, g->edges_host));
     g->edges_bw = 0;
-    return QC_OK;
+    g->edges_order.clear();
+    return upload_edges(g, g->edges_bias < 0 ? 0 : g->edges_bias);
+}
+
+qc_status check_edges(qc_graph g)
+{
+    return g->edges_bias == bfs_row_bias(g->plan.bw, g->plan.nw, g->plan.shape) ? QC_OK : QC_E_STATE;
 }
 
 qc_status set_plan(qc_graph g, const BfsPlan &plan, bool reorder)
@@ -153,9 +178,17 @@ qc_status set_plan(qc_graph g, const BfsPlan &plan, bool reorder)
     // the bank-aware order costs host time per edge that only repeated
     // searches repay: it is chosen once the largest distance (and so the
     // final batch width) is known, and never for serving requests, which
-    // search once
-    if (reorder && g->dmax >= 0 && !g->bump_base && p.bw != g->edges_bw) QC_TRY(order_edges(g, p.bw));
+    // search once; and the rows carry the bias of the plan's launch shape.
+    // The edges go up last, once nothing else can fail (a failed upload
+    // leaves them unknown, and launches refuse them until a plan is set).
+    const int bias = bfs_row_bias(p.bw, p.nw, p.shape);
+    auto edges = [&]() -> qc_status {
+        if (reorder && g->dmax >= 0 && !g->bump_base && p.bw != g->edges_bw)
+            return order_edges(g, p.bw, bias);
+        return bias != g->edges_bias ? upload_edges(g, bias) : QC_OK;
+    };
     if (g->d_bfs_jobs && p.bw == g->plan.bw) {
+        QC_TRY(edges());
         g->plan = p;
         return QC_OK;
     }
@@ -170,7 +203,8 @@ qc_status set_plan(qc_graph g, const BfsPlan &plan, bool reorder)
     // failed allocation leaves the handle's plan and jobs as they were
     BfsJob *d_jobs = nullptr;
     QC_TRY(galloc(g, &d_jobs, jobs.size()));
-    const qc_status s = upload(d_jobs, jobs);
+    qc_status s = upload(d_jobs, jobs);
+    if (s == QC_OK) s = edges();
     if (s != QC_OK) {
         gfree(g, d_jobs);
         return s;
@@ -204,6 +238,7 @@ qc_status ensure_hist_jobs(qc_graph g)
 // BFS into g->d_dist, then histograms. The first run waits to learn dmax.
 qc_status run_distances(qc_graph g, hipStream_t st)
 {
+    QC_TRY(check_edges(g));
     QC_HIP(launch_fill_i32(g->d_status, 2, 0, st));
     QC_TRY(push_desc(g, st));
     {
@@ -614,16 +649,21 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
         (st_ = galloc(g, &g->d_recheck, 1)) || (st_ = galloc(g, &g->d_desc, 1)) ||
         (st_ = galloc(g, &g->d_node_jobs, njobs.size())))
         return fail(st_);
+    // the edges go up with the row bias of the first plan's launch shape
+    const BfsPlan plan0 = plan_bfs(n_bfs, bound);
+    const int bias0 = plan0.bw > 0 ? bfs_row_bias(plan0.bw, plan0.nw, plan0.shape) : 0;
+    const std::vector<uint32_t> edges0 = bias0 ? biased_edges(edges, bias0) : std::vector<uint32_t>();
+    g->edges_bias = bias0;
     std::vector<HostSpan> spans = {span_of(g->d_row_ptr, rp),        span_of(g->d_col, col),
                                    span_of(g->d_order, order),        span_of(g->d_src, g->src_order),
                                    span_of(g->d_sell_col, sell_col),  span_of(g->d_sell_off, sell_off),
-                                   span_of(g->d_sell_deg, sell_deg),  span_of(g->d_edges, edges),
+                                   span_of(g->d_sell_deg, sell_deg),  span_of(g->d_edges, bias0 ? edges0 : edges),
                                    span_of(g->d_node_jobs, njobs)};
     if (weights) {
         spans.push_back(span_of(g->d_bfs_row_ptr, brp));
         spans.push_back(span_of(g->d_bfs_col, bcol));
     }
-    if ((st_ = upload_group(g, spans)) || (st_ = set_plan(g, plan_bfs(n_bfs, bound))))
+    if ((st_ = upload_group(g, spans)) || (st_ = set_plan(g, plan0)))
         return fail(st_);
     if ((st_ = from_hip(launch_fill_u64(g->d_recheck, 1, st))) || (st_ = push_desc(g, st)))
         return fail(st_);

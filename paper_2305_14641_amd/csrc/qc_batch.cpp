@@ -215,6 +215,7 @@ qc_status build_bfs_groups(const std::vector<qc_graph> &graphs, std::vector<BfsG
 {
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by_class;
     for (size_t i = 0; i < graphs.size(); ++i) {
+        QC_TRY(check_edges(graphs[i]));
         const BfsPlan &p = graphs[i]->plan;
         by_class[std::make_tuple(p.bw, p.nw, p.planes,
                                  p.shape | (graphs[i]->weighted ? kBfsWeighted : 0))]

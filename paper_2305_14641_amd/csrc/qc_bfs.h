@@ -96,11 +96,12 @@ __device__ __forceinline__ typename BfsWord<BW>::T field_of(const typename BfsWo
 // a run with something to deliver issues a no-return LDS atomic into nxt[r].
 // Bits r has already seen are harmless: the word's owner masks with seen.
 // brk[k] (edge k ends a run) serves both as "edge k is a run's last" and as
-// "edge k + 1 starts a new run".
+// "edge k + 1 starts a new run". `dst` is nxt, or the start of the fields when
+// the rows are packed with the bias that reaches nxt from there.
 template <int BW>
 __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
                                          const typename BfsWord<BW>::T *src,
-                                         typename BfsWord<BW>::T *nxt)
+                                         typename BfsWord<BW>::T *dst)
 {
     using W = BfsWord<BW>;
     using T = typename W::T;
@@ -118,7 +119,7 @@ __device__ __forceinline__ void pull_oct(const u32x4 &a, const u32x4 &b,
         const uint32_t r = e[k] >> 16;
         if (k > 0) acc = brk[k - 1] ? x[k] : (acc | x[k]);
         if (brk[k] && acc)
-            __hip_atomic_fetch_or(&nxt[r / W::kPer], (T)(acc << ((r % W::kPer) * BW)),
+            __hip_atomic_fetch_or(&dst[r / W::kPer], (T)(acc << ((r % W::kPer) * BW)),
                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
@@ -240,6 +241,11 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     T *const front = fields;
     T *const nxt = fields + kLdsWords;
     T *const seen = WIDE ? fields : fields + 2 * kLdsWords;   // (not with SREG)
+    // where the pull's row field points: with a row bias, rows count from the
+    // start of the fields (nxt = fields + kLdsWords)
+    constexpr int kRowBias = bfs_row_bias(BW, NW, SHAPE);
+    static_assert(kRowBias == 0 || kRowBias == kLdsWords * W::kPer, "row bias reaches nxt");
+    T *const pull_dst = kRowBias ? fields : nxt;
     T seen_r[SREG ? NWW : 1];             // SREG: seen of the owned words
 
     const BfsJob job = jobs[blockIdx.x];
@@ -339,19 +345,19 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
                 while (off < quad_bytes) {
                     const u32x4 a1 = edge_quad(edges, off + kStep);
                     const u32x4 b1 = edge_quad(edges, off + kStep + 16u);
-                    pull_oct<BW>(a0, b0, front, nxt);
+                    pull_oct<BW>(a0, b0, front, pull_dst);
                     off += kStep;
                     if (off >= quad_bytes) break;
                     a0 = edge_quad(edges, off + kStep);
                     b0 = edge_quad(edges, off + kStep + 16u);
-                    pull_oct<BW>(a1, b1, front, nxt);
+                    pull_oct<BW>(a1, b1, front, pull_dst);
                     off += kStep;
                 }
             } else {
                 for (; off < quad_bytes; off += kStep) {
                     const u32x4 a1 = edge_quad(edges, off + kStep);
                     const u32x4 b1 = edge_quad(edges, off + kStep + 16u);
-                    pull_oct<BW>(a0, b0, front, nxt);
+                    pull_oct<BW>(a0, b0, front, pull_dst);
                     a0 = a1;
                     b0 = b1;
                 }

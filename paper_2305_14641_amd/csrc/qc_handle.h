@@ -45,6 +45,8 @@ struct qc_graph_s {
     uint32_t *d_edges = nullptr;
     std::vector<uint32_t> edges_host; // packed edges, rows ascending (host copy)
     int edges_bw = 0;                 // batch width d_edges' order was chosen for (0: rows ascending)
+    std::vector<uint32_t> edges_order; // that order (edges_bw > 0), rows as in edges_host
+    int edges_bias = 0;               // row bias of d_edges (bfs_row_bias of the plan; -1: unknown)
 
     // distances and histograms
     int8_t *d_dist_owned = nullptr;   // library-owned matrix (n*n, 16-byte padded)
@@ -231,6 +233,8 @@ qc_status ensure_hist_jobs(qc_graph g);
 qc_status set_plan(qc_graph g, const BfsPlan &p, bool reorder = true);
 // Put the graph's edges back into rows-ascending order.
 qc_status plain_edges(qc_graph g);
+// QC_OK when the device edges carry the row bias of the handle's plan.
+qc_status check_edges(qc_graph g);
 // Reachable (source, node) pairs of the batch of sources at positions
 // s0..s0+bw-1 of the source order.
 uint32_t batch_target(qc_graph g, int s0, int bw);

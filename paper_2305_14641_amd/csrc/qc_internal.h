@@ -30,6 +30,24 @@ enum { kBfsNarrow = 0, kBfsWide = 1, kBfsWide1024 = 2, kBfsFront = 3 };
 constexpr int kBfsFullWidth = 32;
 // Added to a shape at launch: the graph carries integer edge weights.
 constexpr int kBfsWeighted = 16;
+// Row bias of the packed edge list for a BFS launch shape. The pull's atomic
+// goes to nxt[row], and nxt starts one field (F words) after the field the
+// pull gathers from; when that offset in bytes exceeds the 16-bit offset of
+// an LDS instruction, every address would need an add. The host then packs
+// each edge's row as row + F * (nodes per word), so that the row field alone
+// addresses nxt from the start of the fields. Zero (rows as they are) when
+// the offset fits, or when the biased rows would not fit 16 bits.
+constexpr int bfs_row_bias(int bw, int nw, int shape)
+{
+    const int threads = ((shape & ~kBfsWeighted) == kBfsWide) ? kBfsThreadsWide : kBfsThreads;
+    const int words = (bw == 64 ? nw / 2 : nw) * threads;   // one field
+    const int word_bytes = bw == 64 ? 8 : 4;
+    const int per = bw >= 32 ? 1 : 32 / bw;                 // nodes per word
+    if ((long long)words * word_bytes <= 65535) return 0;
+    if (2LL * words * per > 65536) return 0;
+    return words * per;
+}
+
 // 32-bit words of each LDS bit field one BFS thread owns at most (the three
 // fields of 13 x 1024 words fill 156 KB of the 160 KB LDS).
 constexpr int kBfsMaxWordsPerThread = 13;
