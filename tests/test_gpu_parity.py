@@ -310,6 +310,7 @@ def front_plan(n, dmax):
     (15000, 4.0, 26),   # 32 sources, 15 of 16 words per thread
     (9000, 4.0, 22),    # 64 sources would need 18 words: 32 sources
     (6000, 5.0, 21),    # 64 sources (64-bit fields)
+    (7500, 4.0, 36),    # 64 sources, 16 words: 64 KB fields, edge rows packed with a bias
     (16500, 4.0, 27),   # beyond 16 words at 32 sources: 16 sources
     (13500, 2.5, 33),   # largest distance above 15: 5 planes, 14 words
 ])
