@@ -235,6 +235,55 @@ qc_status ensure_hist_jobs(qc_graph g)
     return QC_OK;
 }
 
+// After the first search: the sources by their exact eccentricity, the last
+// non-empty bin of their histogram row (ties keep the order of the bounds
+// the host sweeps gave). A batch searches until its farthest source is
+// done, so batches of sources with equal eccentricity pull the fewest
+// levels; every later search of the handle (a batch, a sigma sweep, a
+// second qc_distances) takes this order, and its batches' targets with it.
+static qc_status exact_source_order(qc_graph g, hipStream_t st)
+{
+    std::vector<int32_t> h((size_t)g->n * g->K);
+    QC_HIP(hipMemcpyAsync(h.data(), g->d_hist, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    QC_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> ecc(g->n, 0);
+    for (int32_t i = 0; i < g->n; ++i)
+        for (int k = g->K - 1; k > 0; --k)
+            if (h[(size_t)i * g->K + k]) {
+                ecc[i] = k;
+                break;
+            }
+    std::vector<int32_t> order = g->src_order;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ecc[a] < ecc[b]; });
+    const BfsPlan &p = g->plan;
+    std::vector<BfsJob> jobs(p.n_batches);
+    // the new tables replace the old ones only once both are in place
+    int32_t *d_src = nullptr;
+    BfsJob *d_jobs = nullptr;
+    qc_status s = galloc(g, &d_src, order.size());
+    if (s == QC_OK) s = galloc(g, &d_jobs, jobs.size());
+    if (s == QC_OK) s = upload(d_src, order);
+    if (s == QC_OK) {
+        std::swap(g->src_order, order);
+        for (int b = 0; b < p.n_batches; ++b) {
+            const int s0 = (p.n_batches - 1 - b) * p.bw;   // last batch first, as in set_plan
+            jobs[b] = BfsJob{0, s0, batch_target(g, s0, p.bw), 0u};
+        }
+        s = upload(d_jobs, jobs);
+        if (s != QC_OK) std::swap(g->src_order, order);
+    }
+    if (s != QC_OK) {
+        if (d_src) gfree(g, d_src);
+        if (d_jobs) gfree(g, d_jobs);
+        return s;
+    }
+    gfree(g, g->d_src);
+    gfree(g, g->d_bfs_jobs);
+    g->d_src = d_src;
+    g->d_bfs_jobs = d_jobs;
+    return push_desc(g, st);
+}
+
 // BFS into g->d_dist, then histograms. The first run waits to learn dmax.
 qc_status run_distances(qc_graph g, hipStream_t st)
 {
@@ -284,6 +333,7 @@ qc_status run_distances(qc_graph g, hipStream_t st)
         StageTimer t(QC_STAGE_HIST, st);
         QC_HIP(launch_hist(g->K, g->d_desc, g->d_hist_jobs, g->n_hist_jobs, st));
     }
+    if (first && g->ecc_order) QC_TRY(exact_source_order(g, st));
     if (first && g->weighted) {
         // the graph's own largest finite distance: the last non-empty bin
         std::vector<int32_t> h((size_t)g->n * g->K);
@@ -619,6 +669,7 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     if (!directed && !region && !(so && strcmp(so, "identity") == 0)) {
         g->src_order = weights ? source_order(n_bfs, brp, bcol, n, kSourceSweeps, &bound)
                                : source_order(n, rp, col, n, kSourceSweeps, &bound);
+        g->ecc_order = !weights;
     } else {
         g->src_order.resize(n);
         std::iota(g->src_order.begin(), g->src_order.end(), 0);

@@ -36,6 +36,7 @@ struct qc_graph_s {
     int32_t *d_sell_off = nullptr;
     int32_t *d_sell_deg = nullptr;
     std::vector<int32_t> src_order;   // BFS sources in batch order (host copy)
+    bool ecc_order = false;           // sources ordered by eccentricity (bounds, then exact)
     int32_t *d_src = nullptr;         // and on the device
     int32_t n_bfs = 0;                // nodes of the graph the BFS walks
     int64_t nnz_bfs = 0;              // and its edges
