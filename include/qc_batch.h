@@ -71,13 +71,16 @@ qc_status qc_batch_node_offsets(qc_batch b, int64_t *offsets);
  * and every later run with the same output pointers replays that graph.
  * When the searches take more than one launch (graphs of different launch
  * shapes), the launches take turns on `stream` and a stream the batch owns,
- * and the distance histograms of the graphs one search launch covers run on
- * another stream the batch owns as soon as that launch has finished, beside
- * the following searches; `stream` waits for all of them before
- * the potentials (Eq. 2 / Eq. 7) and Algorithms 2-3, so the run is ordered
- * on `stream` like any other work (and a captured graph holds both
- * branches). QC_BATCH_SERIAL keeps every launch on `stream`, in stream order
- * (timing one stage at a time). The outputs are the same either way.
+ * largest first. The distance histograms of the graphs one search launch
+ * covers run on another stream the batch owns as soon as that launch has
+ * finished, beside the following searches, and the potentials (Eq. 2 /
+ * Eq. 7) and Algorithms 2-3 of the graphs of all but the last few launches
+ * follow them there, beside those last launches; the last launches' graphs
+ * take their histograms and later stages on `stream` once every search is
+ * done. `stream` waits for the other streams before the run ends, so the run
+ * is ordered on `stream` like any other work (and a captured graph holds
+ * every branch). QC_BATCH_SERIAL keeps every launch on `stream`, in stream
+ * order (timing one stage at a time). The outputs are the same either way.
  */
 qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
                        void *stream);
@@ -111,10 +114,12 @@ qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *st
  *                    graph of that row length); each workgroup counts 32 rows
  *   jump_global_out  host or NULL: 1 when the pointer jumping runs in global
  *                    memory, 0 when it runs in LDS
- *   overlap_out      host or NULL: 1 when the histograms run beside the
+ *   overlap_out      host or NULL: 3 when the histograms and the later
+ *                    stages of the first launches' graphs run beside the
  *                    searches (see qc_batch_run), 0 when every stage runs in
- *                    stream order (2: every stage after the search beside the
- *                    searches, a measurement switch)
+ *                    stream order (1: the histograms only, 2: every stage
+ *                    after the search beside the searches, measurement
+ *                    switches)
  * The autotuner times the whole BFS stage of the batch under each planning
  * policy (widest batch 32, 64 or 16 with the seen-in-registers shape first,
  * and 32 without it) and keeps the fastest; then, after one run of the whole

@@ -34,7 +34,8 @@ struct KGroup {
 // The stages after the search for a set of the batch's graphs: histograms,
 // then (unless `rest` is false) potentials, descent and pointer jumping.
 struct Stages {
-    int bfs_group = -1;        // the BFS launch whose matrices it reads (-1: all of them)
+    int bfs_group = -1;        // the BFS launch whose matrices it reads (-1: all of them;
+                               // -2: the last launch's, on the caller's stream, beside the side stream)
     bool rest = true;
     std::vector<KGroup> hist, pot;
     NodeJob *d_ggd_jobs = nullptr;
@@ -307,7 +308,10 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
     }
     bool forked = false;
     for (const Stages &c : b->stages) {
-        if (c.bfs_group < 0) {
+        if (c.bfs_group == -2) {
+            // the last launch's graphs: on the caller's stream, beside the side stream
+            QC_TRY(run_stages(b, c, psi_out, v_out, labels_out, st));
+        } else if (c.bfs_group < 0) {
             // after every search: on the caller's stream, joined with the side stream first
             if (forked) {
                 QC_HIP(hipEventRecord(b->ev_join, b->side));
@@ -552,15 +556,20 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     if ((flags & QC_BATCH_AUTOTUNE) && (s = autotune_bfs_batch(b, st, &b->bfs_policy)))
         return fail(s);
     if ((s = build_bfs_groups(b->graphs, b->bfs))) return fail(s);
-    // The histograms overlap the searches when the searches take more than
-    // one launch (QC_BATCH_OVERLAP=2: every stage after the search, per
-    // search launch; 0: none; switches for measurements and tests). Every
-    // stage overlapped measured slower: the descent and jumping of one
-    // launch's few graphs are latency-bound chains that, queued behind one
-    // another on the side stream, outlast the searches.
+    // When the searches take more than one launch, the histograms of each
+    // launch's graphs run beside the later searches, and the potentials,
+    // descent and jumping of the graphs of all but the last k launches run
+    // beside those k launches (the tail, mode 3); the last launches' graphs
+    // take theirs on the caller's stream once the searches are done.
+    // QC_BATCH_OVERLAP=1 keeps every stage after the histograms for the end,
+    // 2 runs every stage after the search per search launch, 0 none
+    // (switches for measurements and tests). Every stage per launch
+    // measured slower: the descent and jumping of one launch's few graphs
+    // are latency-bound chains that, queued behind one another on the side
+    // stream, outlast the searches.
     {
         const char *ov = getenv("QC_BATCH_OVERLAP");
-        const int want = (ov && atoi(ov) >= 0 && atoi(ov) <= 2) ? atoi(ov) : 1;
+        const int want = (ov && atoi(ov) >= 0 && atoi(ov) <= 3) ? atoi(ov) : 3;
         b->overlap = (b->bfs.size() > 1 && !(flags & QC_BATCH_SERIAL)) ? want : 0;
     }
     if (b->overlap) {
@@ -569,6 +578,7 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         std::stable_sort(b->bfs.begin(), b->bfs.end(), [](const BfsGroup &x, const BfsGroup &y) {
             return x.rows_bytes > y.rows_bytes;
         });
+
         if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) {
             b->side = nullptr;
             return fail(QC_E_DEVICE);
@@ -673,9 +683,33 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
     if (b->overlap == 0) {
         if ((s = add_stages(all, -1, true, true))) return fail(s);
     } else {
-        for (size_t i = 0; i < b->bfs.size(); ++i)
-            if ((s = add_stages(b->bfs[i].graphs, (int)i, true, b->overlap == 2))) return fail(s);
+        const int G = (int)b->bfs.size();
+        // mode 3: the later stages of the graphs of the first G - k launches
+        // run beside the last k launches, the fewest that hold a tenth of
+        // the batch's matrix bytes (the launches go largest first), so that
+        // their searches last about as long as those stages
+        // (QC_BATCH_TAIL_LAUNCHES=k sets k, a switch for measurements and tests)
+        int k = 1;
+        {
+            double all_bytes = 0.0, last_bytes = 0.0;
+            for (const BfsGroup &g : b->bfs) all_bytes += g.rows_bytes;
+            while (k < G - 1 && (last_bytes += b->bfs[G - k].rows_bytes) < 0.1 * all_bytes) ++k;
+        }
+        if (const char *tl = getenv("QC_BATCH_TAIL_LAUNCHES")) k = atoi(tl);
+        k = std::max(1, std::min(k, G - 1));
+        for (int i = 0; i < G; ++i)
+            if (b->overlap != 3 || i < G - k)
+                if ((s = add_stages(b->bfs[i].graphs, i, true, b->overlap == 2))) return fail(s);
         if (b->overlap == 1 && (s = add_stages(all, -1, false, true))) return fail(s);
+        if (b->overlap == 3) {
+            std::vector<int> early, late;
+            for (int i = 0; i < G; ++i) {
+                std::vector<int> &to = (i < G - k) ? early : late;
+                to.insert(to.end(), b->bfs[i].graphs.begin(), b->bfs[i].graphs.end());
+            }
+            if ((s = add_stages(early, G - k - 1, false, true))) return fail(s);
+            if ((s = add_stages(late, -2, true, true))) return fail(s);
+        }
     }
     // Each graph's own descriptor now reflects the batch's sigma list.
     for (int i = 0; i < n_graphs; ++i)

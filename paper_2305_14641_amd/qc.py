@@ -407,14 +407,17 @@ class Batch:
         """Launch shapes of the stages: the BFS planning policy (widest batch,
         seen-in-registers shape first), the histogram pass (wavefronts per
         workgroup by row length), the pointer jumping (LDS or global) and
-        which stages run beside the searches ("all", "histograms", "none")."""
+        which stages run beside the searches ("all", "histograms",
+        "histograms and the tail": the other graphs' later stages beside the
+        last search, or "none")."""
         bw, ff, j, ov = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         w = (ctypes.c_int32 * 3)()
         _check(lib().qc_batch_stage_tiles(self._h, ctypes.byref(bw), ctypes.byref(ff), w,
                                           ctypes.byref(j), ctypes.byref(ov)), "qc_batch_stage_tiles")
         return {"bfs_widest": bw.value, "bfs_front_first": bool(ff.value),
                 "hist_waves": {32: w[0], 64: w[1], 128: w[2]}, "jump": "global" if j.value else "lds",
-                "overlap": {0: "none", 1: "histograms", 2: "all"}[ov.value]}
+                "overlap": {0: "none", 1: "histograms", 2: "all",
+                            3: "histograms and the tail"}[ov.value]}
 
     def search_stats(self) -> tuple:
         """(edge visits, LDS bytes gathered) of the last run's searches."""

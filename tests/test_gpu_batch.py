@@ -175,25 +175,33 @@ def test_batch_stage_shapes_change_no_output(setup, monkeypatch, env):
     bb.close()
 
 
-@pytest.mark.parametrize("form", ["histograms", "all", "histograms-eager", "one-search-stream",
+@pytest.mark.parametrize("form", ["default", "histograms", "all", "tail-one-launch",
+                                  "tail-two-launches", "default-eager", "one-search-stream",
                                   "three-search-streams"])
 def test_batch_overlapped_stages_change_no_output(setup, monkeypatch, form):
-    """The histograms (by default) or every stage after the search on the
-    batch's second stream, beside the searches, with the search launches on
-    one, two (by default) or three streams (replayed as a HIP graph several
-    times with other work in between, or run eagerly), give the bytes of the
-    serial form, and the serial form matches the oracle."""
+    """The stages beside the searches on the batch's second stream: the
+    histograms and the later stages of the first launches' graphs beside the
+    last launches (by default; one or two last launches forced), the
+    histograms only, or every stage after the search; with the search
+    launches on one, two (by default) or three streams (replayed as a HIP
+    graph several times with other work in between, or run eagerly). Each
+    gives the bytes of the serial form, and the serial form matches the
+    oracle."""
     torch, qc, graphs, sigmas = setup
     hs = [qc.Graph.from_graph(g) for g in graphs]
     bs = qc.Batch(hs, sigmas, hipgraph=True, serial=True)
     assert bs.stage_tiles()["overlap"] == "none"
-    if form == "all":
-        monkeypatch.setenv("QC_BATCH_OVERLAP", "2")
+    overlap = {"histograms": "1", "all": "2", "tail-one-launch": "3", "tail-two-launches": "3"}
+    if form in overlap:
+        monkeypatch.setenv("QC_BATCH_OVERLAP", overlap[form])
+    if form.startswith("tail"):
+        monkeypatch.setenv("QC_BATCH_TAIL_LAUNCHES", "2" if form.endswith("launches") else "1")
     if form.endswith("search-stream") or form.endswith("search-streams"):
         monkeypatch.setenv("QC_BATCH_BFS_STREAMS", "1" if form.startswith("one") else "3")
     ho = [qc.Graph.from_graph(g) for g in graphs]
-    bo = qc.Batch(ho, sigmas, hipgraph=(form != "histograms-eager"))
-    assert bo.stage_tiles()["overlap"] == ("all" if form == "all" else "histograms")
+    bo = qc.Batch(ho, sigmas, hipgraph=(form != "default-eager"))
+    assert bo.stage_tiles()["overlap"] == {"histograms": "histograms", "all": "all"}.get(
+        form, "histograms and the tail")
     os_, oo = bs.outputs(), bo.outputs()
     bs.run(*os_)
     torch.cuda.synchronize()
