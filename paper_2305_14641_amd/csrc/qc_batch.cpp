@@ -2,6 +2,7 @@
 // sigmas, optionally captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <functional>
@@ -24,6 +25,8 @@ struct BfsGroup {
     int n_jobs = 0;
     std::vector<int> graphs;   // the batch's graphs whose searches this launch runs
     double rows_bytes = 0.0;   // their distance matrices' bytes (sum of n^2)
+    double cost = 0.0;         // their searches' estimated work (batches x levels x edges)
+    int stream = 0;            // the search stream it runs on (0: the caller's)
 };
 struct KGroup {
     int K = 0;
@@ -66,16 +69,18 @@ struct qc_batch_s {
     // runs beside the next searches (histograms only, followed by one set of
     // the remaining stages over every graph on the caller's stream; or every
     // stage); the caller's stream waits for ev_join.
-    int overlap = 0;   // 0 serial, 1 histograms overlapped, 2 every stage overlapped
+    int overlap = 0;   // 0 serial, 1 histograms overlapped, 2 every stage overlapped,
+                       // 3 histograms and the first launches' later stages overlapped
     std::vector<Stages> stages;
     std::vector<KGroup> pot_all;   // potential jobs of every graph by bin count (BF16 sweep)
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> ev_bfs;
     hipEvent_t ev_join = nullptr;
-    // The search launches themselves go round-robin over the caller's stream
-    // and these, forked after the counters are cleared (ev_fork) and joined
-    // back after the last search (ev_search_join), so that one launch's last
-    // workgroups run beside the next launch's first.
+    // The search launches themselves run on the caller's stream and these
+    // (each launch on the one with the least estimated work so far), forked
+    // after the counters are cleared (ev_fork) and joined back after the
+    // last search (ev_search_join), so that one launch's last workgroups run
+    // beside the next launch's first.
     std::vector<hipStream_t> search_side;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_search_join;
@@ -245,6 +250,7 @@ qc_status build_bfs_groups(const std::vector<qc_graph> &graphs, std::vector<BfsG
         grp.n_jobs = (int)jobs.size();
         grp.graphs = kv.second;
         for (int gi : kv.second) grp.rows_bytes += (double)graphs[gi]->n * graphs[gi]->n;
+        for (double c : cost) grp.cost += c;
         out.push_back(grp);
         QC_TRY(upload_jobs(&out.back().d_jobs, jobs));
     }
@@ -295,7 +301,7 @@ qc_status enqueue(qc_batch b, float *psi_out, float *v_out, int32_t *labels_out,
     }
     for (size_t i = 0; i < b->bfs.size(); ++i) {
         const BfsGroup &g = b->bfs[i];
-        hipStream_t bs = (i % k) ? b->search_side[i % k - 1] : st;
+        hipStream_t bs = g.stream ? b->search_side[g.stream - 1] : st;
         {
             StageTimer t(QC_STAGE_BFS, bs);
             QC_HIP(launch_bfs(g.bw, g.nw, g.planes, g.shape, b->d_descs, g.d_jobs, g.n_jobs, bs));
@@ -605,6 +611,17 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
             hipEvent_t e = nullptr;
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(QC_E_DEVICE);
             b->ev_search_join.push_back(e);
+        }
+        // each launch, in order, on the search stream with the least
+        // estimated work so far (QC_BATCH_BFS_ASSIGN=turns: in turn, a
+        // switch for measurements)
+        const char *as = getenv("QC_BATCH_BFS_ASSIGN");
+        const bool turns = as && strcmp(as, "turns") == 0;
+        std::vector<double> load((size_t)k, 0.0);
+        for (size_t i = 0; i < b->bfs.size(); ++i) {
+            BfsGroup &g = b->bfs[i];
+            g.stream = turns ? (int)(i % k) : (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[(size_t)g.stream] += g.cost;
         }
     }
     // One stage set over graphs `gis`: histogram and potential jobs grouped
