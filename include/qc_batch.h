@@ -70,8 +70,9 @@ qc_status qc_batch_node_offsets(qc_batch b, int64_t *offsets);
  * With QC_BATCH_HIPGRAPH the first run captures the launches on `stream`
  * and every later run with the same output pointers replays that graph.
  * When the searches take more than one launch (graphs of different launch
- * shapes), the launches take turns on `stream` and a stream the batch owns,
- * largest first. The distance histograms of the graphs one search launch
+ * shapes), the launches, largest first, run on `stream` and a stream the
+ * batch owns, each on the one with the least estimated search work so far.
+ * The distance histograms of the graphs one search launch
  * covers run on another stream the batch owns as soon as that launch has
  * finished, beside the following searches, and the potentials (Eq. 2 /
  * Eq. 7) and Algorithms 2-3 of the graphs of all but the last few launches
