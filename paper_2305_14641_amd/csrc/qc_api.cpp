@@ -460,7 +460,7 @@ int64_t handle_footprint(int32_t n, int64_t nnz, int32_t n_sigmas, bool with_dis
     add(16 * ((N + kNodesPerJob - 1) / kNodesPerJob));  // node jobs
     add(8 * N);                       // BFS jobs (first plan, <= one job per node)
     add(8 * N);                       // BFS jobs (plan after dmax is known)
-    if (with_dist) add(N * N + 16);   // distance matrix
+    if (with_dist) add(N * owned_ld(n) + 16);   // distance matrix (rows on 128-byte lines)
     add(4 * N * K);                   // histograms
     add(16 * N);                      // histogram jobs
     add(4 * N * S);                   // psi
@@ -761,9 +761,11 @@ qc_status qc_distances(qc_graph g, int8_t *dist_out, int32_t *dmax_out, void *st
     if (dist_out) {
         if (((uintptr_t)dist_out) % 16) return QC_E_INVAL;  // rows are read in 16-byte chunks
         g->d_dist = dist_out;
+        g->d_ld = g->n;
     } else {
-        if (!g->d_dist_owned) QC_TRY(galloc(g, &g->d_dist_owned, (size_t)g->n * g->n + 16));
+        if (!g->d_dist_owned) QC_TRY(galloc(g, &g->d_dist_owned, (size_t)(g->n * owned_ld(g->n) + 16)));
         g->d_dist = g->d_dist_owned;
+        g->d_ld = owned_ld(g->n);
     }
     QC_TRY(run_distances(g, st));
     if (dmax_out) *dmax_out = g->dmax;

@@ -528,10 +528,11 @@ qc_status qc_batch_create(const qc_graph *graphs, int32_t n_graphs, const double
         // the batch writes distances only into a matrix the handle owns,
         // never into a caller's buffer an earlier qc_distances was given
         if (!g->d_dist_owned) {
-            qc_status s = galloc(g, &g->d_dist_owned, (size_t)g->n * g->n + 16);
+            qc_status s = galloc(g, &g->d_dist_owned, (size_t)(g->n * owned_ld(g->n) + 16));
             if (s) return fail(s);
         }
         g->d_dist = g->d_dist_owned;
+        g->d_ld = owned_ld(g->n);
         if (g->dmax < 0) {
             qc_status s = run_distances(g, st);
             if (s) return fail(s);

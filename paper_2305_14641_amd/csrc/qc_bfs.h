@@ -457,7 +457,7 @@ __global__ __launch_bounds__(BfsShape<SHAPE>::kThreads) void k_bfs(const GraphDe
     // source b at 4 (b % 8) + b / 8.
     constexpr bool kLanes = BW == 32;
     gbyte **const rows = (gbyte **)nxt;
-    if (tid < nb) rows[kLanes ? 4 * (tid & 7) + (tid >> 3) : tid] = (gbyte *)G.dist + (int64_t)srcs[tid] * n;
+    if (tid < nb) rows[kLanes ? 4 * (tid & 7) + (tid >> 3) : tid] = (gbyte *)G.dist + (int64_t)srcs[tid] * G.ld;
     __syncthreads();
     // words of the graph's own nodes (the first n)
     const int own_words = WEIGHTED ? (n + W::kPer - 1) / W::kPer : nwords;

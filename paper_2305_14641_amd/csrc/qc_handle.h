@@ -50,8 +50,9 @@ struct qc_graph_s {
     int edges_bias = 0;               // row bias of d_edges (bfs_row_bias of the plan; -1: unknown)
 
     // distances and histograms
-    int8_t *d_dist_owned = nullptr;   // library-owned matrix (n*n, 16-byte padded)
+    int8_t *d_dist_owned = nullptr;   // library-owned matrix (n rows of owned_ld(n), 16-byte padded)
     int8_t *d_dist = nullptr;         // current resident matrix (owned or caller's)
+    int64_t d_ld = 0;                 // its row stride
     int32_t *d_hist = nullptr;
     int K = 0;
     int32_t dmax = -1;
@@ -105,6 +106,7 @@ struct qc_graph_s {
         d.bfs_col = d_bfs_row_ptr ? d_bfs_col : d_col;
         d.edges = d_edges;
         d.dist = d_dist;
+        d.ld = d_ld;
         d.hist = d_hist;
         d.psi = d_psi;
         d.v = d_v;

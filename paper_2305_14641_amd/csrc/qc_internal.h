@@ -48,6 +48,10 @@ constexpr int bfs_row_bias(int bw, int nw, int shape)
     return words * per;
 }
 
+// Row stride of a distance matrix the library owns: rows start on 128-byte
+// lines, so that the search's 256-byte stores of a row cover whole lines.
+constexpr int64_t owned_ld(int32_t n) { return ((int64_t)n + 127) & ~(int64_t)127; }
+
 // 32-bit words of each LDS bit field one BFS thread owns at most (the three
 // fields of 13 x 1024 words fill 156 KB of the 160 KB LDS).
 constexpr int kBfsMaxWordsPerThread = 13;
@@ -89,7 +93,8 @@ struct GraphDev {
     const int32_t *sell_deg;  // [n] degree of node order[t]
     const int32_t *src;       // [n] BFS sources in batch order (a permutation of 0..n-1)
     const uint32_t *edges;    // packed in-edges (row << 16) | col of the BFS graph, rows ascending
-    int8_t *dist;             // [n*n] row-major
+    int8_t *dist;             // [n rows of ld] row-major
+    int64_t ld;               // its row stride: n for a caller's matrix, owned_ld(n) for the library's
     int32_t *hist;            // [n*K]
     float *psi;               // [n_sigmas*n] resident
     float *v;                 // resident, sigma groups of kVGroup interleaved by node (v_index)

@@ -55,7 +55,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
     const int wave = threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
     const int8_t *__restrict__ base = G.dist;
-    const int64_t total = (int64_t)n * n;
+    // bytes up to the end of the last row (rows are G.ld apart)
+    const int64_t total = (int64_t)(n - 1) * G.ld + n;
     const bool vec_ok = total >= 16;
     const int64_t last_whole = vec_ok ? ((total - 16) & ~(int64_t)15) : 0;
     constexpr int64_t kStep = 64 * 16;   // bytes one wavefront covers per chunk
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
         const int row = __builtin_amdgcn_readfirstlane(job.i0 + rr * WAVES + wave);
         const bool active = row < n;
         if (active && vec_ok) {
-            const int64_t r0 = (int64_t)row * n;
+            const int64_t r0 = (int64_t)row * G.ld;
             const int64_t r1 = r0 + n;
             const int64_t wb0 = r0 & ~(int64_t)15;   // the wavefront's first chunk
             const int64_t first = wb0 + lane * 16;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hist(const GraphDev *__restrict_
                 count((uint32_t)(uint8_t)base[f]);
         } else if (active) {
             // a matrix of fewer than 16 bytes: byte loads
-            const int64_t r0 = (int64_t)row * n;
+            const int64_t r0 = (int64_t)row * G.ld;
             for (int64_t f = r0 + lane; f < r0 + n; f += 64) count((uint32_t)(uint8_t)base[f]);
         }
         wave_sync();
