@@ -270,7 +270,7 @@ def configs_leg(args, qc, gg, torch) -> dict:
         f"{out['c1']['resident_graph_ms']['p50']:.3f} ms on a resident graph")
     for key, g, sigmas in (("c2", gg.config2(), gg.SIGMAS_C2), ("c3", gg.config3(), gg.SIGMAS_C3)):
         G = qc.Graph.from_graph(g)
-        dist = torch.empty((g.n, g.n), dtype=torch.int8, device="cuda")
+        dist = None   # the handle's own resident matrix (rows on 128-byte lines)
         for _ in range(2):
             path(G, sigmas, dist)        # the first run learns dmax and re-plans
         ts = []

@@ -155,7 +155,10 @@ qc_status qc_graph_info(qc_graph g, int32_t *n, int64_t *nnz, int32_t *dmax,
  * sums regroup into.
  *   dist_out  device, int8[n*n] row-major (dist_out[i*n + j] = d(i,j)), 16-byte
  *             aligned (else QC_E_INVAL), or
- *             NULL to keep the matrix in a library-owned device buffer.
+ *             NULL to keep the matrix in a library-owned device buffer
+ *             (its rows start on 128-byte lines, so the search writes whole
+ *             lines: the faster form when the caller does not read the
+ *             matrix itself).
  *             A non-NULL buffer is also remembered as the resident matrix
  *             and must stay alive while the handle may read it (until the
  *             next qc_distances call or qc_graph_destroy).
