@@ -24,7 +24,7 @@ namespace {
 
 constexpr uint32_t kInfBits = 0x7F800000u;   // +infinity: unreached
 // Out-edges a thread relaxes itself (more: a wavefront shares them).
-constexpr int kSsspSmallDegree = 32;
+constexpr int kSsspSmallDegree = 16;
 // Edges whose loads a lane issues together.
 constexpr int kSsspChunk = 8;
 // Entries of the per-round queue of high-degree nodes (beyond it a node's
