@@ -23,8 +23,11 @@ namespace qc {
 namespace {
 
 constexpr uint32_t kInfBits = 0x7F800000u;   // +infinity: unreached
-// Out-edges a thread relaxes itself (more: a wavefront shares them).
-constexpr int kSsspSmallDegree = 16;
+// Out-edges a thread relaxes itself (more: a group of kSsspGroup lanes
+// shares them).
+constexpr int kSsspSmallDegree = 12;
+// Lanes that share a queued node's edges (four nodes per wavefront at a time).
+constexpr int kSsspGroup = 16;
 // Edges whose loads a lane issues together.
 constexpr int kSsspChunk = 8;
 // Entries of the per-round queue of high-degree nodes (beyond it a node's
@@ -141,15 +144,18 @@ __global__ __launch_bounds__(T) void k_sssp(int n, const int32_t *__restrict__ r
             v = top;
         }
         __syncthreads();
-        // the queued high-degree nodes: one per wavefront at a time, its
-        // edges spread over the lanes
+        // the queued high-degree nodes: four per wavefront at a time, each
+        // node's edges spread over a group of 16 lanes (most queued nodes
+        // have fewer than 64 edges, which would leave a whole wavefront's
+        // lanes idle)
         const int nq = min(queued, kSsspQueue);
-        for (int j = wave; j < nq; j += kWaves) {
+        constexpr int kPerWave = 64 / kSsspGroup;
+        for (int j = wave * kPerWave + lane / kSsspGroup; j < nq; j += kWaves * kPerWave) {
             const int u = queue[j];
             const int e0 = row_ptr[u], e1 = row_ptr[u + 1];
             const float du = __uint_as_float(
                 __hip_atomic_load(&d[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-            relax_edges(du, e0 + lane, e1, 64, cw, d, nxt, &spare[tid]);
+            relax_edges(du, e0 + lane % kSsspGroup, e1, kSsspGroup, cw, d, nxt, &spare[tid]);
         }
         __syncthreads();
         int any = 0;
