@@ -29,7 +29,7 @@ constexpr int kSsspSmallDegree = 12;
 // Lanes that share a queued node's edges (four nodes per wavefront at a time).
 constexpr int kSsspGroup = 16;
 // Edges whose loads a lane issues together.
-constexpr int kSsspChunk = 8;
+constexpr int kSsspChunk = 4;
 // Entries of the per-round queue of high-degree nodes (beyond it a node's
 // thread relaxes its edges itself).
 constexpr int kSsspQueue = 1024;
