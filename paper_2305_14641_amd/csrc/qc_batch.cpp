@@ -212,6 +212,9 @@ constexpr int kTuneReps = 2;
 // turn, and a variant's time is its best round, so that a drift over the
 // tuning (clocks settling) does not favour the variants timed last.
 constexpr int kTuneRounds = 3;
+// How much faster than the default an alternative must be to replace it
+// (half of it for the stage variants, which take their best of the rounds).
+constexpr float kTuneMargin = 0.02f;
 
 // BFS launch groups of the graphs' current plans: jobs grouped by launch
 // shape (batch width, words per thread, planes, shape), each group's jobs in
@@ -428,7 +431,9 @@ qc_status autotune_stages(qc_batch b, hipStream_t st)
                 if (ms < 0.0f) s = QC_E_DEVICE;
                 else best[(size_t)v] = std::min(best[(size_t)v], ms);
             }
-        const int chosen = (int)(std::min_element(best.begin(), best.end()) - best.begin());
+        // the default (variant 0) stays unless another is clearly faster
+        int chosen = (int)(std::min_element(best.begin(), best.end()) - best.begin());
+        if (chosen != 0 && best[(size_t)chosen] > best[0] * (1.0f - kTuneMargin / 2)) chosen = 0;
         apply(chosen);
         std::lock_guard<std::mutex> lk(g_tiles_mu);
         if (s == QC_OK) g_tiles[key] = chosen;
@@ -477,8 +482,14 @@ qc_status autotune_bfs_batch(qc_batch b, hipStream_t st, int *chosen)
                     return e;
                 },
                 st);
+            // the planner's policy (the first) stays unless another is
+            // clearly faster: the policies' times are close on graphs the
+            // planner was tuned on, and a close call is noise
             if (ms < 0.0f) s = QC_E_DEVICE;
-            else if (ms < best) { best = ms; *chosen = pi; }
+            else if (pi == 0 || ms < best * (pi > 0 && *chosen == 0 ? 1.0f - kTuneMargin : 1.0f)) {
+                best = ms;
+                *chosen = pi;
+            }
         }
         free_bfs_groups(groups);
         if (s != QC_OK) break;
