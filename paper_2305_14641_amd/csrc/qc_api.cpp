@@ -586,7 +586,7 @@ namespace qc {
 
 qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                        uint32_t flags, hipStream_t st, char *region, size_t region_bytes,
-                       qc_graph *out, const uint8_t *weights)
+                       qc_graph *out, const uint8_t *weights, bool hop_search)
 {
     if (!out) return QC_E_INVAL;
     if (flags & ~(uint32_t)(QC_GRAPH_CANONICALIZE | QC_GRAPH_DIRECTED)) return QC_E_INVAL;
@@ -666,14 +666,14 @@ qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
     // sweep for this bound when the 7-plane plan would narrow its batches.
     const char *so = getenv("QC_SOURCE_ORDER");
     int32_t bound = -1;
-    if (!directed && !region && !(so && strcmp(so, "identity") == 0)) {
+    if (hop_search && !directed && !region && !(so && strcmp(so, "identity") == 0)) {
         g->src_order = weights ? source_order(n_bfs, brp, bcol, n, kSourceSweeps, &bound)
                                : source_order(n, rp, col, n, kSourceSweeps, &bound);
         g->ecc_order = !weights;
     } else {
         g->src_order.resize(n);
         std::iota(g->src_order.begin(), g->src_order.end(), 0);
-        if (!directed && plan_bfs(n_bfs, -1).bw < kBfsFullWidth) {
+        if (hop_search && !directed && plan_bfs(n_bfs, -1).bw < kBfsFullWidth) {
             if (weights)
                 (void)source_order(n_bfs, brp, bcol, 0, 1, &bound);
             else

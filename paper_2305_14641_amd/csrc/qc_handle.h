@@ -270,8 +270,11 @@ qc_status cluster_scratch(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
 void destroy(qc_graph g, bool sync = true);
 // qc_graph_create with an optional arena region for every device buffer.
 // `weights` (host, one per CSR entry, or null): integer edge weights 1..126.
+// `hop_search` false: the handle's hop distances will never be searched (the
+// real-weight path uses only its descent), so the host sweeps that order
+// the search's sources are skipped.
 qc_status create_graph(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                        uint32_t flags, hipStream_t stream, char *region, size_t region_bytes,
-                       qc_graph *out, const uint8_t *weights = nullptr);
+                       qc_graph *out, const uint8_t *weights = nullptr, bool hop_search = true);
 
 }  // namespace qc

@@ -101,7 +101,7 @@ qc_status qc_cluster_real(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
     // The handle carries the descent's neighbour lists and the resident
     // potentials; its hop distances are never computed.
     qc_graph g = nullptr;
-    QC_TRY(create_graph(n, nnz, row_ptr, col_idx, flags, st, nullptr, 0, &g));
+    QC_TRY(create_graph(n, nnz, row_ptr, col_idx, flags, st, nullptr, 0, &g, nullptr, false));
     float *dist = dist_out;
     double *psi = psi_out;
     qc_status s = QC_OK;
