@@ -523,7 +523,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1"}))
         sys.exit(2)
     # the serving stream is drawn in worker processes before anything
     # touches the GPU
