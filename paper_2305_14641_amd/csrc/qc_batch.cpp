@@ -68,7 +68,10 @@ struct qc_batch_s {
     // launch on `side`, started by that launch's event ev_bfs[i] so that it
     // runs beside the next searches (histograms only, followed by one set of
     // the remaining stages over every graph on the caller's stream; or every
-    // stage); the caller's stream waits for ev_join.
+    // stage; or, by default, histograms for all but the last k launches, then
+    // one set of the remaining stages of those launches' graphs on `side`,
+    // and the last k launches' graphs on the caller's stream, bfs_group -2);
+    // the caller's stream waits for ev_join.
     int overlap = 0;   // 0 serial, 1 histograms overlapped, 2 every stage overlapped,
                        // 3 histograms and the first launches' later stages overlapped
     std::vector<Stages> stages;
