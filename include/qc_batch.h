@@ -123,12 +123,15 @@ qc_status qc_batch_sweep_bf16(qc_batch b, float *psi_out, float *v_out, void *st
  *                    switches)
  * The autotuner times the whole BFS stage of the batch under each planning
  * policy (widest batch 32, 64 or 16 with the seen-in-registers shape first,
- * and 32 without it) and keeps the fastest; then, after one run of the whole
- * path, it times the histogram pass in three shapes (the default wavefront
- * count, half and twice) and the pointer jumping in LDS and in global
- * memory, and keeps the fastest of each; a later batch of the same class
- * (row length, rows, largest graph) in the process reuses these two choices
- * without timing. The outputs do not depend on any of these choices.
+ * and 32 without it); then, after one run of the whole path, it times whole
+ * steps with the histogram pass in three shapes (the default wavefront
+ * count, half and twice) and with the pointer jumping in LDS and in global
+ * memory (in interleaved rounds, each variant's best round). Each default
+ * (the first policy, the first variant) stays unless an alternative is
+ * faster by 2 % (policies) or 1 % (variants); a later batch of the same
+ * class (row length, rows, largest graph) in the process reuses the two
+ * stage choices without timing. The outputs do not depend on any of these
+ * choices.
  */
 qc_status qc_batch_stage_tiles(qc_batch b, int32_t *bfs_widest_out, int32_t *bfs_front_first_out,
                                int32_t *hist_waves_out, int32_t *jump_global_out, int32_t *overlap_out);
