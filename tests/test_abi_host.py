@@ -108,8 +108,13 @@ def test_null_pointers_rejected():
 def test_request_footprint_host_only():
     n, nnz, S = 19717, 88726, 2
     fp = qc.request_footprint(n, nnz, S)
-    assert fp >= n * n + 4 * (n + 1) + 4 * nnz + 24 * n * S
+    # the request's own distance matrix has its rows on 128-byte lines
+    ld = -(-n // 128) * 128
+    assert fp >= n * ld + 4 * (n + 1) + 4 * nnz + 24 * n * S
     assert fp < n * n * 1.2
+    # one node more than a multiple of 128 pads every row by 127 bytes
+    m = 1025
+    assert qc.request_footprint(m, 4 * m, 1) >= m * 1152
     assert qc.request_footprint(n, nnz, 3) > fp
     assert qc.request_footprint(0, 1, 1) == -1
     assert qc.request_footprint(10, 4, 0) == -1
