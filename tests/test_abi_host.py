@@ -112,9 +112,11 @@ def test_request_footprint_host_only():
     ld = -(-n // 128) * 128
     assert fp >= n * ld + 4 * (n + 1) + 4 * nnz + 24 * n * S
     assert fp < n * n * 1.2
-    # one node more than a multiple of 128 pads every row by 127 bytes
-    m = 1025
-    assert qc.request_footprint(m, 4 * m, 1) >= m * 1152
+    # one node past a multiple of 128 pads every row by 127 bytes: from 1,024
+    # to 1,025 nodes the matrix alone grows by 1025 * 1152 - 1024 * 1024
+    # bytes (dense rows would add 2,049, the other buffers a few KB)
+    grow = qc.request_footprint(1025, 4096, 1) - qc.request_footprint(1024, 4096, 1)
+    assert grow >= 1025 * 1152 - 1024 * 1024
     assert qc.request_footprint(n, nnz, 3) > fp
     assert qc.request_footprint(0, 1, 1) == -1
     assert qc.request_footprint(10, 4, 0) == -1
