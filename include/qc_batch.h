@@ -32,6 +32,12 @@ enum {
  *              uses their resident buffers (distance matrix, histograms,
  *              potentials, weights), so a graph must not be used elsewhere
  *              while a batch run is in flight, and must outlive the batch.
+ *              A graph may be in several batches, used one after another:
+ *              a later batch's planning can give it another BFS launch
+ *              shape, and a run (of any batch, or a plain call) that finds
+ *              the graph's packed edges in another shape's form waits for
+ *              the device to drain and uploads them again (host to device,
+ *              once per switch).
  *              A graph appears at most once. The batch computes each
  *              graph's distances into a matrix the graph's handle owns
  *              (allocated here when the handle has none), never into a

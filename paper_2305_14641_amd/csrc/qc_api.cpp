@@ -165,9 +165,19 @@ qc_status plain_edges(qc_graph g)
     return upload_edges(g, g->edges_bias < 0 ? 0 : g->edges_bias);
 }
 
+qc_status ensure_edges(qc_graph g, int bias)
+{
+    if (g->edges_bias == bias) return QC_OK;
+    // the edges carry another launch shape's bias (the graph is also in a
+    // batch that planned it otherwise, or a failed upload left them
+    // unknown): nothing still in flight may read the old rows
+    QC_HIP(hipDeviceSynchronize());
+    return upload_edges(g, bias);
+}
+
 qc_status check_edges(qc_graph g)
 {
-    return g->edges_bias == bfs_row_bias(g->plan.bw, g->plan.nw, g->plan.shape) ? QC_OK : QC_E_STATE;
+    return ensure_edges(g, bfs_row_bias(g->plan.bw, g->plan.nw, g->plan.shape));
 }
 
 qc_status set_plan(qc_graph g, const BfsPlan &plan, bool reorder)

@@ -21,6 +21,7 @@ using namespace qc;
 struct BfsGroup {
     int bw = 0, nw = 0, planes = 7;
     int shape = 0;
+    int bias = 0;              // the row bias its graphs' edges carry (bfs_row_bias)
     BfsJob *d_jobs = nullptr;
     int n_jobs = 0;
     std::vector<int> graphs;   // the batch's graphs whose searches this launch runs
@@ -253,6 +254,8 @@ qc_status build_bfs_groups(const std::vector<qc_graph> &graphs, std::vector<BfsG
         grp.nw = std::get<1>(kv.first);
         grp.planes = std::get<2>(kv.first);
         grp.shape = std::get<3>(kv.first);
+        const BfsPlan &p0 = graphs[kv.second[0]]->plan;
+        grp.bias = bfs_row_bias(p0.bw, p0.nw, p0.shape);
         grp.n_jobs = (int)jobs.size();
         grp.graphs = kv.second;
         for (int gi : kv.second) grp.rows_bytes += (double)graphs[gi]->n * graphs[gi]->n;
@@ -792,6 +795,10 @@ qc_status qc_batch_run(qc_batch b, float *psi_out, float *v_out, int32_t *labels
 {
     if (!b || !labels_out) return QC_E_INVAL;
     hipStream_t st = as_stream(stream);
+    // a graph that is also in another batch, or searched alone since, may
+    // hold its edges in the form another launch shape reads
+    for (const BfsGroup &grp : b->bfs)
+        for (int gi : grp.graphs) QC_TRY(ensure_edges(b->graphs[gi], grp.bias));
     const bool use_graph = (b->flags & QC_BATCH_HIPGRAPH) && st != nullptr;
     if (!use_graph) {
         QC_TRY(enqueue(b, psi_out, v_out, labels_out, st));

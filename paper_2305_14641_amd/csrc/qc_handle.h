@@ -236,7 +236,11 @@ qc_status ensure_hist_jobs(qc_graph g);
 qc_status set_plan(qc_graph g, const BfsPlan &p, bool reorder = true);
 // Put the graph's edges back into rows-ascending order.
 qc_status plain_edges(qc_graph g);
-// QC_OK when the device edges carry the row bias of the handle's plan.
+// Make the device edges carry row bias `bias` (bfs_row_bias of the launch
+// shape about to read them): a no-op when they do; else, after the device
+// has drained, an upload of the handle's current edge order with that bias.
+qc_status ensure_edges(qc_graph g, int bias);
+// ensure_edges for the launch shape of the handle's own plan.
 qc_status check_edges(qc_graph g);
 // Reachable (source, node) pairs of the batch of sources at positions
 // s0..s0+bw-1 of the source order.
