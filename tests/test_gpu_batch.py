@@ -73,9 +73,27 @@ def test_batch_without_hipgraph_and_fp32c(setup):
     o2 = b2.outputs()
     b2.run(*o2)
     torch.cuda.synchronize()
-    # FP32C and FP64ACC agree to the FP32 bound and give identical labels
-    np.testing.assert_allclose(o2[1].cpu().numpy(), o1[1].cpu().numpy(), rtol=2e-6)
+    # FP32C and FP64ACC give identical labels
     np.testing.assert_array_equal(o2[2].cpu().numpy(), o1[2].cpu().numpy())
+    # FP32C against the oracle's FP64 values to 1e-6 (psi and V) and its
+    # labels in both tie modes
+    b3 = qc.Batch(handles, sigmas, tie_mode=qc.TIE_MERGE, hipgraph=False, fp32c=True)
+    o3 = b3.outputs()
+    b3.run(*o3)
+    torch.cuda.synchronize()
+    psi2, v2, lab2 = (x.cpu().numpy() for x in o2)
+    lab3 = o3[2].cpu().numpy()
+    for i, g in enumerate(graphs[:5]):
+        o0, o1_ = b2.offsets[i], b2.offsets[i + 1]
+        hist, _ = oracle.hist_all(g.n, g.row_ptr, g.col, handles[i].histograms_k())
+        for s, sigma in enumerate(sigmas):
+            psi_c, v_c = oracle.potential_canonical(hist, sigma)
+            np.testing.assert_allclose(psi2[s, o0:o1_], psi_c, rtol=1e-6, atol=0)
+            np.testing.assert_allclose(v2[s, o0:o1_], v_c, rtol=1e-6, atol=0)
+            for tie, lab in ((qc.TIE_STRICT, lab2), (qc.TIE_MERGE, lab3)):
+                ref = oracle.find_centers(oracle.ggd_parent(g.n, g.row_ptr, g.col, v_c, tie))
+                np.testing.assert_array_equal(lab[s, o0:o1_], ref, err_msg=f"graph {i} sigma {sigma} tie {tie}")
+    b3.close()
 
 
 @pytest.mark.parametrize("S", [1, 5, 7])
